@@ -1,0 +1,82 @@
+"""Oracle: schedules, the Adam step on se(3) twists and the iteration loop.
+
+Test infrastructure only (see the package header).
+
+  * clamp annealing: lambda goes from 10 to 6 over the first 1000 steps
+    (Alg. 3, AnnealClamp); read as linear, lambda(s) = 10 - 4 min(s, 1000)/1000;
+  * learning rate: linear warm-up to 3e-3 over 25 steps, then cosine decay
+    over N = 2000 iterations (Sec. 4 "Implementation Details"); read as
+    lr(s) = 3e-3 (s + 1)/25 for s < 25, else
+    3e-3 (1 + cos(pi (s - 25)/(2000 - 25)))/2;
+  * optimizer: Adam with beta = (0.9, 0.999) (Sec. 4), eps = 1e-8, no weight
+    decay (the paper's decay acts on network parameters that a direct twist
+    parameterization does not have), on left twists of each pose:
+      m <- b1 m + (1 - b1) g,  v <- b2 v + (1 - b2) g^2,
+      step = -lr (m / (1 - b1^s)) / (sqrt(v / (1 - b2^s)) + eps),
+      P <- Exp(step) P;
+    poses in `fixed` skip both the moment update and the step.
+
+Pins: first Adam step equals -lr g/(|g| + eps) componentwise (closed form),
+zero gradient leaves poses unchanged.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .cost import CostParams, OracleProblem
+from .geometry import left_update
+
+
+def clamp_lambda(step: int) -> float:
+    return 10.0 - 4.0 * min(step, 1000) / 1000.0
+
+
+def learning_rate(step: int, peak: float = 3e-3, warmup: int = 25, total: int = 2000) -> float:
+    if step < warmup:
+        return peak * (step + 1) / warmup
+    return peak * 0.5 * (1.0 + math.cos(math.pi * (step - warmup) / (total - warmup)))
+
+
+def adam_se3_step(poses, m, v, g, step: int, lr, b1=0.9, b2=0.999, eps=1e-8, fixed=None,
+                  scene_of_view=None):
+    """One Adam update of every pose; `step` counts from 1.  `lr` is a scalar
+    or one value per scene (with scene_of_view)."""
+    poses = poses.copy()
+    m = m.copy()
+    v = v.copy()
+    V = poses.shape[0]
+    lr = np.asarray(lr, np.float64)
+    for k in range(V):
+        if fixed is not None and fixed[k]:
+            continue
+        m[k] = b1 * m[k] + (1.0 - b1) * g[k]
+        v[k] = b2 * v[k] + (1.0 - b2) * g[k] * g[k]
+        mhat = m[k] / (1.0 - b1 ** step)
+        vhat = v[k] / (1.0 - b2 ** step)
+        lr_k = float(lr) if lr.ndim == 0 else float(lr[scene_of_view[k]])
+        delta = -lr_k * mhat / (np.sqrt(vhat) + eps)
+        poses[k] = left_update(poses[k], delta)
+    return poses, m, v
+
+
+def run(op: OracleProblem, poses0: np.ndarray, n_iters: int, params: CostParams = CostParams(),
+        fixed=None, start_step: int = 0, record_every: int = 1):
+    """The optimisation loop: for s = start .. start + n - 1 evaluate lambda(s)
+    and lr(s), the loss and the gradient at the current poses, then step."""
+    poses = poses0.copy()
+    m = np.zeros((op.V, 6))
+    v = np.zeros((op.V, 6))
+    hist = dict(loss=[], grad_norm=[], poses=[])
+    for s in range(start_step, start_step + n_iters):
+        r = op.evaluate(poses, clamp_lambda(s), params)
+        if (s - start_step) % record_every == 0:
+            hist["loss"].append(r["loss"].copy())
+            hist["grad_norm"].append(float(np.linalg.norm(r["grad"])))
+            hist["poses"].append(poses.copy())
+        poses, m, v = adam_se3_step(poses, m, v, r["grad"], s - start_step + 1, learning_rate(s),
+                                    fixed=fixed)
+    hist["final_poses"] = poses
+    hist["m"], hist["v"] = m, v
+    return hist

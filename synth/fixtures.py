@@ -1,0 +1,66 @@
+"""Hand-built tiny inputs with known answers (inputs only, no method arithmetic).
+
+`shifted_pair` is the exact-zero configuration used as a pin: two views with
+identical intrinsics fx = fy = 128, cx = 79.5, cy = 59.5 (160 x 120) and poses
+that differ by a pure x-translation of b = 0.5.  A point of view 0 at pixel
+(u, v) with depth Z appears in view 1 at (u - fx b / Z, v) with the same depth;
+with Z in {8, 16, 32, 64} the shift fx b / Z is 8, 4, 2 or 1 pixels, an exact
+integer, so every edge pixel of either view lands exactly on an edge pixel of
+the other view.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .scenes import Scene, pack
+
+
+def problem_from_maps(widths, heights, Ks, edge_maps, depth_maps, poses, pairs, poses_gt=None,
+                      name="fixture"):
+    """Pack explicit per-view maps into a one-scene Problem."""
+    V = len(widths)
+    idx, zs = [], []
+    for v in range(V):
+        e = np.asarray(edge_maps[v]).reshape(-1)
+        lin = np.flatnonzero(e)
+        idx.append(lin.astype(np.int64))
+        zs.append(np.asarray(depth_maps[v], np.float32).reshape(-1)[lin])
+    poses = np.asarray(poses, np.float64)
+    sc = Scene(width=np.asarray(widths, np.int32), height=np.asarray(heights, np.int32),
+               K=np.asarray(Ks, np.float32), edge_idx=idx, edge_z=zs,
+               poses_gt=poses if poses_gt is None else np.asarray(poses_gt, np.float64),
+               poses_init=poses, pairs=np.asarray(pairs, np.int32).reshape(-1, 2),
+               meta=dict(config=name))
+    return pack([sc], name)
+
+
+def shifted_pair(seed: int = 0, per_depth: int = 40):
+    W, H = 160, 120
+    K = [128.0, 128.0, 79.5, 59.5]
+    b = 0.5
+    rng = np.random.default_rng(seed)
+    e0 = np.zeros((H, W), np.uint8)
+    e1 = np.zeros((H, W), np.uint8)
+    z0 = np.zeros((H, W), np.float32)
+    z1 = np.zeros((H, W), np.float32)
+    used0, used1 = set(), set()
+    for Z in (8.0, 16.0, 32.0, 64.0):
+        shift = int(128 * b / Z)
+        placed = 0
+        while placed < per_depth:
+            u = int(rng.integers(10, W - 10))
+            v = int(rng.integers(5, H - 5))
+            u1 = u - shift
+            if (v, u) in used0 or (v, u1) in used1:
+                continue
+            used0.add((v, u))
+            used1.add((v, u1))
+            e0[v, u] = 255
+            z0[v, u] = Z
+            e1[v, u1] = 255
+            z1[v, u1] = Z
+            placed += 1
+    P0 = np.concatenate([np.eye(3), np.zeros((3, 1))], axis=1)
+    P1 = np.concatenate([np.eye(3), np.array([[-b], [0.0], [0.0]])], axis=1)
+    return problem_from_maps([W, W], [H, H], [K, K], [e0, e1], [z0, z1], [P0, P1],
+                             [[0, 1], [1, 0]], name="shifted_pair")
