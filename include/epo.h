@@ -1,0 +1,306 @@
+/*
+ * epo.h -- C-ABI of libepo.so, the MI355X (gfx950) hot path of EPO's
+ * edge-based pose optimization (arXiv 2607.00579).
+ *
+ * The problem (paper Sec. 3 "Method"): a geometric estimate
+ * G = {(K_i, P_i, Z_i)} of V views (intrinsics, world->camera pose, per-pixel
+ * depth), a binary edge map E_i and its distance transform field DTF_i per
+ * view, and a list of image pairs.  Edge pixels of each source view are lifted
+ * to 3-D with their depth, moved into the target camera by the relative pose,
+ * pinhole-projected, and scored by a clamped Huber loss of the bilinearly
+ * sampled target DTF (Eqs. pi, L, L_ij, d_ij; supplementary Alg. 3).  The loss
+ * is minimised by gradient steps on the poses; the output is the refined
+ * poses.
+ *
+ * Conventions shared by every call
+ *  - Pointers are DEVICE pointers unless the argument is marked (host).
+ *  - The caller owns every buffer it passes.  The library only borrows the
+ *    pointers for the work it enqueues; a plan owns the workspace it allocates
+ *    in epo_plan_create and frees in epo_plan_destroy.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call is asynchronous on that stream unless stated otherwise.
+ *  - Pixels: u = column, v = row, integer coordinates at pixel centres.
+ *    Images are row-major uint8 / float32 / int32 of height x width, packed
+ *    back to back at per-view element offsets.
+ *  - Intrinsics K: 4 floats per view (fx, fy, cx, cy).
+ *  - Poses: float64 world->camera [R | t], 12 doubles per view, row-major
+ *    3 x 4, OpenCV axes (x right, y down, z forward).  Depth is z-depth.
+ *  - Twists: left perturbations xi = (rho, omega), P <- Exp(xi) P, translation
+ *    first; gradients are float64 dL/dxi at xi = 0, 6 doubles per view.
+ *  - Errors: every entry point returns an epo_status; no C++ exception
+ *    crosses the ABI.  epo_last_error() gives a thread-local message.
+ *    Argument and shape errors are detected on the host before any work is
+ *    enqueued; launch failures map to EPO_ERR_HIP.
+ *  - Threading: a plan must not be used by two host threads at once; distinct
+ *    plans are independent.
+ */
+#ifndef EPO_H
+#define EPO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define EPO_API __attribute__((visibility("default")))
+#else
+#define EPO_API
+#endif
+
+typedef enum epo_status {
+    EPO_OK = 0,
+    EPO_ERR_INVALID_ARG = -1,   /* null pointer, bad size, index out of range */
+    EPO_ERR_HIP = -2,           /* a HIP runtime call or kernel launch failed */
+    EPO_ERR_UNSUPPORTED = -3,   /* valid request outside what the build supports */
+    EPO_ERR_NONFINITE = -4      /* a non-finite value was detected (see device status) */
+} epo_status;
+
+/* Largest image side accepted anywhere (keeps every squared distance < 2^30). */
+#define EPO_MAX_SIDE 16384
+/* Squared distance stored for every pixel of an edge map without edge pixels. */
+#define EPO_D2_EMPTY (1 << 30)
+
+/* Cost parameters (paper Sec. 3 "Edge Reprojection Loss"; Alg. 3).
+ *   huber_delta  threshold of the Huber loss H (the paper does not state it;
+ *                default 1 px): H(d) = d^2/2 for d <= delta, else
+ *                delta (d - delta/2)
+ *   z_min        a projection is valid only if the target-camera depth
+ *                exceeds z_min (default 1e-4)
+ *   norm_mode    0: per-direction mean over valid residuals (Alg. 3,
+ *                default); 1: sum over the source edge count |E_i| (Eq. L_ij)
+ *   lambda_max   largest clamp lambda the plan will be called with (default
+ *                10, the start of the paper's annealing 10 -> 6).  Values up to
+ *                14.5 allow the compact texture (see epo_plan_options). */
+typedef struct epo_cost_params {
+    float huber_delta;
+    float z_min;
+    int32_t norm_mode;
+    float lambda_max;
+} epo_cost_params;
+
+/* Kernel schedule choices.  0 in any field = let the plan decide (the
+ * autotuner, epo_plan_autotune, may change the decision later). */
+typedef struct epo_plan_options {
+    int32_t texture_format;     /* 1 = float32 taps of sqrt(d2) (4 gathers per sample);
+                                   2 = one uint32 per pixel holding the four taps of the
+                                   bilinear cell as min(d2, 255) bytes (1 gather per
+                                   sample; exact for lambda_max <= 14.5) */
+    int32_t points_per_thread;  /* residuals per thread per tile: 1, 2, 4, 8 or 16
+                                   (a tile is 256 x this many residuals of one pair) */
+    int32_t tile_order;         /* 1 = tiles grouped by target view, consecutive groups
+                                   on one XCD; 2 = tiles in pair-list order */
+    int32_t persistent;         /* 1 = persistent work-queue launch; 2 = one workgroup
+                                   per tile */
+} epo_plan_options;
+
+typedef struct epo_plan_s* epo_plan;
+
+/* ---------------------------------------------------------------------------
+ * 1. build_distance_fields
+ * Exact squared Euclidean distance transform of binary edge maps (the DTF of
+ * Sec. 3 "Method", computed with the Felzenszwalb-Huttenlocher transform;
+ * supplementary Sec. A1.2 "Construction kernels"):
+ *   d2(x, y) = min over pixels (x', y') with edge(y', x') != 0 of
+ *              (x - x')^2 + (y - y')^2,
+ * an exact integer; EPO_D2_EMPTY for every pixel of a map with no edge pixel.
+ * The DTF itself is sqrt(d2) (rounded to float32).
+ *
+ *   edge_maps    uint8, nonzero = edge; view v occupies elements
+ *                [view_offset[v], view_offset[v] + height[v] * width[v])
+ *   view_offset  (host) int64 [n_views] element offsets (views must not overlap)
+ *   width/height (host) int32 [n_views], each in [1, EPO_MAX_SIDE]
+ *   d2_out       int32, same packing as edge_maps: exact squared distances
+ *   dtf_out      float32, same packing: sqrt(d2).  Required: it also serves as
+ *                the scratch of the column pass during the call.
+ * Errors: EPO_ERR_INVALID_ARG for null pointers, n_views < 0, sides out of
+ * range or negative offsets.  No allocation; capture-safe.
+ * ------------------------------------------------------------------------- */
+EPO_API epo_status epo_build_distance_fields(const uint8_t* edge_maps, const int64_t* view_offset,
+                                     const int32_t* width, const int32_t* height,
+                                     int32_t n_views, int32_t* d2_out, float* dtf_out,
+                                     void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Plan: the static part of a problem (one or several independent scenes).
+ * Compacts the edge pixels of every view into 8-byte records (u, v as uint16,
+ * depth Z as float32; every edge pixel is used, no sub-sampling), builds the
+ * sampling texture of every view from d2, and the tile schedule over
+ * (directed pair, record chunk).  Synchronises `stream` once (edge counts come
+ * back to the host).  The edge maps, depth maps and d2 may be freed after the
+ * call returns.
+ *
+ *   n_views         number of views V (>= 1)
+ *   width/height    (host) int32 [V], each in [2, EPO_MAX_SIDE]
+ *   K               (host) float32 [V][4] (fx, fy, cx, cy); fx, fy > 0
+ *   scene_of_view   (host) int32 [V] scene index per view, scenes numbered
+ *                   0..S-1 with every scene non-empty; NULL = one scene
+ *   view_offset     (host) int64 [V] element offsets of the packed images
+ *   edge_maps       uint8 packed edge maps (nonzero = edge)
+ *   depth           float32 packed depth maps (read at edge pixels only)
+ *   d2              int32 packed squared distances (epo_build_distance_fields)
+ *   pairs           (host) int32 [n_pairs][2] directed pairs (source, target),
+ *                   both views of a pair in the same scene; the loss of a
+ *                   scene is (2 / its number of pairs) * sum of per-pair means,
+ *                   the paper's mean over pairs of both directions when the
+ *                   list holds (i, j) and (j, i)
+ *   params          (host) cost parameters, NULL = defaults
+ *   options         (host) schedule choices, NULL = automatic
+ * Errors: EPO_ERR_INVALID_ARG (shapes, indices, scene numbering, K),
+ * EPO_ERR_UNSUPPORTED (lambda_max too large for the requested texture),
+ * EPO_ERR_HIP (allocation or launch).
+ * ------------------------------------------------------------------------- */
+EPO_API epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int32_t* width,
+                           const int32_t* height, const float* K, const int32_t* scene_of_view,
+                           const int64_t* view_offset, const uint8_t* edge_maps,
+                           const float* depth, const int32_t* d2, const int32_t* pairs,
+                           int32_t n_pairs, const epo_cost_params* params,
+                           const epo_plan_options* options, void* stream);
+
+EPO_API epo_status epo_plan_destroy(epo_plan plan);
+
+/* Sizes of a plan (host outputs, any may be NULL): number of scenes, total
+ * edge records, residuals per iteration (sum over pairs of source edge
+ * counts), number of tiles, and the schedule in use. */
+EPO_API epo_status epo_plan_info(epo_plan plan, int32_t* n_scenes, int64_t* n_records,
+                         int64_t* n_residuals, int64_t* n_tiles, epo_plan_options* options);
+
+/* Edge records of view v in plan order (u | v << 16 in the low word, float32 Z
+ * bits in the high word), copied to `records_out` (host, at least
+ * edge_count(v) entries); count returned in *count.  Synchronous.  Testing and
+ * inspection only. */
+EPO_API epo_status epo_plan_view_records(epo_plan plan, int32_t v, uint64_t* records_out,
+                                 int64_t capacity, int64_t* count);
+
+/* ---------------------------------------------------------------------------
+ * 2. edge_cost_fwd
+ * Loss of every scene at `poses`, and, when `grad` is non-NULL, its gradient
+ * from the same fused pass (the forward and the analytic adjoint run in one
+ * kernel; supplementary Sec. A1.2 "Per-iteration kernels").
+ * Per directed pair d = (i -> j): S_d = sum of H(min(D, lambda)) over valid
+ * residuals, n_d = number of valid residuals, L_d = S_d / n_d (0 if n_d = 0);
+ * loss[s] = (2 / |pairs of s|) sum_{d in s} L_d.
+ *
+ *   poses       float64 [V][3][4]
+ *   lambda      float32 [n_scenes] clamp per scene, each <= params.lambda_max
+ *   loss        float64 [n_scenes] (written)
+ *   pair_cost   float64 [n_pairs] L_d, or NULL
+ *   pair_valid  int32 [n_pairs] n_d, or NULL
+ *   pair_grad   float64 [n_pairs][6] unweighted sum over the valid residuals of
+ *               pair d of the left-twist gradient of the TARGET pose, or NULL
+ *   grad        float64 [V][6] dloss[scene(v)]/dxi_v, or NULL
+ * Residual arithmetic is float32; per-pair and per-pose sums are float64 and
+ * run in a fixed order, so results are bitwise reproducible.  No allocation,
+ * no synchronisation, capture-safe.
+ * ------------------------------------------------------------------------- */
+EPO_API epo_status epo_edge_cost_fwd(epo_plan plan, const double* poses, const float* lambda,
+                             double* loss, double* pair_cost, int32_t* pair_valid,
+                             double* pair_grad, double* grad, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * 3. edge_cost_bwd
+ * Adjoint only: recomputes the residuals and writes
+ *   grad[v] = upstream[scene(v)] * dloss[scene(v)]/dxi_v     (overwrites).
+ *   upstream  float64 [n_scenes]; NULL = all ones
+ * No allocation, no synchronisation, capture-safe.
+ * ------------------------------------------------------------------------- */
+EPO_API epo_status epo_edge_cost_bwd(epo_plan plan, const double* poses, const float* lambda,
+                             const double* upstream, double* grad, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * 4. pose_step
+ * Adam on left twists with an SE(3) update, in float64 (optimizer of Sec. 4
+ * "Implementation Details" with beta = (0.9, 0.999); the pose refiner network
+ * of the paper is replaced by one twist per pose):
+ *   s = ++(*step);  for every view v not fixed:
+ *   m_v <- b1 m_v + (1 - b1) g_v,  w_v <- b2 w_v + (1 - b2) g_v^2
+ *   xi  = -lr[scene(v)] (m_v / (1 - b1^s)) / (sqrt(w_v / (1 - b2^s)) + eps)
+ *   P_v <- Exp(xi) P_v   (Rodrigues rotation, left Jacobian for translation)
+ *
+ *   poses          float64 [V][3][4], updated in place
+ *   adam_m/adam_v  float64 [V][6] first / second moments, updated in place
+ *   grad           float64 [V][6]
+ *   scene_of_view  int32 [V] or NULL (all scene 0)
+ *   fixed_mask     uint8 [V] nonzero = pose held fixed, or NULL
+ *   lr             float64 [n_scenes] learning rate per scene
+ *   step           int32 [1] step counter, incremented on the device
+ * No allocation, capture-safe.
+ * ------------------------------------------------------------------------- */
+EPO_API epo_status epo_pose_step(double* poses, double* adam_m, double* adam_v, const double* grad,
+                         int32_t n_views, const int32_t* scene_of_view,
+                         const uint8_t* fixed_mask, const double* lr, double beta1,
+                         double beta2, double eps, int32_t* step, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Schedules of the paper, evaluated on the device from the step counter (so
+ * that a captured iteration needs no host writes between replays):
+ *   lambda(s) = lambda0 - (lambda0 - lambda1) min(s, anneal_steps)/anneal_steps
+ *     (Alg. 3 AnnealClamp: 10 -> 6 over the first 1000 steps, read as linear)
+ *   lr(s) = peak (s + 1)/warmup for s < warmup, else
+ *           peak (1 + cos(pi (s - warmup)/(total - warmup)))/2
+ *     (Sec. 4: linear warm-up to 3e-3 over 25 steps, cosine decay to N = 2000)
+ * with s = *step (the number of pose steps taken so far).  Writes n_scenes
+ * copies of each into lambda_out (float32) and lr_out (float64).
+ * ------------------------------------------------------------------------- */
+EPO_API epo_status epo_schedule(const int32_t* step, int32_t n_scenes, float lambda0, float lambda1,
+                        int32_t anneal_steps, double peak_lr, int32_t warmup, int32_t total,
+                        float* lambda_out, double* lr_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * One whole iteration captured as a HIP graph owned by the plan:
+ *   schedule -> fused cost + adjoint -> float64 reductions -> pose_step.
+ * The pointers given here are baked into the graph; replays read the current
+ * contents of every buffer.  Capturing synchronises `stream` once.
+ *   poses, adam_m, adam_v, step   as in epo_pose_step
+ *   loss                          float64 [n_scenes], written each replay
+ *   grad                          float64 [V][6] scratch/result of each replay
+ *   fixed_mask                    uint8 [V] or NULL
+ *   schedule constants            as in epo_schedule
+ * epo_iteration_launch replays it on `stream` (any stream of the device).
+ * ------------------------------------------------------------------------- */
+EPO_API epo_status epo_iteration_capture(epo_plan plan, double* poses, double* adam_m, double* adam_v,
+                                 int32_t* step, double* loss, double* grad,
+                                 const uint8_t* fixed_mask, float lambda0, float lambda1,
+                                 int32_t anneal_steps, double peak_lr, int32_t warmup,
+                                 int32_t total, double beta1, double beta2, double eps,
+                                 void* stream);
+EPO_API epo_status epo_iteration_launch(epo_plan plan, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Autotuner: times every supported schedule (texture format, points per
+ * thread, tile order, launch style) on the plan's own data at `poses` with
+ * `iters` fused cost+adjoint evaluations each, keeps the fastest, and returns
+ * it in *chosen (host, may be NULL).  Allocates and synchronises; call it
+ * before capturing an iteration.
+ * ------------------------------------------------------------------------- */
+EPO_API epo_status epo_plan_autotune(epo_plan plan, const double* poses, const float* lambda,
+                             int32_t iters, epo_plan_options* chosen, void* stream);
+
+/* Switch the plan to a given schedule (rebuilds the tile schedule; allocates;
+ * synchronises).  Invalidates a captured iteration. */
+EPO_API epo_status epo_plan_set_options(epo_plan plan, const epo_plan_options* options, void* stream);
+
+/* Device status word of the plan, OR-ed by the kernels: bit 0 = a non-finite
+ * per-pair sum was seen, bit 1 = a lambda above lambda_max was seen.  Copies
+ * to *flags (host) after synchronising `stream`, then clears the word. */
+EPO_API epo_status epo_get_device_status(epo_plan plan, int32_t* flags, void* stream);
+
+/* Duration in milliseconds of the fused cost+adjoint kernel in the most recent
+ * epo_edge_cost_fwd / epo_edge_cost_bwd / iteration replay, measured with HIP
+ * events recorded around that kernel on the stream it ran on.  Synchronises
+ * on the end event.  Requires epo_plan_enable_timing(plan, 1) beforehand. */
+EPO_API epo_status epo_plan_enable_timing(epo_plan plan, int32_t enable);
+EPO_API epo_status epo_plan_last_kernel_ms(epo_plan plan, float* ms);
+
+/* Thread-local description of the last error (empty string if none). */
+EPO_API const char* epo_last_error(void);
+
+/* Library version string. */
+EPO_API const char* epo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPO_H */

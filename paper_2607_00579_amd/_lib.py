@@ -1,0 +1,211 @@
+"""ctypes binding of libepo.so: argument marshalling only.
+
+Every function of include/epo.h is exposed under the same name without the
+`epo_` prefix.  Pointers are plain integers (device addresses from
+torch.Tensor.data_ptr(), host addresses from NumPy arrays); streams are the
+integer handle of a HIP stream.  A non-OK status raises EpoError with the
+library's message.  There is no fallback: if the library is missing the first
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libepo.so")
+
+OK, ERR_INVALID_ARG, ERR_HIP, ERR_UNSUPPORTED, ERR_NONFINITE = 0, -1, -2, -3, -4
+D2_EMPTY = 1 << 30
+MAX_SIDE = 16384
+
+
+class EpoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"epo status {status}: {msg}")
+        self.status = status
+
+
+class CostParams(C.Structure):
+    _fields_ = [("huber_delta", C.c_float), ("z_min", C.c_float), ("norm_mode", C.c_int32),
+                ("lambda_max", C.c_float)]
+
+
+class PlanOptions(C.Structure):
+    _fields_ = [("texture_format", C.c_int32), ("points_per_thread", C.c_int32),
+                ("tile_order", C.c_int32), ("persistent", C.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+P, I32, I64, F32, F64 = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_double
+
+_SIGS = {
+    "epo_build_distance_fields": [P, P, P, P, I32, P, P, P],
+    "epo_plan_create": [C.POINTER(C.c_void_p), I32, P, P, P, P, P, P, P, P, P, I32,
+                        C.POINTER(CostParams), C.POINTER(PlanOptions), P],
+    "epo_plan_destroy": [P],
+    "epo_plan_info": [P, P, P, P, P, C.POINTER(PlanOptions)],
+    "epo_plan_view_records": [P, I32, P, I64, P],
+    "epo_edge_cost_fwd": [P, P, P, P, P, P, P, P, P],
+    "epo_edge_cost_bwd": [P, P, P, P, P, P],
+    "epo_pose_step": [P, P, P, P, I32, P, P, P, F64, F64, F64, P, P],
+    "epo_schedule": [P, I32, F32, F32, I32, F64, I32, I32, P, P, P],
+    "epo_iteration_capture": [P, P, P, P, P, P, P, P, F32, F32, I32, F64, I32, I32, F64, F64,
+                              F64, P],
+    "epo_iteration_launch": [P, P],
+    "epo_plan_autotune": [P, P, P, I32, C.POINTER(PlanOptions), P],
+    "epo_plan_set_options": [P, C.POINTER(PlanOptions), P],
+    "epo_get_device_status": [P, P, P],
+    "epo_plan_enable_timing": [P, I32],
+    "epo_plan_last_kernel_ms": [P, P],
+}
+EXPORTS = sorted(list(_SIGS) + ["epo_last_error", "epo_version"])
+
+_lib = None
+
+
+def load():
+    """Load libepo.so (built in-tree by paper_2607_00579_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2607_00579_amd.build` (there is no fallback path)")
+    lib = C.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.epo_last_error.restype = C.c_char_p
+    lib.epo_last_error.argtypes = []
+    lib.epo_version.restype = C.c_char_p
+    lib.epo_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise EpoError(status, load().epo_last_error().decode())
+
+
+def _ptr(x):
+    """Address of a NumPy array, a torch tensor, an int, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        assert x.flags["C_CONTIGUOUS"], "host arrays must be C-contiguous"
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        assert x.is_contiguous(), "tensors must be contiguous"
+        return x.data_ptr()
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def version() -> str:
+    return load().epo_version().decode()
+
+
+def build_distance_fields(edge_maps, view_offset, width, height, n_views, d2_out, dtf_out, stream):
+    _check(load().epo_build_distance_fields(_ptr(edge_maps), _ptr(view_offset), _ptr(width),
+                                            _ptr(height), n_views, _ptr(d2_out), _ptr(dtf_out),
+                                            stream))
+
+
+def plan_create(n_views, width, height, K, scene_of_view, view_offset, edge_maps, depth, d2, pairs,
+                n_pairs, params: CostParams | None, options: PlanOptions | None, stream):
+    h = C.c_void_p()
+    _check(load().epo_plan_create(C.byref(h), n_views, _ptr(width), _ptr(height), _ptr(K),
+                                  _ptr(scene_of_view), _ptr(view_offset), _ptr(edge_maps),
+                                  _ptr(depth), _ptr(d2), _ptr(pairs), n_pairs,
+                                  C.byref(params) if params is not None else None,
+                                  C.byref(options) if options is not None else None, stream))
+    return h.value
+
+
+def plan_destroy(plan):
+    _check(load().epo_plan_destroy(plan))
+
+
+def plan_info(plan):
+    s, r, n, t = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()
+    o = PlanOptions()
+    _check(load().epo_plan_info(plan, C.byref(s), C.byref(r), C.byref(n), C.byref(t), C.byref(o)))
+    return dict(n_scenes=s.value, n_records=r.value, n_residuals=n.value, n_tiles=t.value,
+                options=o.as_dict())
+
+
+def plan_view_records(plan, v):
+    cnt = C.c_int64()
+    _check(load().epo_plan_view_records(plan, v, None, 0, C.byref(cnt)))
+    out = np.empty(max(cnt.value, 1), np.uint64)
+    _check(load().epo_plan_view_records(plan, v, out.ctypes.data, out.size, C.byref(cnt)))
+    return out[:cnt.value]
+
+
+def edge_cost_fwd(plan, poses, lam, loss, pair_cost, pair_valid, pair_grad, grad, stream):
+    _check(load().epo_edge_cost_fwd(plan, _ptr(poses), _ptr(lam), _ptr(loss), _ptr(pair_cost),
+                                    _ptr(pair_valid), _ptr(pair_grad), _ptr(grad), stream))
+
+
+def edge_cost_bwd(plan, poses, lam, upstream, grad, stream):
+    _check(load().epo_edge_cost_bwd(plan, _ptr(poses), _ptr(lam), _ptr(upstream), _ptr(grad),
+                                    stream))
+
+
+def pose_step(poses, m, v, grad, n_views, scene_of_view, fixed_mask, lr, beta1, beta2, eps, step,
+              stream):
+    _check(load().epo_pose_step(_ptr(poses), _ptr(m), _ptr(v), _ptr(grad), n_views,
+                                _ptr(scene_of_view), _ptr(fixed_mask), _ptr(lr), beta1, beta2,
+                                eps, _ptr(step), stream))
+
+
+def schedule(step, n_scenes, lambda0, lambda1, anneal_steps, peak_lr, warmup, total, lambda_out,
+             lr_out, stream):
+    _check(load().epo_schedule(_ptr(step), n_scenes, lambda0, lambda1, anneal_steps, peak_lr,
+                               warmup, total, _ptr(lambda_out), _ptr(lr_out), stream))
+
+
+def iteration_capture(plan, poses, m, v, step, loss, grad, fixed_mask, lambda0, lambda1,
+                      anneal_steps, peak_lr, warmup, total, beta1, beta2, eps, stream):
+    _check(load().epo_iteration_capture(plan, _ptr(poses), _ptr(m), _ptr(v), _ptr(step),
+                                        _ptr(loss), _ptr(grad), _ptr(fixed_mask), lambda0,
+                                        lambda1, anneal_steps, peak_lr, warmup, total, beta1,
+                                        beta2, eps, stream))
+
+
+def iteration_launch(plan, stream):
+    _check(load().epo_iteration_launch(plan, stream))
+
+
+def plan_autotune(plan, poses, lam, iters, stream):
+    o = PlanOptions()
+    _check(load().epo_plan_autotune(plan, _ptr(poses), _ptr(lam), iters, C.byref(o), stream))
+    return o.as_dict()
+
+
+def plan_set_options(plan, options: dict, stream):
+    o = PlanOptions(**{k: int(options.get(k, 0)) for k, _ in PlanOptions._fields_})
+    _check(load().epo_plan_set_options(plan, C.byref(o), stream))
+
+
+def get_device_status(plan, stream) -> int:
+    f = C.c_int32()
+    _check(load().epo_get_device_status(plan, C.byref(f), stream))
+    return f.value
+
+
+def plan_enable_timing(plan, enable: bool):
+    _check(load().epo_plan_enable_timing(plan, 1 if enable else 0))
+
+
+def plan_last_kernel_ms(plan) -> float:
+    ms = C.c_float()
+    _check(load().epo_plan_last_kernel_ms(plan, C.byref(ms)))
+    return ms.value

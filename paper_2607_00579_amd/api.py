@@ -1,0 +1,206 @@
+"""Python-level objects over the C-ABI: device buffers from torch, calls into
+libepo.so.  No arithmetic of the method happens here.
+
+    plan = EdgePlan.from_problem(problem, device="cuda:0")
+    out = plan.cost(poses, lam, grad=True)           # fused forward + adjoint
+    plan.pose_step(poses, m, v, out["grad"], lr, step)
+
+`EdgeCostFn` puts the fused adjoint behind torch.autograd.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _stream(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _require_gpu(device):
+    dev = torch.device(device)
+    if dev.type != "cuda" or not torch.cuda.is_available():
+        raise RuntimeError("the HIP path needs a ROCm GPU (no CPU fallback exists)")
+    _lib.load()
+    return dev
+
+
+def build_distance_fields(edge_flat: torch.Tensor, view_offset, width, height):
+    """Exact d2 (int32) and DTF (float32) of packed uint8 edge maps on the GPU."""
+    dev = edge_flat.device
+    n = edge_flat.numel()
+    d2 = torch.empty(n, dtype=torch.int32, device=dev)
+    dtf = torch.empty(n, dtype=torch.float32, device=dev)
+    vo = np.ascontiguousarray(view_offset, np.int64)
+    w = np.ascontiguousarray(width, np.int32)
+    h = np.ascontiguousarray(height, np.int32)
+    _lib.build_distance_fields(edge_flat, vo, w, h, int(w.size), d2, dtf, _stream(dev))
+    return d2, dtf
+
+
+class EdgePlan:
+    """A problem resident on one GPU: edge records, sampling textures, tile
+    schedule and per-iteration buffers, owned by a libepo plan."""
+
+    def __init__(self, width, height, K, scene_of_view, view_offset, edge_flat, depth_flat, pairs,
+                 huber_delta=1.0, z_min=1e-4, norm_mode=0, lambda_max=10.0, options=None,
+                 device="cuda:0", keep_fields=False):
+        dev = _require_gpu(device)
+        self.device = dev
+        self.width = np.ascontiguousarray(width, np.int32)
+        self.height = np.ascontiguousarray(height, np.int32)
+        self.K = np.ascontiguousarray(K, np.float32).reshape(-1, 4)
+        self.scene_of_view = np.ascontiguousarray(scene_of_view, np.int32)
+        self.view_offset = np.ascontiguousarray(view_offset, np.int64)[: self.width.size]
+        self.pairs = np.ascontiguousarray(pairs, np.int32).reshape(-1, 2)
+        self.n_views = int(self.width.size)
+        self.n_pairs = int(self.pairs.shape[0])
+        with torch.cuda.device(dev):
+            e = edge_flat if torch.is_tensor(edge_flat) else torch.from_numpy(np.asarray(edge_flat))
+            z = depth_flat if torch.is_tensor(depth_flat) else torch.from_numpy(np.asarray(depth_flat))
+            e = e.to(dev, torch.uint8).contiguous()
+            z = z.to(dev, torch.float32).contiguous()
+            d2, dtf = build_distance_fields(e, self.view_offset, self.width, self.height)
+            self.params = _lib.CostParams(huber_delta, z_min, norm_mode, lambda_max)
+            opts = None
+            if options is not None:
+                opts = _lib.PlanOptions(**{k: int(options.get(k, 0))
+                                           for k, _ in _lib.PlanOptions._fields_})
+            self.handle = _lib.plan_create(self.n_views, self.width, self.height, self.K,
+                                           self.scene_of_view, self.view_offset, e, z, d2,
+                                           self.pairs, self.n_pairs, self.params, opts,
+                                           _stream(dev))
+            self.d2 = d2 if keep_fields else None
+            self.dtf = dtf if keep_fields else None
+            del e, z
+        info = _lib.plan_info(self.handle)
+        self.n_scenes = info["n_scenes"]
+        self.n_residuals = info["n_residuals"]
+        self.n_records = info["n_records"]
+        self.scene_of_view_t = torch.from_numpy(self.scene_of_view.astype(np.int64)).to(dev)
+        self.scene_of_view_i32 = torch.from_numpy(self.scene_of_view).to(dev)
+
+    @classmethod
+    def from_problem(cls, prob, device="cuda:0", **kw):
+        return cls(prob.width, prob.height, prob.K, prob.scene_of_view, prob.view_offset,
+                   prob.edge_flat, prob.depth_flat, prob.pairs, device=device, **kw)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                _lib.plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    # ------------------------------------------------------------------
+    def info(self):
+        return _lib.plan_info(self.handle)
+
+    def view_records(self, v: int) -> np.ndarray:
+        return _lib.plan_view_records(self.handle, v)
+
+    def _f64(self, *shape):
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    def lam_tensor(self, lam):
+        if torch.is_tensor(lam):
+            return lam.to(self.device, torch.float32).contiguous()
+        a = np.broadcast_to(np.asarray(lam, np.float32), (self.n_scenes,)).copy()
+        return torch.from_numpy(a).to(self.device)
+
+    def cost(self, poses: torch.Tensor, lam, grad=True, pairs=False, out=None):
+        """Fused forward (+ adjoint).  Returns device tensors: loss [S], grad
+        [V, 6] (if grad), and per-pair cost / valid count / target gradient
+        sums (if pairs)."""
+        lam_t = self.lam_tensor(lam)
+        o = out if out is not None else {}
+        if "loss" not in o:
+            o["loss"] = self._f64(self.n_scenes)
+        if grad and "grad" not in o:
+            o["grad"] = self._f64(self.n_views, 6)
+        if pairs:
+            o.setdefault("pair_cost", self._f64(self.n_pairs))
+            o.setdefault("pair_valid", torch.empty(self.n_pairs, dtype=torch.int32,
+                                                   device=self.device))
+            o.setdefault("pair_grad", self._f64(self.n_pairs, 6))
+        _lib.edge_cost_fwd(self.handle, poses, lam_t, o["loss"], o.get("pair_cost") if pairs else None,
+                           o.get("pair_valid") if pairs else None,
+                           o.get("pair_grad") if pairs else None, o.get("grad") if grad else None,
+                           _stream(self.device))
+        return o
+
+    def cost_bwd(self, poses, lam, upstream=None, grad=None):
+        lam_t = self.lam_tensor(lam)
+        g = grad if grad is not None else self._f64(self.n_views, 6)
+        up = None if upstream is None else upstream.to(self.device, torch.float64).contiguous()
+        _lib.edge_cost_bwd(self.handle, poses, lam_t, up, g, _stream(self.device))
+        return g
+
+    def pose_step(self, poses, m, v, grad, lr, step, fixed_mask=None, beta1=0.9, beta2=0.999,
+                  eps=1e-8):
+        if not torch.is_tensor(lr):
+            lr = torch.full((self.n_scenes,), float(lr), dtype=torch.float64, device=self.device)
+        _lib.pose_step(poses, m, v, grad, self.n_views, self.scene_of_view_i32, fixed_mask, lr,
+                       beta1, beta2, eps, step, _stream(self.device))
+
+    def autotune(self, poses, lam, iters=3):
+        return _lib.plan_autotune(self.handle, poses, self.lam_tensor(lam), iters,
+                                  _stream(self.device))
+
+    def set_options(self, **options):
+        _lib.plan_set_options(self.handle, options, _stream(self.device))
+
+    def capture_iteration(self, poses, m, v, step, loss, grad=None, fixed_mask=None,
+                          lambda0=10.0, lambda1=6.0, anneal_steps=1000, peak_lr=3e-3, warmup=25,
+                          total=2000, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._graph_refs = (poses, m, v, step, loss, grad, fixed_mask)   # keep buffers alive
+        _lib.iteration_capture(self.handle, poses, m, v, step, loss, grad, fixed_mask, lambda0,
+                               lambda1, anneal_steps, peak_lr, warmup, total, beta1, beta2, eps,
+                               _stream(self.device))
+
+    def launch_iteration(self):
+        _lib.iteration_launch(self.handle, _stream(self.device))
+
+    def device_status(self) -> int:
+        return _lib.get_device_status(self.handle, _stream(self.device))
+
+    def enable_timing(self, on=True):
+        _lib.plan_enable_timing(self.handle, on)
+
+    def last_kernel_ms(self) -> float:
+        return _lib.plan_last_kernel_ms(self.handle)
+
+
+class EdgeCostFn(torch.autograd.Function):
+    """loss[s] of every scene as a differentiable function of left twists xi
+    (V x 6, float64) at the current poses; the gradient is the derivative at
+    xi = 0 and comes from the hand-written adjoint kernel.
+
+    mode "fused": the forward pass runs forward + adjoint together and keeps
+    the gradient; mode "recompute": backward calls the adjoint-only entry
+    point with the upstream gradient."""
+
+    @staticmethod
+    def forward(ctx, xi, plan: EdgePlan, poses, lam, mode="fused"):
+        ctx.plan, ctx.mode = plan, mode
+        if mode == "fused":
+            o = plan.cost(poses, lam, grad=True)
+            ctx.save_for_backward(o["grad"])
+        else:
+            o = plan.cost(poses, lam, grad=False)
+            ctx.poses, ctx.lam = poses, lam
+        return o["loss"]
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        plan = ctx.plan
+        if ctx.mode == "fused":
+            (g,) = ctx.saved_tensors
+            scale = grad_loss.to(torch.float64)[plan.scene_of_view_t].unsqueeze(1)
+            return scale * g, None, None, None, None
+        g = plan.cost_bwd(ctx.poses, ctx.lam, upstream=grad_loss.to(torch.float64).contiguous())
+        return g, None, None, None, None

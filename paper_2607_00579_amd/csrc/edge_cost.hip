@@ -1,0 +1,453 @@
+// Per-iteration hot path on gfx950: relative poses, the fused residual +
+// adjoint kernel, and the float64 reductions to per-pair, per-pose and
+// per-scene sums (paper Eqs. pi, L, L_ij, d_ij; supplementary Alg. 3 and
+// Sec. A1.2 "Per-iteration kernels").
+//
+// Fused kernel, per residual (source edge pixel p = (u, v) with depth Z of
+// view i, directed pair i -> j):
+//   lift + warp + project in one step: h = Z B (u, v, 1)^T + c with
+//     B = K_j R_ji K_i^-1 and c = K_j t_ji, so u' = h_x / h_z, v' = h_y / h_z
+//     and the target-camera depth is z = h_z (the paper lifts to the world once
+//     per image and projects per pair; folding the pose-free lift into one
+//     3x3 per pair gives the same point with fewer operations); this
+//     coordinate, the validity test and the cell split are float64, the rest
+//     of the residual and its adjoint float32;
+//   valid iff z > z_min and 0 <= u' < W_j - 1 and 0 <= v' < H_j - 1;
+//   bilinear D from the cell floor(u'), floor(v'); d^ = min(D, lambda);
+//   rho = Huber(d^); rho' = dHuber/dd^ if D < lambda else 0;
+//   adjoint: with A_u = rho' dD/du' fx_j, A_v = rho' dD/dv' fy_j, the
+//   normalised target coordinates x_n = (u' - cx_j)/fx_j, y_n likewise and
+//   w = -(A_u x_n + A_v y_n), the left-twist gradient of the target pose is
+//     (A_u, A_v, w) / z   and   (y_n w - A_v, A_u - x_n w, x_n A_v - y_n A_u)
+//   (the translation block is dH/dX', the rotation block X' x dH/dX', in
+//   which the depth cancels).
+// Each thread adds its float32 residual terms in float64; each workgroup
+// reduces its tile to eight float64 partial sums (S, n, G[6]) with wave64
+// butterflies and an LDS step across its four waves.  Everything above the
+// tile is float64 in a fixed order too: per pair (tiles in order), per
+// pose (g_j += w_d G_d, g_i += -w_d Ad(T_ji)^T G_d), per scene.
+#include "epo_internal.h"
+
+namespace epo {
+namespace {
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// relative poses and pair descriptors (one thread per directed pair)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void pair_setup_kernel(
+    const double* __restrict__ poses, const float* __restrict__ K, const int32_t* __restrict__ wh,
+    const int64_t* __restrict__ view_off, const PairStatic* __restrict__ ps,
+    const float* __restrict__ lambda, float lambda_max, PairDesc* __restrict__ desc,
+    double* __restrict__ rel, int32_t D, int32_t* __restrict__ counters, int32_t n_counters,
+    int32_t* __restrict__ status) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d < n_counters) counters[d] = 0;      // work queues of the next cost launch
+    if (d >= D) return;
+    const PairStatic st = ps[d];
+    const int i = st.src, j = st.tgt;
+    double Ri[9], ti[3], Rj[9], tj[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) {
+            Ri[3 * r + c] = poses[12 * i + 4 * r + c];
+            Rj[3 * r + c] = poses[12 * j + 4 * r + c];
+        }
+        ti[r] = poses[12 * i + 4 * r + 3];
+        tj[r] = poses[12 * j + 4 * r + 3];
+    }
+    // R_ji = R_j R_i^T, t_ji = t_j - R_ji t_i
+    double R[9], t[3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            R[3 * r + c] = Rj[3 * r + 0] * Ri[3 * c + 0] + Rj[3 * r + 1] * Ri[3 * c + 1] +
+                           Rj[3 * r + 2] * Ri[3 * c + 2];
+    for (int r = 0; r < 3; ++r)
+        t[r] = tj[r] - (R[3 * r + 0] * ti[0] + R[3 * r + 1] * ti[1] + R[3 * r + 2] * ti[2]);
+    const double fxi = K[4 * i + 0], fyi = K[4 * i + 1], cxi = K[4 * i + 2], cyi = K[4 * i + 3];
+    const double fxj = K[4 * j + 0], fyj = K[4 * j + 1], cxj = K[4 * j + 2], cyj = K[4 * j + 3];
+    // M = R_ji K_i^-1
+    double M[9];
+    for (int r = 0; r < 3; ++r) {
+        M[3 * r + 0] = R[3 * r + 0] / fxi;
+        M[3 * r + 1] = R[3 * r + 1] / fyi;
+        M[3 * r + 2] = R[3 * r + 2] - R[3 * r + 0] * (cxi / fxi) - R[3 * r + 1] * (cyi / fyi);
+    }
+    PairDesc o;
+    for (int c = 0; c < 3; ++c) {
+        o.B[0 + c] = fxj * M[0 + c] + cxj * M[6 + c];
+        o.B[3 + c] = fyj * M[3 + c] + cyj * M[6 + c];
+        o.B[6 + c] = M[6 + c];
+    }
+    o.c[0] = fxj * t[0] + cxj * t[2];
+    o.c[1] = fyj * t[1] + cyj * t[2];
+    o.c[2] = t[2];
+    o.fx = (float)fxj;
+    o.fy = (float)fyj;
+    o.ifx = (float)(1.0 / fxj);
+    o.ify = (float)(1.0 / fyj);
+    o.cxn = (float)(cxj / fxj);
+    o.cyn = (float)(cyj / fyj);
+    o.wlim = (double)(wh[2 * j + 0] - 1);
+    o.hlim = (double)(wh[2 * j + 1] - 1);
+    const float lam = lambda[st.scene];
+    if (!(lam <= lambda_max)) atomicOr(status, 2);
+    o.lambda = lam;
+    o.width = wh[2 * j + 0];
+    o.tex_off = view_off[j];
+    desc[d] = o;
+    for (int k = 0; k < 9; ++k) rel[12 * d + k] = R[k];
+    for (int k = 0; k < 3; ++k) rel[12 * d + 9 + k] = t[k];
+}
+
+// ---------------------------------------------------------------------------
+// fused residual + adjoint + tile reduction
+// ---------------------------------------------------------------------------
+template <int FMT>
+struct Taps;
+
+// float32 texture: four gathers
+template <>
+struct Taps<1> {
+    __device__ static inline void load(const uint32_t* __restrict__ tex, int idx, int W,
+                                       const float* /*lut*/, float& d00, float& d10, float& d01,
+                                       float& d11) {
+        const float* t = reinterpret_cast<const float*>(tex);
+        d00 = t[idx];
+        d10 = t[idx + 1];
+        d01 = t[idx + W];
+        d11 = t[idx + W + 1];
+    }
+};
+
+// saturated u8 quads: one gather, four LDS look-ups of sqrt(k)
+template <>
+struct Taps<2> {
+    __device__ static inline void load(const uint32_t* __restrict__ tex, int idx, int /*W*/,
+                                       const float* lut, float& d00, float& d10, float& d01,
+                                       float& d11) {
+        const uint32_t q = tex[idx];
+        d00 = lut[q & 0xffu];
+        d10 = lut[(q >> 8) & 0xffu];
+        d01 = lut[(q >> 16) & 0xffu];
+        d11 = lut[q >> 24];
+    }
+};
+
+// per-thread sums: every float32 residual term is added in float64 (the
+// pose-gradient sums cancel strongly, up to a few hundred in
+// sum |term| / |sum|), the valid count in integers
+struct Acc {
+    double S, g0, g1, g2, g3, g4, g5;
+    int n;
+};
+
+template <int FMT>
+__device__ inline void residual(const uint2 rec, bool active, const PairDesc& pd,
+                                const uint32_t* __restrict__ texj, const float* lut, float delta,
+                                double zmin, Acc& a) {
+    // projected coordinate in float64 (full rate on CDNA4 with packed FP32
+    // off): it decides the bilinear cell, an integer, exactly as the oracle
+    const double u = (double)(rec.x & 0xffffu);
+    const double v = (double)(rec.x >> 16);
+    const double Z = (double)__uint_as_float(rec.y);
+    const double hx = fma(Z, fma(pd.B[0], u, fma(pd.B[1], v, pd.B[2])), pd.c[0]);
+    const double hy = fma(Z, fma(pd.B[3], u, fma(pd.B[4], v, pd.B[5])), pd.c[1]);
+    const double hz = fma(Z, fma(pd.B[6], u, fma(pd.B[7], v, pd.B[8])), pd.c[2]);
+    const double rzd = 1.0 / hz;
+    const double upd = hx * rzd;
+    const double vpd = hy * rzd;
+    const bool valid = active && (hz > zmin) && (upd >= 0.0) && (upd < pd.wlim) && (vpd >= 0.0) &&
+                       (vpd < pd.hlim);
+    const double fx0 = floor(upd), fy0 = floor(vpd);
+    // invalid residuals may carry inf/NaN coordinates: zero everything that
+    // reaches a product with a zero weight
+    const float al = valid ? (float)(upd - fx0) : 0.0f;
+    const float be = valid ? (float)(vpd - fy0) : 0.0f;
+    const int idx = valid ? ((int)fy0 * pd.width + (int)fx0) : 0;
+    const float up = (float)upd, vp = (float)vpd, rz = (float)rzd;
+    float d00, d10, d01, d11;
+    Taps<FMT>::load(texj, idx, pd.width, lut, d00, d10, d01, d11);
+    const float e0 = d10 - d00, e1 = d11 - d01;
+    const float f0 = d01 - d00, f1 = d11 - d10;
+    const float gu = fmaf(be, e1 - e0, e0);
+    const float gv = fmaf(al, f1 - f0, f0);
+    const float D = fmaf(be, gv, fmaf(al, e0, d00));
+    const bool unclamped = D < pd.lambda;
+    const float dh = unclamped ? D : pd.lambda;
+    const bool quad = dh <= delta;
+    float rho = quad ? 0.5f * dh * dh : delta * (dh - 0.5f * delta);
+    float drho = unclamped ? (quad ? dh : delta) : 0.0f;
+    rho = valid ? rho : 0.0f;
+    drho = valid ? drho : 0.0f;
+    const float Au = drho * gu * pd.fx;
+    const float Av = drho * gv * pd.fy;
+    const float xn = valid ? fmaf(up, pd.ifx, -pd.cxn) : 0.0f;
+    const float yn = valid ? fmaf(vp, pd.ify, -pd.cyn) : 0.0f;
+    const float w = -fmaf(Au, xn, Av * yn);
+    const float rzv = valid ? rz : 0.0f;
+    a.S += (double)rho;
+    a.n += valid ? 1 : 0;
+    a.g0 += (double)(Au * rzv);
+    a.g1 += (double)(Av * rzv);
+    a.g2 += (double)(w * rzv);
+    a.g3 += (double)fmaf(yn, w, -Av);
+    a.g4 += (double)fmaf(-xn, w, Au);
+    a.g5 += (double)fmaf(xn, Av, -yn * Au);
+}
+
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+template <int FMT, int P>
+__device__ inline void do_tile(int64_t t, const uint2* __restrict__ records,
+                               const uint32_t* __restrict__ tex, const Tile* __restrict__ tiles,
+                               const PairDesc* __restrict__ desc, Partial* __restrict__ partials,
+                               const float* lut, double (*red)[8], float delta, double zmin) {
+    const int tid = threadIdx.x;
+    const Tile tl = tiles[t];
+    const PairDesc pd = desc[tl.pair];
+    const uint32_t* texj = tex + pd.tex_off;
+    const uint2* rec = records + tl.rec;
+    Acc a{0, 0, 0, 0, 0, 0, 0, 0};
+    uint2 r[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const int idx = k * kBlock + tid;
+        r[k] = idx < tl.count ? rec[idx] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        residual<FMT>(r[k], k * kBlock + tid < tl.count, pd, texj, lut, delta, zmin, a);
+    }
+    double s[8] = {a.S, (double)a.n, a.g0, a.g1, a.g2, a.g3, a.g4, a.g5};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] = wave_sum(s[k]);
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) red[wave][k] = s[k];
+    }
+    __syncthreads();
+    if (tid < 8) {
+        const double x = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+        partials[t].v[tid] = x;
+    }
+}
+
+template <int FMT, int P>
+__global__ __launch_bounds__(kBlock) void edge_cost_kernel(
+    const uint2* __restrict__ records, const uint32_t* __restrict__ tex,
+    const Tile* __restrict__ tiles, const PairDesc* __restrict__ desc,
+    Partial* __restrict__ partials, const int64_t* __restrict__ xcd_begin, int32_t n_queues,
+    int32_t* __restrict__ counters, int32_t persistent, float delta, double zmin) {
+    __shared__ float lut[256];
+    __shared__ double red[4][8];
+    __shared__ int64_t claim;
+    if (FMT == 2) lut[threadIdx.x] = sqrtf((float)threadIdx.x);
+    __syncthreads();
+    const int q0 = (int)(blockIdx.x % (unsigned)n_queues);
+    if (!persistent) {
+        // one workgroup per tile; workgroup b runs on XCD b mod 8, so the
+        // tiles of queue q (consecutive target views) stay on one XCD's L2
+        const int64_t t = xcd_begin[q0] + blockIdx.x / (unsigned)n_queues;
+        if (t >= xcd_begin[q0 + 1]) return;
+        do_tile<FMT, P>(t, records, tex, tiles, desc, partials, lut, red, delta, zmin);
+        return;
+    }
+    // persistent: claim tiles from the own queue, then from the others
+    for (int qi = 0; qi < n_queues; ++qi) {
+        const int q = (q0 + qi) % n_queues;
+        const int64_t begin = xcd_begin[q], end = xcd_begin[q + 1];
+        for (;;) {
+            if (threadIdx.x == 0) claim = begin + atomicAdd(&counters[q], 1);
+            __syncthreads();
+            const int64_t t = claim;
+            __syncthreads();
+            if (t >= end) break;
+            do_tile<FMT, P>(t, records, tex, tiles, desc, partials, lut, red, delta, zmin);
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// float64 reductions
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void reduce_pairs_kernel(
+    const Partial* __restrict__ partials, const PairStatic* __restrict__ ps, int32_t D,
+    int32_t norm_mode, double* __restrict__ pair_sum, double* __restrict__ pair_w,
+    double* __restrict__ pair_cost, int32_t* __restrict__ pair_valid,
+    double* __restrict__ pair_grad, int32_t* __restrict__ status) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= D) return;
+    const PairStatic st = ps[d];
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < st.n_tiles; ++k) {
+        const Partial pt = partials[st.first_tile + k];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s[c] += pt.v[c];
+    }
+    const double den = norm_mode == 0 ? s[1] : (double)st.n_src;
+    const double L = den > 0 ? s[0] / den : 0.0;
+    const double w = den > 0 ? (double)st.scale / den : 0.0;
+    if (!isfinite(s[0]) || !isfinite(s[2]) || !isfinite(s[5])) atomicOr(status, 1);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) pair_sum[8 * d + c] = s[c];
+    pair_w[d] = w;
+    if (pair_cost) pair_cost[d] = L;
+    if (pair_valid) pair_valid[d] = (int32_t)s[1];
+    if (pair_grad) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) pair_grad[6 * d + c] = s[2 + c];
+    }
+}
+
+__global__ __launch_bounds__(256) void reduce_views_kernel(
+    const double* __restrict__ pair_sum, const double* __restrict__ pair_w,
+    const double* __restrict__ rel, const PairStatic* __restrict__ ps,
+    const int32_t* __restrict__ in_ptr, const int32_t* __restrict__ in_idx,
+    const int32_t* __restrict__ out_ptr, const int32_t* __restrict__ out_idx,
+    const int32_t* __restrict__ scene_of_view, const int32_t* __restrict__ scene_ptr,
+    const int32_t* __restrict__ scene_pairs, int32_t V, int32_t S, int32_t norm_mode,
+    const double* __restrict__ upstream, double* __restrict__ grad, double* __restrict__ loss) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (loss && id < S) {
+        double L = 0.0;
+        for (int k = scene_ptr[id]; k < scene_ptr[id + 1]; ++k) {
+            const int d = scene_pairs[k];
+            const PairStatic st = ps[d];
+            const double den = norm_mode == 0 ? pair_sum[8 * d + 1] : (double)st.n_src;
+            if (den > 0) L += (double)st.scale * (pair_sum[8 * d + 0] / den);
+        }
+        loss[id] = L;
+    }
+    if (!grad || id >= V) return;
+    double g[6] = {0, 0, 0, 0, 0, 0};
+    // pairs whose target is this view: g += w G
+    for (int k = in_ptr[id]; k < in_ptr[id + 1]; ++k) {
+        const int d = in_idx[k];
+        const double w = pair_w[d];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) g[c] += w * pair_sum[8 * d + 2 + c];
+    }
+    // pairs whose source is this view: g += -w Ad(T_ji)^T G
+    //   Ad^T (G_r, G_w) = (R^T G_r, R^T (G_w - t x G_r))
+    for (int k = out_ptr[id]; k < out_ptr[id + 1]; ++k) {
+        const int d = out_idx[k];
+        const double w = pair_w[d];
+        const double* R = rel + 12 * d;
+        const double* t = R + 9;
+        const double* G = pair_sum + 8 * d + 2;
+        const double c0 = G[3] - (t[1] * G[2] - t[2] * G[1]);
+        const double c1 = G[4] - (t[2] * G[0] - t[0] * G[2]);
+        const double c2 = G[5] - (t[0] * G[1] - t[1] * G[0]);
+        for (int r = 0; r < 3; ++r) {
+            g[r] -= w * (R[0 + r] * G[0] + R[3 + r] * G[1] + R[6 + r] * G[2]);
+            g[3 + r] -= w * (R[0 + r] * c0 + R[3 + r] * c1 + R[6 + r] * c2);
+        }
+    }
+    const double up = upstream ? upstream[scene_of_view[id]] : 1.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) grad[6 * id + c] = up * g[c];
+}
+
+template <int FMT, int P>
+void launch_cost_kernel(Plan& p, hipStream_t s) {
+    const uint32_t* tex = (FMT == 2) ? p.tex.p : reinterpret_cast<const uint32_t*>(p.tex_f32.p);
+    const int nq = p.n_xcd_queues;
+    unsigned grid;
+    if (p.opt.persistent == 1) {
+        int64_t want = (int64_t)p.n_cu * 8;
+        want = std::min<int64_t>(want, ceil_div(p.n_tiles, 1) + nq);
+        grid = (unsigned)(ceil_div(want, nq) * nq);
+    } else {
+        int64_t per_q = 0;
+        for (int q = 0; q < nq; ++q)
+            per_q = std::max<int64_t>(per_q, p.xcd_begin[q + 1] - p.xcd_begin[q]);
+        grid = (unsigned)(per_q * nq);
+    }
+    if (grid == 0) return;
+    edge_cost_kernel<FMT, P><<<grid, kBlock, 0, s>>>(
+        reinterpret_cast<const uint2*>(p.records.p), tex, p.tiles.p, p.pair_desc.p, p.partials.p,
+        p.xcd_begin_d.p, nq, p.counters.p,
+        p.opt.persistent == 1 ? 1 : 0, p.params.huber_delta, p.params.z_min);
+    EPO_CHECK_LAUNCH();
+}
+
+template <int FMT>
+void launch_cost_fmt(Plan& p, hipStream_t s) {
+    switch (p.opt.points_per_thread) {
+        case 1: launch_cost_kernel<FMT, 1>(p, s); break;
+        case 2: launch_cost_kernel<FMT, 2>(p, s); break;
+        case 4: launch_cost_kernel<FMT, 4>(p, s); break;
+        case 8: launch_cost_kernel<FMT, 8>(p, s); break;
+        case 16: launch_cost_kernel<FMT, 16>(p, s); break;
+        default: throw Failure{EPO_ERR_UNSUPPORTED, "points_per_thread must be 1, 2, 4, 8 or 16"};
+    }
+}
+
+}  // namespace
+
+void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss,
+                 double* pair_cost, int32_t* pair_valid, double* pair_grad, double* grad,
+                 const double* upstream, hipStream_t s) {
+    if (p.D > 0) {
+        pair_setup_kernel<<<(unsigned)ceil_div(std::max(p.D, 16), 256), 256, 0, s>>>(
+            poses, p.K_d.p, p.wh_d.p, p.view_offset_d.p, p.pair_static.p, lambda,
+            p.params.lambda_max, p.pair_desc.p, p.pair_rel.p, p.D, p.counters.p, 8, p.status.p);
+        EPO_CHECK_LAUNCH();
+        const bool timed = p.timing;
+        if (timed) EPO_HIP(hipEventRecord(p.ev0, s));
+        if (p.opt.texture_format == 2)
+            launch_cost_fmt<2>(p, s);
+        else
+            launch_cost_fmt<1>(p, s);
+        if (timed) {
+            EPO_HIP(hipEventRecord(p.ev1, s));
+            p.timed_once = true;
+        }
+        reduce_pairs_kernel<<<(unsigned)ceil_div(p.D, 256), 256, 0, s>>>(
+            p.partials.p, p.pair_static.p, p.D, p.params.norm_mode, p.pair_sum.p, p.pair_w.p,
+            pair_cost, pair_valid, pair_grad, p.status.p);
+        EPO_CHECK_LAUNCH();
+    }
+    const int n = std::max(p.V, p.S);
+    reduce_views_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(
+        p.pair_sum.p, p.pair_w.p, p.pair_rel.p, p.pair_static.p, p.view_in_ptr.p, p.view_in_idx.p,
+        p.view_out_ptr.p, p.view_out_idx.p, p.scene_of_view_d.p, p.scene_ptr.p, p.scene_pairs.p,
+        p.V, p.S, p.params.norm_mode, upstream, grad, loss);
+    EPO_CHECK_LAUNCH();
+}
+
+}  // namespace epo
+
+extern "C" epo_status epo_edge_cost_fwd(epo_plan plan, const double* poses, const float* lambda,
+                                        double* loss, double* pair_cost, int32_t* pair_valid,
+                                        double* pair_grad, double* grad, void* stream) {
+    using namespace epo;
+    return guarded([&] {
+        EPO_REQUIRE(plan, "null plan");
+        EPO_REQUIRE(poses && lambda && loss, "poses, lambda and loss are required");
+        Plan& p = *reinterpret_cast<Plan*>(plan);
+        EPO_HIP(hipSetDevice(p.device));
+        launch_cost(p, poses, lambda, loss, pair_cost, pair_valid, pair_grad, grad, nullptr,
+                    as_stream(stream));
+    });
+}
+
+extern "C" epo_status epo_edge_cost_bwd(epo_plan plan, const double* poses, const float* lambda,
+                                        const double* upstream, double* grad, void* stream) {
+    using namespace epo;
+    return guarded([&] {
+        EPO_REQUIRE(plan, "null plan");
+        EPO_REQUIRE(poses && lambda && grad, "poses, lambda and grad are required");
+        Plan& p = *reinterpret_cast<Plan*>(plan);
+        EPO_HIP(hipSetDevice(p.device));
+        launch_cost(p, poses, lambda, nullptr, nullptr, nullptr, nullptr, grad, upstream,
+                    as_stream(stream));
+    });
+}

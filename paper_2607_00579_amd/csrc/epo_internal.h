@@ -1,0 +1,205 @@
+// Internal declarations shared by the translation units of libepo.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/epo.h"
+
+namespace epo {
+
+// ---------------------------------------------------------------------------
+// error handling: thread-local message + status, no exception crosses the ABI
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+void clear_error();
+
+struct Failure {
+    epo_status status;
+    std::string msg;
+};
+
+#define EPO_REQUIRE(cond, msg)                                                  \
+    do {                                                                        \
+        if (!(cond)) throw ::epo::Failure{EPO_ERR_INVALID_ARG, (msg)};          \
+    } while (0)
+
+#define EPO_HIP(call)                                                           \
+    do {                                                                        \
+        hipError_t e_ = (call);                                                 \
+        if (e_ != hipSuccess)                                                   \
+            throw ::epo::Failure{EPO_ERR_HIP, std::string(#call) + ": " +       \
+                                                  hipGetErrorString(e_)};       \
+    } while (0)
+
+#define EPO_CHECK_LAUNCH()                                                      \
+    do {                                                                        \
+        hipError_t e_ = hipGetLastError();                                      \
+        if (e_ != hipSuccess)                                                   \
+            throw ::epo::Failure{EPO_ERR_HIP, std::string("kernel launch: ") +  \
+                                                  hipGetErrorString(e_)};       \
+    } while (0)
+
+template <class F>
+epo_status guarded(F&& f) {
+    try {
+        clear_error();
+        f();
+        return EPO_OK;
+    } catch (const Failure& e) {
+        set_error(e.msg);
+        return e.status;
+    } catch (const std::exception& e) {
+        set_error(std::string("internal error: ") + e.what());
+        return EPO_ERR_HIP;
+    } catch (...) {
+        set_error("internal error");
+        return EPO_ERR_HIP;
+    }
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// device buffer owned by a plan
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    void alloc(size_t count) {
+        release();
+        if (count == 0) count = 1;
+        EPO_HIP(hipMalloc(&p, count * sizeof(T)));
+        n = count;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    ~DevBuf() { release(); }
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+};
+
+// ---------------------------------------------------------------------------
+// per-iteration pair descriptor consumed by the fused kernel
+//   h = Z * B (u, v, 1)^T + c ; u' = h_x / h_z ; v' = h_y / h_z
+//   B = K_j R_ji K_i^-1, c = K_j t_ji (float64: the projected coordinate
+//   decides the bilinear cell, and float32 coordinates of a 500-1000 px image
+//   flip cells often enough to move pose gradients by a few 1e-4)
+// ---------------------------------------------------------------------------
+struct alignas(16) PairDesc {
+    double B[9];
+    double c[3];
+    double wlim, hlim;     // W_j - 1, H_j - 1
+    float fx, fy;          // target focal lengths (chain rule)
+    float ifx, ify;        // 1 / fx_j, 1 / fy_j
+    float cxn, cyn;        // cx_j / fx_j, cy_j / fy_j
+    float lambda;          // clamp of the pair's scene
+    int32_t width;         // W_j (texture row stride)
+    int64_t tex_off;       // element offset of view j in the texture
+};
+static_assert(sizeof(PairDesc) == 160, "PairDesc layout");
+
+// static per-pair data (plan lifetime)
+struct PairStatic {
+    int32_t src, tgt, scene;
+    int32_t first_tile, n_tiles;
+    int32_t n_src;          // source edge count |E_i|
+    float scale;            // 2 / (pairs in the scene)
+    int32_t pad;
+};
+
+// one tile = up to tile_size consecutive records of the source view of a pair
+struct Tile {
+    int32_t pair;
+    int32_t count;
+    int64_t rec;            // first record
+};
+
+// per-tile partial sums: S, n, G[6] (float64)
+struct alignas(64) Partial {
+    double v[8];
+};
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct Plan {
+    int device = 0;
+    int n_cu = 256;
+    int32_t V = 0, S = 0, D = 0;
+    epo_cost_params params{};
+    epo_plan_options opt{};
+    std::vector<int32_t> width, height, scene_of_view;
+    std::vector<float> K;                 // V x 4
+    std::vector<int64_t> view_offset;     // V
+    std::vector<int64_t> rec_off;         // V + 1 record offsets
+    std::vector<int32_t> pairs;           // D x 2
+    int64_t total_px = 0;
+    int64_t n_residuals = 0;
+
+    // device, plan lifetime
+    DevBuf<uint64_t> records;             // (u | v << 16) | (Z bits << 32)
+    DevBuf<uint32_t> tex;                 // texture (f32 bits or u8 quads), total_px
+    DevBuf<float> tex_f32;                // f32 texture when both kept
+    DevBuf<int32_t> scene_of_view_d;
+    DevBuf<float> K_d;                    // V x 4
+    DevBuf<int32_t> wh_d;                 // V x 2
+    DevBuf<int64_t> view_offset_d;        // V
+    DevBuf<PairStatic> pair_static;       // D
+    DevBuf<PairDesc> pair_desc;           // D (rewritten every iteration)
+    DevBuf<double> pair_rel;              // D x 12: R_ji, t_ji (float64)
+    DevBuf<Tile> tiles;                   // T
+    DevBuf<Partial> partials;             // T
+    DevBuf<double> pair_sum;              // D x 8: S, n, G[6] (float64)
+    DevBuf<double> pair_w;                // D: weight w_d
+    DevBuf<int32_t> view_in_idx, view_in_ptr;     // CSR: pairs with tgt == v
+    DevBuf<int32_t> view_out_idx, view_out_ptr;   // CSR: pairs with src == v
+    DevBuf<int32_t> scene_ptr;            // CSR: pairs of scene s are [scene_ptr[s], scene_ptr[s+1]) of scene_pairs
+    DevBuf<int32_t> scene_pairs;
+    DevBuf<int32_t> counters;             // work counters of the 8 XCD queues
+    DevBuf<int64_t> xcd_begin_d;          // 9 entries: tile range of each queue
+    DevBuf<int32_t> status;               // device status word
+    DevBuf<double> grad_scratch;          // V x 6 (graph iteration)
+    DevBuf<float> lambda_buf;             // S (graph iteration)
+    DevBuf<double> lr_buf;                // S (graph iteration)
+    int64_t n_tiles = 0;
+    int32_t tile_size = 0;
+    int32_t n_xcd_queues = 8;
+    std::vector<int64_t> xcd_begin;       // tile range of each XCD queue
+
+    // timing
+    bool timing = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed_once = false;
+
+    // captured iteration
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+
+    ~Plan();
+};
+
+// schedule (tile list) construction; (re)allocates tiles and partials
+void build_tiles(Plan& p, hipStream_t stream);
+
+// launches of the per-iteration pipeline (no allocation, no sync)
+void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss,
+                 double* pair_cost, int32_t* pair_valid, double* pair_grad, double* grad,
+                 const double* upstream, hipStream_t stream);
+void launch_pose_step(double* poses, double* m, double* v, const double* grad, int32_t n_views,
+                      const int32_t* scene_of_view, const uint8_t* fixed, const double* lr,
+                      double b1, double b2, double eps, int32_t* step, hipStream_t stream);
+void launch_schedule(const int32_t* step, int32_t n_scenes, float lambda0, float lambda1,
+                     int32_t anneal_steps, double peak_lr, int32_t warmup, int32_t total,
+                     float* lambda_out, double* lr_out, hipStream_t stream);
+void build_texture(Plan& p, const int32_t* d2, hipStream_t stream);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace epo

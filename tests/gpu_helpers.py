@@ -1,0 +1,38 @@
+"""Shared helpers of the GPU tests (inputs and comparisons only)."""
+import os
+
+import numpy as np
+
+from synth import make as _make
+
+_CACHE = {}
+
+
+def problem(name):
+    """Seeded workload, cached per process (and on disk via $EPO_SYNTH_CACHE)."""
+    if name not in _CACHE:
+        _CACHE[name] = _make(name)
+    return _CACHE[name]
+
+
+def rel_norm_err(got, want, axis=None):
+    """max_v ||got_v - want_v|| / max_v ||want_v|| over rows (or all)."""
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    if axis is None:
+        return float(np.abs(got - want).max() / max(np.abs(want).max(), 1e-300))
+    return float(np.linalg.norm(got - want, axis=axis).max()
+                 / max(np.linalg.norm(want, axis=axis).max(), 1e-300))
+
+
+def rotation_angle_deg(Ra, Rb):
+    c = np.clip((np.trace(Ra @ Rb.T) - 1.0) / 2.0, -1.0, 1.0)
+    return float(np.degrees(np.arccos(c)))
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def env_flag(name):
+    return os.environ.get(name, "") not in ("", "0")

@@ -1,0 +1,74 @@
+"""GPU: exact distance transform, bit-exact against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import edt as oedt
+from tests.gpu_helpers import problem, say
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_edt(maps):
+    """Run the HIP EDT on a list of uint8 maps packed back to back."""
+    from paper_2607_00579_amd.api import build_distance_fields
+    sizes = [m.size for m in maps]
+    off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    flat = np.concatenate([m.reshape(-1) for m in maps]).astype(np.uint8)
+    e = torch.from_numpy(flat).cuda()
+    d2, dtf = build_distance_fields(e, off, [m.shape[1] for m in maps], [m.shape[0] for m in maps])
+    d2 = d2.cpu().numpy()
+    dtf = dtf.cpu().numpy()
+    return ([d2[o:o + m.size].reshape(m.shape) for o, m in zip(off, maps)],
+            [dtf[o:o + m.size].reshape(m.shape) for o, m in zip(off, maps)])
+
+
+def test_all_4x4_maps_bit_exact(gpu):
+    say("edt: all 65536 4x4 maps")
+    m = np.arange(1 << 16, dtype=np.int64)
+    bits = ((m[:, None] >> np.arange(16)[None, :]) & 1).astype(np.uint8)
+    maps = [b.reshape(4, 4) for b in bits]
+    got, dtf = gpu_edt(maps)
+    ys, xs = np.divmod(np.arange(16), 4)
+    dist = (xs[:, None] - xs[None, :]) ** 2 + (ys[:, None] - ys[None, :]) ** 2
+    want = np.empty((1 << 16, 16), np.int64)
+    for p in range(16):
+        want[:, p] = np.where(bits.astype(bool), dist[p][None, :], oedt.INF_D2).min(axis=1)
+    got = np.stack([g.reshape(-1) for g in got])
+    assert np.array_equal(got, want)
+    assert np.array_equal(np.stack([d.reshape(-1) for d in dtf]),
+                          np.sqrt(want.astype(np.float32)).astype(np.float32))
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 37), (37, 1), (33, 17), (120, 160), (97, 301),
+                                   (392, 518)])
+@pytest.mark.parametrize("density", [0.0, 0.0005, 0.01, 0.1, 0.6, 1.0])
+def test_random_maps_bit_exact(gpu, shape, density):
+    rng = np.random.default_rng(abs(hash((shape, density))) % (1 << 32))
+    maps = [(rng.random(shape) < density).astype(np.uint8) * 255 for _ in range(3)]
+    got, _ = gpu_edt(maps)
+    for g, m in zip(got, maps):
+        assert np.array_equal(g, oedt.edt_separable(m))
+
+
+def test_wide_and_single_pixel(gpu):
+    maps = []
+    for (H, W, y0, x0) in [(3, 4000, 1, 3999), (2000, 2, 0, 0), (64, 2048, 63, 1000)]:
+        e = np.zeros((H, W), np.uint8)
+        e[y0, x0] = 1
+        maps.append(e)
+    got, _ = gpu_edt(maps)
+    for g, m in zip(got, maps):
+        (y0,), (x0,) = np.nonzero(m)
+        yy, xx = np.mgrid[0:m.shape[0], 0:m.shape[1]]
+        assert np.array_equal(g, (xx - x0) ** 2 + (yy - y0) ** 2)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_config_maps_bit_exact(gpu, name):
+    p = problem(name)
+    maps = [p.edge_map(v) for v in range(p.n_views)]
+    say(f"edt: {name} {len(maps)} views")
+    got, _ = gpu_edt(maps)
+    for v, (g, m) in enumerate(zip(got, maps)):
+        assert np.array_equal(g, oedt.edt_separable(m)), v

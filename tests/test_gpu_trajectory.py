@@ -1,0 +1,190 @@
+"""GPU: whole optimisation runs (captured iteration and eager calls) against
+the oracle's trajectories, and the pose step against the oracle's Adam step."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import loop as oloop
+from tests.gpu_helpers import problem, rel_norm_err, rotation_angle_deg, say
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    from tests.golden.make_golden import input_checksum
+    g = np.load(os.path.join(GOLDEN, f"{name}_trajectory.npz"), allow_pickle=False)
+    assert str(g["checksum"]) == input_checksum(problem(name)), "generator changed: rerun make_golden"
+    return g
+
+
+def run_captured(prob, n):
+    from paper_2607_00579_amd.api import EdgePlan
+    dev = torch.device("cuda:0")
+    plan = EdgePlan.from_problem(prob, device=dev)
+    poses = torch.from_numpy(prob.poses_init.copy()).to(dev)
+    m = torch.zeros(prob.n_views, 6, dtype=torch.float64, device=dev)
+    v = torch.zeros_like(m)
+    step = torch.zeros(1, dtype=torch.int32, device=dev)
+    loss = torch.zeros(plan.n_scenes, dtype=torch.float64, device=dev)
+    plan.capture_iteration(poses, m, v, step, loss)
+    hist = torch.zeros(n, plan.n_scenes, dtype=torch.float64, device=dev)
+    for s in range(n):
+        plan.launch_iteration()
+        hist[s] = loss
+    torch.cuda.synchronize()
+    assert int(step.item()) == n
+    return hist.cpu().numpy(), poses.cpu().numpy()
+
+
+def run_eager(prob, n):
+    from paper_2607_00579_amd import _lib
+    from paper_2607_00579_amd.api import EdgePlan
+    dev = torch.device("cuda:0")
+    plan = EdgePlan.from_problem(prob, device=dev)
+    poses = torch.from_numpy(prob.poses_init.copy()).to(dev)
+    m = torch.zeros(prob.n_views, 6, dtype=torch.float64, device=dev)
+    v = torch.zeros_like(m)
+    step = torch.zeros(1, dtype=torch.int32, device=dev)
+    lam = torch.zeros(plan.n_scenes, dtype=torch.float32, device=dev)
+    lr = torch.zeros(plan.n_scenes, dtype=torch.float64, device=dev)
+    hist = []
+    st = torch.cuda.current_stream().cuda_stream
+    for s in range(n):
+        _lib.schedule(step, plan.n_scenes, 10.0, 6.0, 1000, 3e-3, 25, 2000, lam, lr, st)
+        o = plan.cost(poses, lam, grad=True)
+        hist.append(o["loss"].clone())
+        plan.pose_step(poses, m, v, o["grad"], lr, step)
+    torch.cuda.synchronize()
+    return torch.stack(hist).cpu().numpy(), poses.cpu().numpy()
+
+
+def pose_diffs(a, b):
+    ang = max(rotation_angle_deg(a[k][:, :3], b[k][:, :3]) for k in range(a.shape[0]))
+    ca = -np.einsum("vji,vj->vi", a[:, :, :3], a[:, :, 3])
+    cb = -np.einsum("vji,vj->vi", b[:, :, :3], b[:, :, 3])
+    return ang, float(np.linalg.norm(ca - cb, axis=1).max())
+
+
+def compare(name, hist, final, g, rot_tol):
+    ref_loss = g["loss"]
+    n = int(g["iterations"])
+    rel = np.abs(hist[:, 0] - ref_loss[:, 0]) / np.abs(ref_loss[:, 0])
+    ang, dc = pose_diffs(final, g["final_poses"])
+    say(f"{name}: {n} iters, loss rel err first 10 {rel[:10].max():.2e}, all {rel.max():.2e}, "
+        f"final rotation diff max {ang:.2e} deg, centre diff {dc:.2e}")
+    assert rel[:10].max() < 1e-5
+    assert ang < rot_tol
+
+
+def test_captured_iteration_trajectory_c1(gpu):
+    """50 steps: the whole run stays within 0.01 deg of the oracle."""
+    g = golden("c1")
+    hist, final = run_captured(problem("c1"), int(g["iterations"]))
+    compare("c1 graph", hist, final, g, rot_tol=0.01)
+
+
+def test_captured_iteration_trajectory_c2_full_run(gpu):
+    """200 steps.  The run is chaotic: the oracle against itself with a 1e-11
+    relative perturbation of each gradient already ends 0.05 deg apart (the
+    gap grows about 30x per 10 steps between steps 30 and 60, then
+    saturates), so the whole run is only held to that saturation level; the
+    10-step windows below carry the parity bar."""
+    g = golden("c2")
+    hist, final = run_captured(problem("c2"), int(g["iterations"]))
+    compare("c2 graph", hist, final, g, rot_tol=0.2)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_trajectory_windows_from_oracle_states(gpu, name):
+    """Restart the captured iteration from the oracle's state (poses, Adam
+    moments, step) every 10 steps and run 10 steps: every window must end
+    within 1e-3 deg of the oracle, every loss within 1e-5."""
+    from paper_2607_00579_amd.api import EdgePlan
+    g = golden(name)
+    prob = problem(name)
+    dev = torch.device("cuda:0")
+    plan = EdgePlan.from_problem(prob, device=dev)
+    poses = torch.zeros(prob.n_views, 3, 4, dtype=torch.float64, device=dev)
+    m = torch.zeros(prob.n_views, 6, dtype=torch.float64, device=dev)
+    v = torch.zeros_like(m)
+    step = torch.zeros(1, dtype=torch.int32, device=dev)
+    loss = torch.zeros(plan.n_scenes, dtype=torch.float64, device=dev)
+    plan.capture_iteration(poses, m, v, step, loss)
+    n_win = g["poses_every10"].shape[0] - 1
+    worst_ang, worst_loss = 0.0, 0.0
+    for k in range(n_win):
+        poses.copy_(torch.from_numpy(g["poses_every10"][k]))
+        m.copy_(torch.from_numpy(g["m_every10"][k]))
+        v.copy_(torch.from_numpy(g["v_every10"][k]))
+        step.fill_(10 * k)
+        steps = min(10, int(g["iterations"]) - 10 * k)
+        for s in range(steps):
+            plan.launch_iteration()
+            ref = g["loss"][10 * k + s, 0]
+            worst_loss = max(worst_loss, abs(float(loss[0].item()) - ref) / abs(ref))
+        ang, _ = pose_diffs(poses.cpu().numpy(), g["poses_every10"][k + 1])
+        worst_ang = max(worst_ang, ang)
+    say(f"{name}: {n_win} windows of 10 steps: worst rotation diff {worst_ang:.2e} deg, "
+        f"worst loss rel err {worst_loss:.2e}")
+    assert worst_ang < 1e-3
+    assert worst_loss < 1e-5
+
+
+def test_eager_trajectory_c1_equals_captured(gpu):
+    g = golden("c1")
+    n = int(g["iterations"])
+    h1, f1 = run_eager(problem("c1"), n)
+    h2, f2 = run_captured(problem("c1"), n)
+    compare("c1 eager", h1, f1, g, rot_tol=0.01)
+    assert np.array_equal(h1, h2) and np.array_equal(f1, f2)
+
+
+def test_pose_step_matches_oracle(gpu):
+    from paper_2607_00579_amd import _lib
+    rng = np.random.default_rng(7)
+    V = 37
+    poses = np.stack([np.concatenate([np.linalg.qr(rng.normal(size=(3, 3)))[0] * 1.0,
+                                      rng.normal(size=(3, 1)) * 3], 1) for _ in range(V)])
+    for k in range(V):
+        if np.linalg.det(poses[k, :, :3]) < 0:
+            poses[k, :, :3] *= -1
+    dev = torch.device("cuda:0")
+    P = torch.from_numpy(poses.copy()).to(dev)
+    m = torch.zeros(V, 6, dtype=torch.float64, device=dev)
+    v = torch.zeros_like(m)
+    step = torch.zeros(1, dtype=torch.int32, device=dev)
+    fixed = torch.from_numpy((np.arange(V) % 5 == 0).astype(np.uint8)).to(dev)
+    sov = torch.from_numpy((np.arange(V) % 3).astype(np.int32)).to(dev)
+    lrs = np.array([1e-2, 3e-3, 0.5])
+    lr = torch.from_numpy(lrs).to(dev)
+    ref_p, ref_m, ref_v = poses.copy(), np.zeros((V, 6)), np.zeros((V, 6))
+    st = torch.cuda.current_stream().cuda_stream
+    for s in range(1, 6):
+        g = rng.normal(size=(V, 6)) * 10 ** rng.uniform(-3, 2, size=(V, 1))
+        G = torch.from_numpy(g).to(dev)
+        _lib.pose_step(P, m, v, G, V, sov, fixed, lr, 0.9, 0.999, 1e-8, step, st)
+        ref_p, ref_m, ref_v = oloop.adam_se3_step(ref_p, ref_m, ref_v, g, s, lrs,
+                                                  fixed=(np.arange(V) % 5 == 0),
+                                                  scene_of_view=np.arange(V) % 3)
+    torch.cuda.synchronize()
+    assert int(step.item()) == 5
+    assert np.abs(P.cpu().numpy() - ref_p).max() < 1e-12
+    assert np.abs(m.cpu().numpy() - ref_m).max() < 1e-12
+    assert rel_norm_err(v.cpu().numpy(), ref_v) < 1e-12
+
+
+def test_schedule_matches_oracle(gpu):
+    from paper_2607_00579_amd import _lib
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream().cuda_stream
+    for s in (0, 1, 24, 25, 26, 500, 999, 1000, 1500, 1999):
+        step = torch.tensor([s], dtype=torch.int32, device=dev)
+        lam = torch.zeros(3, dtype=torch.float32, device=dev)
+        lr = torch.zeros(3, dtype=torch.float64, device=dev)
+        _lib.schedule(step, 3, 10.0, 6.0, 1000, 3e-3, 25, 2000, lam, lr, st)
+        torch.cuda.synchronize()
+        assert np.allclose(lam.cpu().numpy(), oloop.clamp_lambda(s), rtol=1e-6)
+        assert np.allclose(lr.cpu().numpy(), oloop.learning_rate(s), rtol=1e-12)

@@ -217,3 +217,13 @@ def test_empty_target_map_gives_no_valid_cost():
     assert r["n"][1] == 0 and r["L"][1] == 0.0
     assert np.all(r["grad"] == 0.0)
     assert np.isclose(r["loss"][0], 9.5)
+
+
+def test_golden_trajectories_match_generator():
+    """The stored oracle trajectories were produced from the current inputs."""
+    import os
+    from tests.golden.make_golden import input_checksum
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    for name in ("c1", "c2"):
+        g = np.load(os.path.join(here, f"{name}_trajectory.npz"), allow_pickle=False)
+        assert str(g["checksum"]) == input_checksum(make(name)), name
