@@ -213,15 +213,22 @@ __device__ inline void do_tile(int64_t t, const uint2* __restrict__ records,
     const uint32_t* texj = tex + pd.tex_off;
     const uint2* rec = records + tl.rec;
     Acc a{0, 0, 0, 0, 0, 0, 0, 0};
-    uint2 r[P];
+    // two residuals in flight per thread (about 50 VGPRs, so the SIMD keeps
+    // eight waves to hide the record load and the dependent tap gather);
+    // unrolling all P would multiply the float64 live ranges
+    constexpr int U = P < 2 ? P : 2;
+#pragma unroll 1
+    for (int k0 = 0; k0 < P; k0 += U) {
+        uint2 r[U];
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const int idx = k * kBlock + tid;
-        r[k] = idx < tl.count ? rec[idx] : make_uint2(0u, 0u);
-    }
+        for (int k = 0; k < U; ++k) {
+            const int idx = (k0 + k) * kBlock + tid;
+            r[k] = idx < tl.count ? rec[idx] : make_uint2(0u, 0u);
+        }
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        residual<FMT>(r[k], k * kBlock + tid < tl.count, pd, texj, lut, delta, zmin, a);
+        for (int k = 0; k < U; ++k)
+            residual<FMT>(r[k], (k0 + k) * kBlock + tid < tl.count, pd, texj, lut, delta, zmin,
+                          a);
     }
     double s[8] = {a.S, (double)a.n, a.g0, a.g1, a.g2, a.g3, a.g4, a.g5};
 #pragma unroll
