@@ -72,27 +72,47 @@ def cpu_baseline(prob, budget_s: float = 15.0):
     the smallest-resolution scenes until the budget is used."""
     import numpy as np
     from oracle import cost as ocost
-    px = prob.width.astype(np.int64) * prob.height
-    scene = int(prob.scene_of_view[int(np.argmin(px))])
-    views = np.flatnonzero(prob.scene_of_view == scene)
-    pair_ids = np.flatnonzero(prob.scene_of_pair == scene)
-    op = ocost.OracleProblem(prob, views=[int(x) for x in views])
     params = ocost.CostParams()
-    done_res, t_used, n_pairs = 0, 0.0, 0
-    t0 = time.perf_counter()
-    for d in pair_ids:
-        op.direction(int(d), prob.poses_init, 10.0, params)
-        done_res += int(op.pts[int(prob.pairs[d, 0])][0].size)
-        n_pairs += 1
-        t_used = time.perf_counter() - t0
+    n_scenes = int(prob.scene_of_view.max()) + 1
+    px = np.array([int(prob.width[np.flatnonzero(prob.scene_of_view == s)[0]])
+                   * int(prob.height[np.flatnonzero(prob.scene_of_view == s)[0]])
+                   for s in range(n_scenes)])
+    done_res, t_used, n_pairs, used = 0, 0.0, 0, []
+    # whole pairs of scenes in order of increasing image size (the oracle's
+    # distance transforms of the sampled views are set-up, not timed)
+    for scene in np.argsort(px, kind="stable"):
+        scene = int(scene)
+        views = np.flatnonzero(prob.scene_of_view == scene)
+        op = ocost.OracleProblem(prob, views=[int(x) for x in views])
+        used.append(f"{scene} ({views.size} views of {int(prob.width[views[0]])}x"
+                    f"{int(prob.height[views[0]])})")
+        for d in np.flatnonzero(prob.scene_of_pair == scene):
+            t0 = time.perf_counter()
+            op.direction(int(d), prob.poses_init, 10.0, params)
+            t_used += time.perf_counter() - t0
+            done_res += int(op.pts[int(prob.pairs[d, 0])][0].size)
+            n_pairs += 1
+            if t_used > budget_s:
+                break
         if t_used > budget_s:
             break
     rate = done_res / t_used
-    w, h = int(prob.width[views[0]]), int(prob.height[views[0]])
     return {"value": rate, "unit": "residual+grad evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_pairs} directed pairs ({done_res} residuals) of scene {scene} "
-                      f"({views.size} views of {w}x{h}); cost + analytic gradient per pair, "
-                      f"float64 NumPy, one process, {t_used:.1f} s"}
+            "sample": f"{n_pairs} directed pairs ({done_res} residuals) of scenes "
+                      f"{', '.join(used)}; cost + analytic gradient per pair, float64 NumPy, "
+                      f"one process, {t_used:.1f} s of evaluation"}
+
+
+def copy_calibration(nbytes: int, reps: int):
+    """A plain device copy of known size, to scale the HBM byte counters."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copied {nbytes} bytes {reps} times")
 
 
 def autograd_baseline(prob, dtf_flat, lam, steps: int, device):
@@ -158,11 +178,16 @@ def main():
     ap.add_argument("--options", default=None, help="JSON plan options (skips the autotuner)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only eager fused-kernel launches (for profilers)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see DESIGN.md for how it would shard)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, args.steps)
+        return
 
     import numpy as np
     import torch

@@ -1,7 +1,7 @@
-// Per-iteration hot path on gfx950: relative poses, the fused residual +
-// adjoint kernel, and the float64 reductions to per-pair, per-pose and
-// per-scene sums (paper Eqs. pi, L, L_ij, d_ij; supplementary Alg. 3 and
-// Sec. A1.2 "Per-iteration kernels").
+// Per-iteration hot path on gfx950: relative poses and the fused residual +
+// adjoint kernel (paper Eqs. pi, L, L_ij, d_ij; supplementary Alg. 3 and
+// Sec. A1.2 "Per-iteration kernels").  The float64 reductions above the tile
+// partials are in reduce.hip.
 //
 // Fused kernel, per residual (source edge pixel p = (u, v) with depth Z of
 // view i, directed pair i -> j):
@@ -74,20 +74,14 @@ __global__ __launch_bounds__(256) void pair_setup_kernel(
         M[3 * r + 2] = R[3 * r + 2] - R[3 * r + 0] * (cxi / fxi) - R[3 * r + 1] * (cyi / fyi);
     }
     PairDesc o;
-    for (int c = 0; c < 3; ++c) {
-        o.B[0 + c] = fxj * M[0 + c] + cxj * M[6 + c];
-        o.B[3 + c] = fyj * M[3 + c] + cyj * M[6 + c];
-        o.B[6 + c] = M[6 + c];
-    }
-    o.c[0] = fxj * t[0] + cxj * t[2];
-    o.c[1] = fyj * t[1] + cyj * t[2];
-    o.c[2] = t[2];
+    for (int k = 0; k < 9; ++k) o.M[k] = M[k];
+    for (int k = 0; k < 3; ++k) o.t[k] = t[k];
+    o.fxd = fxj;
+    o.fyd = fyj;
+    o.cxd = cxj;
+    o.cyd = cyj;
     o.fx = (float)fxj;
     o.fy = (float)fyj;
-    o.ifx = (float)(1.0 / fxj);
-    o.ify = (float)(1.0 / fyj);
-    o.cxn = (float)(cxj / fxj);
-    o.cyn = (float)(cyj / fyj);
     o.wlim = (double)(wh[2 * j + 0] - 1);
     o.hlim = (double)(wh[2 * j + 1] - 1);
     const float lam = lambda[st.scene];
@@ -134,6 +128,20 @@ struct Taps<2> {
     }
 };
 
+// float32 quads: the four float32 taps of the cell in one 16-byte gather
+template <>
+struct Taps<3> {
+    __device__ static inline void load(const uint32_t* __restrict__ tex, int idx, int /*W*/,
+                                       const float* /*lut*/, float& d00, float& d10, float& d01,
+                                       float& d11) {
+        const float4 q = reinterpret_cast<const float4*>(tex)[idx];
+        d00 = q.x;
+        d10 = q.y;
+        d01 = q.z;
+        d11 = q.w;
+    }
+};
+
 // per-thread sums: every float32 residual term is added in float64 (the
 // pose-gradient sums cancel strongly, up to a few hundred in
 // sum |term| / |sum|), the valid count in integers
@@ -151,13 +159,19 @@ __device__ inline void residual(const uint2 rec, bool active, const PairDesc& pd
     const double u = (double)(rec.x & 0xffffu);
     const double v = (double)(rec.x >> 16);
     const double Z = (double)__uint_as_float(rec.y);
-    const double hx = fma(Z, fma(pd.B[0], u, fma(pd.B[1], v, pd.B[2])), pd.c[0]);
-    const double hy = fma(Z, fma(pd.B[3], u, fma(pd.B[4], v, pd.B[5])), pd.c[1]);
-    const double hz = fma(Z, fma(pd.B[6], u, fma(pd.B[7], v, pd.B[8])), pd.c[2]);
-    const double rzd = 1.0 / hz;
-    const double upd = hx * rzd;
-    const double vpd = hy * rzd;
-    const bool valid = active && (hz > zmin) && (upd >= 0.0) && (upd < pd.wlim) && (vpd >= 0.0) &&
+    const double Xx = fma(Z, fma(pd.M[0], u, fma(pd.M[1], v, pd.M[2])), pd.t[0]);
+    const double Xy = fma(Z, fma(pd.M[3], u, fma(pd.M[4], v, pd.M[5])), pd.t[1]);
+    const double Xz = fma(Z, fma(pd.M[6], u, fma(pd.M[7], v, pd.M[8])), pd.t[2]);
+    // 1 / z: hardware reciprocal refined by one Newton step, which squares its
+    // relative error (exact when z is a power of two; the parity tests hold
+    // the valid counts and cells to the float64 oracle); z <= 0, inf or NaN
+    // end as invalid
+    double rzd = __builtin_amdgcn_rcp(Xz);
+    rzd = fma(rzd, fma(-Xz, rzd, 1.0), rzd);
+    const double xnd = Xx * rzd, ynd = Xy * rzd;          // normalised target coordinates
+    const double upd = fma(pd.fxd, xnd, pd.cxd);
+    const double vpd = fma(pd.fyd, ynd, pd.cyd);
+    const bool valid = active && (Xz > zmin) && (upd >= 0.0) && (upd < pd.wlim) && (vpd >= 0.0) &&
                        (vpd < pd.hlim);
     const double fx0 = floor(upd), fy0 = floor(vpd);
     // invalid residuals may carry inf/NaN coordinates: zero everything that
@@ -165,7 +179,9 @@ __device__ inline void residual(const uint2 rec, bool active, const PairDesc& pd
     const float al = valid ? (float)(upd - fx0) : 0.0f;
     const float be = valid ? (float)(vpd - fy0) : 0.0f;
     const int idx = valid ? ((int)fy0 * pd.width + (int)fx0) : 0;
-    const float up = (float)upd, vp = (float)vpd, rz = (float)rzd;
+    const float xn = valid ? (float)xnd : 0.0f;
+    const float yn = valid ? (float)ynd : 0.0f;
+    const float rzv = valid ? (float)rzd : 0.0f;
     float d00, d10, d01, d11;
     Taps<FMT>::load(texj, idx, pd.width, lut, d00, d10, d01, d11);
     const float e0 = d10 - d00, e1 = d11 - d01;
@@ -174,7 +190,7 @@ __device__ inline void residual(const uint2 rec, bool active, const PairDesc& pd
     const float gv = fmaf(al, f1 - f0, f0);
     const float D = fmaf(be, gv, fmaf(al, e0, d00));
     const bool unclamped = D < pd.lambda;
-    const float dh = unclamped ? D : pd.lambda;
+    const float dh = fminf(D, pd.lambda);      // D is finite here (masked cell)
     const bool quad = dh <= delta;
     float rho = quad ? 0.5f * dh * dh : delta * (dh - 0.5f * delta);
     float drho = unclamped ? (quad ? dh : delta) : 0.0f;
@@ -182,10 +198,7 @@ __device__ inline void residual(const uint2 rec, bool active, const PairDesc& pd
     drho = valid ? drho : 0.0f;
     const float Au = drho * gu * pd.fx;
     const float Av = drho * gv * pd.fy;
-    const float xn = valid ? fmaf(up, pd.ifx, -pd.cxn) : 0.0f;
-    const float yn = valid ? fmaf(vp, pd.ify, -pd.cyn) : 0.0f;
     const float w = -fmaf(Au, xn, Av * yn);
-    const float rzv = valid ? rz : 0.0f;
     a.S += (double)rho;
     a.n += valid ? 1 : 0;
     a.g0 += (double)(Au * rzv);
@@ -281,90 +294,11 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
     }
 }
 
-// ---------------------------------------------------------------------------
-// float64 reductions
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void reduce_pairs_kernel(
-    const Partial* __restrict__ partials, const PairStatic* __restrict__ ps, int32_t D,
-    int32_t norm_mode, double* __restrict__ pair_sum, double* __restrict__ pair_w,
-    double* __restrict__ pair_cost, int32_t* __restrict__ pair_valid,
-    double* __restrict__ pair_grad, int32_t* __restrict__ status) {
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= D) return;
-    const PairStatic st = ps[d];
-    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < st.n_tiles; ++k) {
-        const Partial pt = partials[st.first_tile + k];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) s[c] += pt.v[c];
-    }
-    const double den = norm_mode == 0 ? s[1] : (double)st.n_src;
-    const double L = den > 0 ? s[0] / den : 0.0;
-    const double w = den > 0 ? (double)st.scale / den : 0.0;
-    if (!isfinite(s[0]) || !isfinite(s[2]) || !isfinite(s[5])) atomicOr(status, 1);
-#pragma unroll
-    for (int c = 0; c < 8; ++c) pair_sum[8 * d + c] = s[c];
-    pair_w[d] = w;
-    if (pair_cost) pair_cost[d] = L;
-    if (pair_valid) pair_valid[d] = (int32_t)s[1];
-    if (pair_grad) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) pair_grad[6 * d + c] = s[2 + c];
-    }
-}
-
-__global__ __launch_bounds__(256) void reduce_views_kernel(
-    const double* __restrict__ pair_sum, const double* __restrict__ pair_w,
-    const double* __restrict__ rel, const PairStatic* __restrict__ ps,
-    const int32_t* __restrict__ in_ptr, const int32_t* __restrict__ in_idx,
-    const int32_t* __restrict__ out_ptr, const int32_t* __restrict__ out_idx,
-    const int32_t* __restrict__ scene_of_view, const int32_t* __restrict__ scene_ptr,
-    const int32_t* __restrict__ scene_pairs, int32_t V, int32_t S, int32_t norm_mode,
-    const double* __restrict__ upstream, double* __restrict__ grad, double* __restrict__ loss) {
-    const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (loss && id < S) {
-        double L = 0.0;
-        for (int k = scene_ptr[id]; k < scene_ptr[id + 1]; ++k) {
-            const int d = scene_pairs[k];
-            const PairStatic st = ps[d];
-            const double den = norm_mode == 0 ? pair_sum[8 * d + 1] : (double)st.n_src;
-            if (den > 0) L += (double)st.scale * (pair_sum[8 * d + 0] / den);
-        }
-        loss[id] = L;
-    }
-    if (!grad || id >= V) return;
-    double g[6] = {0, 0, 0, 0, 0, 0};
-    // pairs whose target is this view: g += w G
-    for (int k = in_ptr[id]; k < in_ptr[id + 1]; ++k) {
-        const int d = in_idx[k];
-        const double w = pair_w[d];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) g[c] += w * pair_sum[8 * d + 2 + c];
-    }
-    // pairs whose source is this view: g += -w Ad(T_ji)^T G
-    //   Ad^T (G_r, G_w) = (R^T G_r, R^T (G_w - t x G_r))
-    for (int k = out_ptr[id]; k < out_ptr[id + 1]; ++k) {
-        const int d = out_idx[k];
-        const double w = pair_w[d];
-        const double* R = rel + 12 * d;
-        const double* t = R + 9;
-        const double* G = pair_sum + 8 * d + 2;
-        const double c0 = G[3] - (t[1] * G[2] - t[2] * G[1]);
-        const double c1 = G[4] - (t[2] * G[0] - t[0] * G[2]);
-        const double c2 = G[5] - (t[0] * G[1] - t[1] * G[0]);
-        for (int r = 0; r < 3; ++r) {
-            g[r] -= w * (R[0 + r] * G[0] + R[3 + r] * G[1] + R[6 + r] * G[2]);
-            g[3 + r] -= w * (R[0 + r] * c0 + R[3 + r] * c1 + R[6 + r] * c2);
-        }
-    }
-    const double up = upstream ? upstream[scene_of_view[id]] : 1.0;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) grad[6 * id + c] = up * g[c];
-}
-
 template <int FMT, int P>
 void launch_cost_kernel(Plan& p, hipStream_t s) {
-    const uint32_t* tex = (FMT == 2) ? p.tex.p : reinterpret_cast<const uint32_t*>(p.tex_f32.p);
+    const uint32_t* tex = FMT == 2   ? p.tex.p
+                          : FMT == 3 ? reinterpret_cast<const uint32_t*>(p.tex_q32.p)
+                                     : reinterpret_cast<const uint32_t*>(p.tex_f32.p);
     const int nq = p.n_xcd_queues;
     unsigned grid;
     if (p.opt.persistent == 1) {
@@ -411,23 +345,16 @@ void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss
         if (timed) EPO_HIP(hipEventRecord(p.ev0, s));
         if (p.opt.texture_format == 2)
             launch_cost_fmt<2>(p, s);
+        else if (p.opt.texture_format == 3)
+            launch_cost_fmt<3>(p, s);
         else
             launch_cost_fmt<1>(p, s);
         if (timed) {
             EPO_HIP(hipEventRecord(p.ev1, s));
             p.timed_once = true;
         }
-        reduce_pairs_kernel<<<(unsigned)ceil_div(p.D, 256), 256, 0, s>>>(
-            p.partials.p, p.pair_static.p, p.D, p.params.norm_mode, p.pair_sum.p, p.pair_w.p,
-            pair_cost, pair_valid, pair_grad, p.status.p);
-        EPO_CHECK_LAUNCH();
     }
-    const int n = std::max(p.V, p.S);
-    reduce_views_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(
-        p.pair_sum.p, p.pair_w.p, p.pair_rel.p, p.pair_static.p, p.view_in_ptr.p, p.view_in_idx.p,
-        p.view_out_ptr.p, p.view_out_idx.p, p.scene_of_view_d.p, p.scene_ptr.p, p.scene_pairs.p,
-        p.V, p.S, p.params.norm_mode, upstream, grad, loss);
-    EPO_CHECK_LAUNCH();
+    launch_reductions(p, loss, pair_cost, pair_valid, pair_grad, grad, upstream, s);
 }
 
 }  // namespace epo

@@ -87,23 +87,23 @@ struct DevBuf {
 
 // ---------------------------------------------------------------------------
 // per-iteration pair descriptor consumed by the fused kernel
-//   h = Z * B (u, v, 1)^T + c ; u' = h_x / h_z ; v' = h_y / h_z
-//   B = K_j R_ji K_i^-1, c = K_j t_ji (float64: the projected coordinate
-//   decides the bilinear cell, and float32 coordinates of a 500-1000 px image
-//   flip cells often enough to move pose gradients by a few 1e-4)
+//   X' = Z M (u, v, 1)^T + t  (target camera frame),  M = R_ji K_i^-1, t = t_ji
+//   u' = fx_j X'_x / X'_z + cx_j,  v' = fy_j X'_y / X'_z + cy_j
+// (float64: the projected coordinate decides the bilinear cell, and float32
+// coordinates of a 500-1000 px image flip cells often enough to move pose
+// gradients by a few 1e-4)
 // ---------------------------------------------------------------------------
 struct alignas(16) PairDesc {
-    double B[9];
-    double c[3];
-    double wlim, hlim;     // W_j - 1, H_j - 1
-    float fx, fy;          // target focal lengths (chain rule)
-    float ifx, ify;        // 1 / fx_j, 1 / fy_j
-    float cxn, cyn;        // cx_j / fx_j, cy_j / fy_j
-    float lambda;          // clamp of the pair's scene
-    int32_t width;         // W_j (texture row stride)
-    int64_t tex_off;       // element offset of view j in the texture
+    double M[9];
+    double t[3];
+    double fxd, fyd, cxd, cyd;   // target intrinsics
+    double wlim, hlim;           // W_j - 1, H_j - 1
+    float fx, fy;                // target focal lengths (chain rule, float32)
+    float lambda;                // clamp of the pair's scene
+    int32_t width;               // W_j (texture row stride)
+    int64_t tex_off;             // pixel offset of view j in the texture
 };
-static_assert(sizeof(PairDesc) == 160, "PairDesc layout");
+static_assert(sizeof(PairDesc) == 176, "PairDesc layout");
 
 // static per-pair data (plan lifetime)
 struct PairStatic {
@@ -146,7 +146,8 @@ struct Plan {
     // device, plan lifetime
     DevBuf<uint64_t> records;             // (u | v << 16) | (Z bits << 32)
     DevBuf<uint32_t> tex;                 // texture (f32 bits or u8 quads), total_px
-    DevBuf<float> tex_f32;                // f32 texture when both kept
+    DevBuf<float> tex_f32;                // float32 sqrt(d2) per pixel
+    DevBuf<float4> tex_q32;               // float32 taps of the cell at each pixel
     DevBuf<int32_t> scene_of_view_d;
     DevBuf<float> K_d;                    // V x 4
     DevBuf<int32_t> wh_d;                 // V x 2
@@ -192,6 +193,9 @@ void build_tiles(Plan& p, hipStream_t stream);
 void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss,
                  double* pair_cost, int32_t* pair_valid, double* pair_grad, double* grad,
                  const double* upstream, hipStream_t stream);
+void launch_reductions(Plan& p, double* loss, double* pair_cost, int32_t* pair_valid,
+                       double* pair_grad, double* grad, const double* upstream,
+                       hipStream_t stream);
 void launch_pose_step(double* poses, double* m, double* v, const double* grad, int32_t n_views,
                       const int32_t* scene_of_view, const uint8_t* fixed, const double* lr,
                       double b1, double b2, double eps, int32_t* step, hipStream_t stream);

@@ -100,7 +100,8 @@ __global__ __launch_bounds__(256) void texture_kernel(const int32_t* __restrict_
                                                       const int64_t* __restrict__ view_off,
                                                       const int32_t* __restrict__ wh,
                                                       uint32_t* __restrict__ q8,
-                                                      float* __restrict__ f32) {
+                                                      float* __restrict__ f32,
+                                                      float4* __restrict__ q32) {
     const int v = blockIdx.y;
     const int W = wh[2 * v], H = wh[2 * v + 1];
     const int64_t n = (int64_t)W * H, base = view_off[v];
@@ -109,6 +110,14 @@ __global__ __launch_bounds__(256) void texture_kernel(const int32_t* __restrict_
         const int y = (int)(i / W), x = (int)(i - (int64_t)y * W);
         const int32_t a = d2[base + i];
         if (f32) f32[base + i] = sqrtf((float)a);
+        if (q32) {
+            // the right column / bottom row of a view repeat their own pixel:
+            // no valid sample ever uses those cells
+            const int64_t ix = x + 1 < W ? 1 : 0, iy = y + 1 < H ? W : 0;
+            q32[base + i] = make_float4(sqrtf((float)a), sqrtf((float)d2[base + i + ix]),
+                                        sqrtf((float)d2[base + i + iy]),
+                                        sqrtf((float)d2[base + i + iy + ix]));
+        }
         if (q8) {
             const bool rx = x + 1 < W, dy = y + 1 < H;
             const uint32_t t00 = (uint32_t)min(a, 255);
@@ -128,7 +137,7 @@ void upload(DevBuf<T>& b, const std::vector<T>& h, hipStream_t s) {
 }
 
 void validate_options(const epo_plan_options& o) {
-    EPO_REQUIRE(o.texture_format == 1 || o.texture_format == 2, "texture_format must be 1 or 2");
+    EPO_REQUIRE(o.texture_format >= 1 && o.texture_format <= 3, "texture_format must be 1, 2 or 3");
     EPO_REQUIRE(o.points_per_thread == 1 || o.points_per_thread == 2 || o.points_per_thread == 4 ||
                     o.points_per_thread == 8 || o.points_per_thread == 16,
                 "points_per_thread must be 1, 2, 4, 8 or 16");
@@ -210,12 +219,14 @@ void build_tiles(Plan& p, hipStream_t s) {
 void build_texture(Plan& p, const int32_t* d2, hipStream_t s) {
     const bool q8 = p.params.lambda_max <= kQ8LambdaMax;
     p.tex_f32.alloc((size_t)p.total_px);
+    p.tex_q32.alloc((size_t)p.total_px);
     if (q8) p.tex.alloc((size_t)p.total_px);
     int64_t maxWH = 1;
     for (int v = 0; v < p.V; ++v) maxWH = std::max<int64_t>(maxWH, (int64_t)p.width[v] * p.height[v]);
     const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(maxWH, 256), 1024);
     texture_kernel<<<dim3(gx, p.V), 256, 0, s>>>(d2, p.view_offset_d.p, p.wh_d.p,
-                                                 q8 ? p.tex.p : nullptr, p.tex_f32.p);
+                                                 q8 ? p.tex.p : nullptr, p.tex_f32.p,
+                                                 p.tex_q32.p);
     EPO_CHECK_LAUNCH();
 }
 
@@ -478,7 +489,7 @@ extern "C" epo_status epo_plan_autotune(epo_plan plan, const double* poses, cons
         EPO_HIP(hipEventCreate(&b));
         float best = 1e30f;
         epo_plan_options best_o = p.opt;
-        const int fmts[2] = {1, 2};
+        const int fmts[3] = {1, 2, 3};
         const int ppts[4] = {2, 4, 8, 16};
         const int orders[2] = {1, 2};
         const int pers[2] = {1, 2};

