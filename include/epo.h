@@ -140,7 +140,8 @@ EPO_API epo_status epo_build_distance_fields(const uint8_t* edge_maps, const int
  *                   0..S-1 with every scene non-empty; NULL = one scene
  *   view_offset     (host) int64 [V] element offsets of the packed images
  *   edge_maps       uint8 packed edge maps (nonzero = edge)
- *   depth           float32 packed depth maps (read at edge pixels only)
+ *   depth           float32 packed depth maps (read at edge pixels only; must
+ *                   be finite there, EPO_ERR_INVALID_ARG otherwise)
  *   d2              int32 packed squared distances (epo_build_distance_fields)
  *   pairs           (host) int32 [n_pairs][2] directed pairs (source, target),
  *                   both views of a pair in the same scene; the loss of a

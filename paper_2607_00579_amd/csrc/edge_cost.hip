@@ -82,8 +82,8 @@ __global__ __launch_bounds__(256) void pair_setup_kernel(
     o.cyd = cyj;
     o.fx = (float)fxj;
     o.fy = (float)fyj;
-    o.wlim = (double)(wh[2 * j + 0] - 1);
-    o.hlim = (double)(wh[2 * j + 1] - 1);
+    o.wcells = wh[2 * j + 0] - 1;
+    o.hcells = wh[2 * j + 1] - 1;
     const float lam = lambda[st.scene];
     if (!(lam <= lambda_max)) atomicOr(status, 2);
     o.lambda = lam;
@@ -171,14 +171,19 @@ __device__ inline void residual(const uint2 rec, bool active, const PairDesc& pd
     const double xnd = Xx * rzd, ynd = Xy * rzd;          // normalised target coordinates
     const double upd = fma(pd.fxd, xnd, pd.cxd);
     const double vpd = fma(pd.fyd, ynd, pd.cyd);
-    const bool valid = active && (Xz > zmin) && (upd >= 0.0) && (upd < pd.wlim) && (vpd >= 0.0) &&
-                       (vpd < pd.hlim);
+    // 0 <= u' < W - 1 holds exactly when the cell column floor(u') lies in
+    // [0, W - 2]: one unsigned compare of the (saturating) integer cell index.
+    // Depth is finite (checked when the plan is built), so u' is NaN only if
+    // z is, and then z > z_min already fails.
     const double fx0 = floor(upd), fy0 = floor(vpd);
+    const int x0 = (int)fx0, y0 = (int)fy0;
+    const bool valid = active && (Xz > zmin) && ((unsigned)x0 < (unsigned)pd.wcells) &&
+                       ((unsigned)y0 < (unsigned)pd.hcells);
     // invalid residuals may carry inf/NaN coordinates: zero everything that
     // reaches a product with a zero weight
     const float al = valid ? (float)(upd - fx0) : 0.0f;
     const float be = valid ? (float)(vpd - fy0) : 0.0f;
-    const int idx = valid ? ((int)fy0 * pd.width + (int)fx0) : 0;
+    const int idx = valid ? (y0 * pd.width + x0) : 0;
     const float xn = valid ? (float)xnd : 0.0f;
     const float yn = valid ? (float)ynd : 0.0f;
     const float rzv = valid ? (float)rzd : 0.0f;
@@ -230,8 +235,11 @@ __device__ inline void do_tile(int64_t t, const uint2* __restrict__ records,
     // eight waves to hide the record load and the dependent tap gather);
     // unrolling all P would multiply the float64 live ranges
     constexpr int U = P < 2 ? P : 2;
+    // the trip count follows the tile's own size (uniform over the
+    // workgroup), so a pair's short last tile costs only its residuals
+    const int rows = (tl.count + kBlock - 1) / kBlock;
 #pragma unroll 1
-    for (int k0 = 0; k0 < P; k0 += U) {
+    for (int k0 = 0; k0 < rows; k0 += U) {
         uint2 r[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {

@@ -97,13 +97,13 @@ struct alignas(16) PairDesc {
     double M[9];
     double t[3];
     double fxd, fyd, cxd, cyd;   // target intrinsics
-    double wlim, hlim;           // W_j - 1, H_j - 1
     float fx, fy;                // target focal lengths (chain rule, float32)
     float lambda;                // clamp of the pair's scene
     int32_t width;               // W_j (texture row stride)
+    int32_t wcells, hcells;      // W_j - 1, H_j - 1: bilinear cells per row / column
     int64_t tex_off;             // pixel offset of view j in the texture
 };
-static_assert(sizeof(PairDesc) == 176, "PairDesc layout");
+static_assert(sizeof(PairDesc) == 160, "PairDesc layout");
 
 // static per-pair data (plan lifetime)
 struct PairStatic {

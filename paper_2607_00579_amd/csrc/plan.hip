@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void scatter_records_kernel(
     const uint8_t* __restrict__ edge, const float* __restrict__ depth,
     const int64_t* __restrict__ view_off, const int32_t* __restrict__ wh,
     const int64_t* __restrict__ tile_first, int V, const int64_t* __restrict__ tile_rec,
-    uint64_t* __restrict__ records) {
+    uint64_t* __restrict__ records, int32_t* __restrict__ bad_depth) {
     __shared__ int wave_cnt[4];
     const int64_t t = blockIdx.x;
     const int v = view_of(tile_first, V, t);
@@ -90,7 +90,9 @@ __global__ __launch_bounds__(256) void scatter_records_kernel(
     int base = 0;
     for (int k = 0; k < wave; ++k) base += wave_cnt[k];
     if (e) {
-        const uint32_t z = __float_as_uint(depth[pix]);
+        const float zf = depth[pix];
+        if (!isfinite(zf)) atomicOr(bad_depth, 1);
+        const uint32_t z = __float_as_uint(zf);
         records[tile_rec[t] + base + below] =
             (uint64_t)((uint32_t)x | ((uint32_t)y << 16)) | ((uint64_t)z << 32);
     }
@@ -251,8 +253,6 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         EPO_REQUIRE(n_pairs == 0 || pairs, "null pair list");
         hipStream_t s = as_stream(stream);
         std::unique_ptr<Plan> p(new Plan());
-        EPO_HIP(hipGetDevice(&p->device));
-        EPO_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
         p->V = n_views;
         p->D = n_pairs;
         p->params = params ? *params : epo_cost_params{1.0f, 1e-4f, 0, 10.0f};
@@ -312,6 +312,10 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
             throw Failure{EPO_ERR_UNSUPPORTED,
                           "texture_format 2 needs lambda_max <= 14.5 (saturated taps)"};
 
+        // every host-side check is done: from here on the device is used
+        EPO_HIP(hipGetDevice(&p->device));
+        EPO_HIP(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device));
+
         // ---- static device data
         std::vector<int32_t> wh(2 * (size_t)n_views);
         for (int v = 0; v < n_views; ++v) {
@@ -354,10 +358,17 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         DevBuf<int64_t> tile_rec_d;
         upload(tile_rec_d, tile_rec, s);
         p->records.alloc((size_t)std::max<int64_t>(acc, 1));
+        DevBuf<int32_t> bad_d;
+        bad_d.alloc(1);
+        EPO_HIP(hipMemsetAsync(bad_d.p, 0, sizeof(int32_t), s));
         scatter_records_kernel<<<(unsigned)n_ptiles, 256, 0, s>>>(
             edge_maps, depth, p->view_offset_d.p, p->wh_d.p, tile_first_d.p, n_views,
-            tile_rec_d.p, p->records.p);
+            tile_rec_d.p, p->records.p, bad_d.p);
         EPO_CHECK_LAUNCH();
+        int32_t bad = 0;
+        EPO_HIP(hipMemcpyAsync(&bad, bad_d.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        EPO_HIP(hipStreamSynchronize(s));
+        EPO_REQUIRE(bad == 0, "depth is not finite at an edge pixel");
 
         // ---- textures
         build_texture(*p, d2, s);

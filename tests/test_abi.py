@@ -66,6 +66,58 @@ def test_version_and_error_paths(lib):
     lib.build_distance_fields(None, None, None, None, 0, None, None, None)
 
 
+def _host_only():
+    """These calls pass placeholder device pointers and must be rejected on
+    the host; never run them where a GPU could be reached."""
+    from tests.conftest import gpu_available
+    if gpu_available():
+        pytest.skip("host-validation test: runs only without a GPU")
+
+
+def _plan_args(**over):
+    a = dict(n_views=2, width=np.array([40, 40], np.int32), height=np.array([30, 30], np.int32),
+             K=np.tile(np.array([32, 32, 19.5, 14.5], np.float32), 2),
+             scene_of_view=np.array([0, 0], np.int32), view_offset=np.array([0, 1200], np.int64),
+             edge_maps=1, depth=1, d2=1, pairs=np.array([[0, 1], [1, 0]], np.int32), n_pairs=2,
+             params=None, options=None, stream=None)
+    a.update(over)
+    return a
+
+
+@pytest.mark.parametrize("over,needle", [
+    (dict(width=np.array([40, 1], np.int32)), "side"),
+    (dict(width=np.array([40, 16385], np.int32)), "side"),
+    (dict(pairs=np.array([[0, 2], [1, 0]], np.int32)), "out of range"),
+    (dict(scene_of_view=np.array([0, 1], np.int32)), "different scenes"),
+    (dict(scene_of_view=np.array([0, 2], np.int32), pairs=np.array([[0, 0], [1, 1]], np.int32)),
+     "without gaps"),
+    (dict(K=np.array([32, 32, 19.5, 14.5, -1, 32, 19.5, 14.5], np.float32)), "focal"),
+    (dict(view_offset=np.array([0, -5], np.int64)), "negative offset"),
+    (dict(n_views=0), "n_views"),
+    (dict(edge_maps=None), "null"),
+])
+def test_plan_create_rejects_bad_arguments_on_host(lib, over, needle):
+    _host_only()
+    with pytest.raises(lib.EpoError) as e:
+        lib.plan_create(**_plan_args(**over))
+    assert e.value.status == lib.ERR_INVALID_ARG
+    assert needle in str(e.value), str(e.value)
+
+
+def test_plan_create_rejects_unsupported_texture(lib):
+    _host_only()
+    with pytest.raises(lib.EpoError) as e:
+        lib.plan_create(**_plan_args(params=lib.CostParams(1.0, 1e-4, 0, 20.0),
+                                     options=lib.PlanOptions(2, 4, 1, 2)))
+    assert e.value.status == lib.ERR_UNSUPPORTED
+    with pytest.raises(lib.EpoError) as e:
+        lib.plan_create(**_plan_args(options=lib.PlanOptions(4, 4, 1, 2)))
+    assert e.value.status == lib.ERR_INVALID_ARG
+    with pytest.raises(lib.EpoError) as e:
+        lib.plan_create(**_plan_args(options=lib.PlanOptions(1, 3, 1, 2)))
+    assert "points_per_thread" in str(e.value)
+
+
 def test_struct_layouts(lib):
     assert C.sizeof(lib.CostParams) == 16
     assert C.sizeof(lib.PlanOptions) == 16
