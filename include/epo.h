@@ -251,8 +251,46 @@ EPO_API epo_status epo_schedule(const int32_t* step, int32_t n_scenes, float lam
                         float* lambda_out, double* lr_out, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Pose-change signal and dual-phase convergence, per scene, on the device
+ * (paper Sec. 3 "Optimization Schedule", Alg. 2, Sec. A1.1):
+ *   dR_v = (180/pi) acos((tr(R_v R_v'^T) - 1)/2),
+ *   dt_v = (180/pi) acos(t_v . t_v' / (|t_v| |t_v'|))   (' = previous poses),
+ *   theta_95 = max(95th percentile of dR, 95th percentile of dt) over the
+ *   scene's views (linear interpolation at rank (n - 1) 0.95);
+ *   Converged(w, eps): the w moving averages (window w) of theta_95 ending at
+ *   the current step are all below eps.
+ * Phase 0 -> 1 when Converged(w1, eps1); phase 1 -> 2 (stopped) when
+ * Converged(w2, eps2) at a later step; both read the whole history.  In a
+ * captured iteration with convergence, a stopped scene gets learning rate 0,
+ * so its poses stay where they stopped.
+ *   params  (host) windows w1, w2 in [1, 64] and thresholds eps1, eps2 > 0;
+ *           NULL = the paper's (25, 0.5, 50, 0.1)
+ * epo_convergence_reset stores `poses` as the previous poses and clears the
+ * state; epo_convergence_update records one step (theta95 [n_scenes] float64
+ * and phase [n_scenes] int32 outputs are optional, device); scenes may have at
+ * most 4096 views.  epo_convergence_query copies the state to the host (phase,
+ * last theta_95, switch steps [n_scenes][2] (-1 = not yet), steps recorded;
+ * any may be NULL) and synchronises `stream`.
+ * ------------------------------------------------------------------------- */
+typedef struct epo_convergence_params {
+    int32_t w1;
+    float eps1;
+    int32_t w2;
+    float eps2;
+} epo_convergence_params;
+
+EPO_API epo_status epo_convergence_reset(epo_plan plan, const double* poses,
+                                         const epo_convergence_params* params, void* stream);
+EPO_API epo_status epo_convergence_update(epo_plan plan, const double* poses, double* theta95,
+                                          int32_t* phase, void* stream);
+EPO_API epo_status epo_convergence_query(epo_plan plan, int32_t* phase, double* theta_last,
+                                         int32_t* switch_steps, int32_t* steps, void* stream);
+
+/* ---------------------------------------------------------------------------
  * One whole iteration captured as a HIP graph owned by the plan:
- *   schedule -> fused cost + adjoint -> float64 reductions -> pose_step.
+ *   schedule -> fused cost + adjoint -> float64 reductions -> pose_step
+ *   [-> convergence update, when with_convergence != 0; call
+ *   epo_convergence_reset before the first replay].
  * The pointers given here are baked into the graph; replays read the current
  * contents of every buffer.  Capturing synchronises `stream` once.
  *   poses, adam_m, adam_v, step   as in epo_pose_step
@@ -267,7 +305,7 @@ EPO_API epo_status epo_iteration_capture(epo_plan plan, double* poses, double* a
                                  const uint8_t* fixed_mask, float lambda0, float lambda1,
                                  int32_t anneal_steps, double peak_lr, int32_t warmup,
                                  int32_t total, double beta1, double beta2, double eps,
-                                 void* stream);
+                                 int32_t with_convergence, void* stream);
 EPO_API epo_status epo_iteration_launch(epo_plan plan, void* stream);
 
 /* ---------------------------------------------------------------------------

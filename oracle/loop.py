@@ -84,3 +84,35 @@ def run(op: OracleProblem, poses0: np.ndarray, n_iters: int, params: CostParams 
     hist["final_poses"] = poses
     hist["m"], hist["v"] = m, v
     return hist
+
+
+def run_with_convergence(op: OracleProblem, poses0: np.ndarray, n_iters: int,
+                         params: CostParams = CostParams(), w1=25, eps1=0.5, w2=50, eps2=0.1):
+    """The loop of Alg. 2 with the pose-change signal and the dual-phase test
+    kept per scene: after every step theta_95 of each scene is recorded; a
+    scene whose phase-2 test has fired stops moving (its learning rate is 0
+    from the next step on), which is what ending the loop means for it."""
+    from .convergence import DualPhase, theta95
+    poses = poses0.copy()
+    m = np.zeros((op.V, 6))
+    v = np.zeros((op.V, 6))
+    sov = op.scene_of_view
+    dual = [DualPhase(w1, eps1, w2, eps2) for _ in range(op.n_scenes)]
+    hist = dict(loss=[], theta=[], phase=[])
+    for s in range(n_iters):
+        lr = np.array([0.0 if d.phase == 2 else learning_rate(s) for d in dual])
+        r = op.evaluate(poses, clamp_lambda(s), params)
+        new, m, v = adam_se3_step(poses, m, v, r["grad"], s + 1, lr, scene_of_view=sov)
+        th = []
+        for k, d in enumerate(dual):
+            views = np.flatnonzero(sov == k)
+            t = theta95(new[views], poses[views])
+            d.update(t)
+            th.append(t)
+        poses = new
+        hist["loss"].append(r["loss"].copy())
+        hist["theta"].append(th)
+        hist["phase"].append([d.phase for d in dual])
+    hist["final_poses"] = poses
+    hist["switch_steps"] = [list(d.switch_step) for d in dual]
+    return hist

@@ -54,7 +54,10 @@ _SIGS = {
     "epo_pose_step": [P, P, P, P, I32, P, P, P, F64, F64, F64, P, P],
     "epo_schedule": [P, I32, F32, F32, I32, F64, I32, I32, P, P, P],
     "epo_iteration_capture": [P, P, P, P, P, P, P, P, F32, F32, I32, F64, I32, I32, F64, F64,
-                              F64, P],
+                              F64, I32, P],
+    "epo_convergence_reset": [P, P, P, P],
+    "epo_convergence_update": [P, P, P, P, P],
+    "epo_convergence_query": [P, P, P, P, P, P],
     "epo_iteration_launch": [P, P],
     "epo_plan_autotune": [P, P, P, I32, C.POINTER(PlanOptions), P],
     "epo_plan_set_options": [P, C.POINTER(PlanOptions), P],
@@ -173,11 +176,35 @@ def schedule(step, n_scenes, lambda0, lambda1, anneal_steps, peak_lr, warmup, to
 
 
 def iteration_capture(plan, poses, m, v, step, loss, grad, fixed_mask, lambda0, lambda1,
-                      anneal_steps, peak_lr, warmup, total, beta1, beta2, eps, stream):
+                      anneal_steps, peak_lr, warmup, total, beta1, beta2, eps, with_convergence,
+                      stream):
     _check(load().epo_iteration_capture(plan, _ptr(poses), _ptr(m), _ptr(v), _ptr(step),
                                         _ptr(loss), _ptr(grad), _ptr(fixed_mask), lambda0,
                                         lambda1, anneal_steps, peak_lr, warmup, total, beta1,
-                                        beta2, eps, stream))
+                                        beta2, eps, 1 if with_convergence else 0, stream))
+
+
+class ConvergenceParams(C.Structure):
+    _fields_ = [("w1", C.c_int32), ("eps1", C.c_float), ("w2", C.c_int32), ("eps2", C.c_float)]
+
+
+def convergence_reset(plan, poses, params: ConvergenceParams | None, stream):
+    _check(load().epo_convergence_reset(plan, _ptr(poses),
+                                        C.byref(params) if params is not None else None, stream))
+
+
+def convergence_update(plan, poses, theta95, phase, stream):
+    _check(load().epo_convergence_update(plan, _ptr(poses), _ptr(theta95), _ptr(phase), stream))
+
+
+def convergence_query(plan, n_scenes, stream):
+    phase = np.zeros(n_scenes, np.int32)
+    theta = np.zeros(n_scenes, np.float64)
+    sw = np.zeros((n_scenes, 2), np.int32)
+    steps = np.zeros(n_scenes, np.int32)
+    _check(load().epo_convergence_query(plan, phase.ctypes.data, theta.ctypes.data,
+                                        sw.ctypes.data, steps.ctypes.data, stream))
+    return dict(phase=phase, theta_last=theta, switch_steps=sw, steps=steps)
 
 
 def iteration_launch(plan, stream):

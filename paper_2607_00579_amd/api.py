@@ -156,11 +156,21 @@ class EdgePlan:
 
     def capture_iteration(self, poses, m, v, step, loss, grad=None, fixed_mask=None,
                           lambda0=10.0, lambda1=6.0, anneal_steps=1000, peak_lr=3e-3, warmup=25,
-                          total=2000, beta1=0.9, beta2=0.999, eps=1e-8):
+                          total=2000, beta1=0.9, beta2=0.999, eps=1e-8, convergence=False):
         self._graph_refs = (poses, m, v, step, loss, grad, fixed_mask)   # keep buffers alive
         _lib.iteration_capture(self.handle, poses, m, v, step, loss, grad, fixed_mask, lambda0,
                                lambda1, anneal_steps, peak_lr, warmup, total, beta1, beta2, eps,
+                               convergence, _stream(self.device))
+
+    def convergence_reset(self, poses, w1=25, eps1=0.5, w2=50, eps2=0.1):
+        _lib.convergence_reset(self.handle, poses, _lib.ConvergenceParams(w1, eps1, w2, eps2),
                                _stream(self.device))
+
+    def convergence_update(self, poses, theta95=None, phase=None):
+        _lib.convergence_update(self.handle, poses, theta95, phase, _stream(self.device))
+
+    def convergence_query(self):
+        return _lib.convergence_query(self.handle, self.n_scenes, _stream(self.device))
 
     def launch_iteration(self):
         _lib.iteration_launch(self.handle, _stream(self.device))

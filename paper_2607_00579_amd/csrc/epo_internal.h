@@ -126,6 +126,16 @@ struct alignas(64) Partial {
     double v[8];
 };
 
+// per-scene convergence state (pose-change signal history and phase)
+constexpr int kConvRing = 128;          // >= 2 w - 1 for windows up to 64
+constexpr int kConvMaxViews = 4096;     // two doubles per view in LDS (64 KB)
+struct ConvState {
+    int32_t phase;                      // 0 poses, 1 joint phase, 2 stopped
+    int32_t count;                      // signals recorded
+    int32_t switch_step[2];             // steps of the 0->1 and 1->2 switches (-1)
+    double theta[kConvRing];            // theta_95 history (ring)
+};
+
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
@@ -166,6 +176,12 @@ struct Plan {
     DevBuf<int32_t> counters;             // work counters of the 8 XCD queues
     DevBuf<int64_t> xcd_begin_d;          // 9 entries: tile range of each queue
     DevBuf<int32_t> status;               // device status word
+    DevBuf<int32_t> scene_view_ptr, scene_view_idx;   // CSR: views of each scene
+    int32_t max_views_per_scene = 0;
+    DevBuf<double> conv_prev;             // V x 12 poses of the previous step
+    DevBuf<ConvState> conv_state;         // S
+    DevBuf<int32_t> conv_phase;           // S (read by the schedule kernel)
+    epo_convergence_params conv{25, 0.5f, 50, 0.1f};
     DevBuf<double> grad_scratch;          // V x 6 (graph iteration)
     DevBuf<float> lambda_buf;             // S (graph iteration)
     DevBuf<double> lr_buf;                // S (graph iteration)
@@ -201,7 +217,10 @@ void launch_pose_step(double* poses, double* m, double* v, const double* grad, i
                       double b1, double b2, double eps, int32_t* step, hipStream_t stream);
 void launch_schedule(const int32_t* step, int32_t n_scenes, float lambda0, float lambda1,
                      int32_t anneal_steps, double peak_lr, int32_t warmup, int32_t total,
-                     float* lambda_out, double* lr_out, hipStream_t stream);
+                     float* lambda_out, double* lr_out, const int32_t* phase,
+                     hipStream_t stream);
+void launch_convergence(Plan& p, const double* poses, double* theta_out, hipStream_t stream);
+void launch_convergence_reset(Plan& p, const double* poses, hipStream_t stream);
 void build_texture(Plan& p, const int32_t* d2, hipStream_t stream);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -397,6 +397,19 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         csr(in, p->view_in_ptr, p->view_in_idx);
         csr(outl, p->view_out_ptr, p->view_out_idx);
         csr(sc, p->scene_ptr, p->scene_pairs);
+        {
+            std::vector<std::vector<int32_t>> sv(S);
+            for (int v = 0; v < n_views; ++v) sv[p->scene_of_view[v]].push_back(v);
+            p->max_views_per_scene = 0;
+            for (const auto& l : sv)
+                p->max_views_per_scene = std::max<int32_t>(p->max_views_per_scene, (int32_t)l.size());
+            csr(sv, p->scene_view_ptr, p->scene_view_idx);
+        }
+        p->conv_prev.alloc(12 * (size_t)n_views);
+        p->conv_state.alloc(S);
+        p->conv_phase.alloc(S);
+        EPO_HIP(hipMemsetAsync(p->conv_state.p, 0, sizeof(ConvState) * S, s));
+        EPO_HIP(hipMemsetAsync(p->conv_phase.p, 0, sizeof(int32_t) * S, s));
 
         // ---- per-iteration buffers
         p->pair_desc.alloc(std::max(n_pairs, 1));
@@ -551,7 +564,7 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
                                             float lambda0, float lambda1, int32_t anneal_steps,
                                             double peak_lr, int32_t warmup, int32_t total,
                                             double beta1, double beta2, double eps,
-                                            void* stream) {
+                                            int32_t with_convergence, void* stream) {
     return guarded([&] {
         EPO_REQUIRE(plan && poses && adam_m && adam_v && step && loss, "null argument");
         EPO_REQUIRE(warmup >= 1 && total > warmup && anneal_steps >= 0, "schedule out of range");
@@ -576,10 +589,12 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
         }
         try {
             launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
-                            p.lambda_buf.p, p.lr_buf.p, cs);
+                            p.lambda_buf.p, p.lr_buf.p,
+                            with_convergence ? p.conv_phase.p : nullptr, cs);
             launch_cost(p, poses, p.lambda_buf.p, loss, nullptr, nullptr, nullptr, g, nullptr, cs);
             launch_pose_step(poses, adam_m, adam_v, g, p.V, p.scene_of_view_d.p, fixed_mask,
                              p.lr_buf.p, beta1, beta2, eps, step, cs);
+            if (with_convergence) launch_convergence(p, poses, nullptr, cs);
         } catch (...) {
             hipGraph_t junk = nullptr;
             (void)hipStreamEndCapture(cs, &junk);

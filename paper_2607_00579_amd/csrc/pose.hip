@@ -91,7 +91,8 @@ __global__ __launch_bounds__(256) void schedule_kernel(const int32_t* __restrict
                                                        int32_t anneal, double peak,
                                                        int32_t warmup, int32_t total,
                                                        float* __restrict__ lam,
-                                                       double* __restrict__ lr) {
+                                                       double* __restrict__ lr,
+                                                       const int32_t* __restrict__ phase) {
     const int s = step[0];
     const double frac = anneal > 0 ? (double)min(s, anneal) / (double)anneal : 1.0;
     const float lv = (float)((double)l0 - ((double)l0 - (double)l1) * frac);
@@ -102,7 +103,8 @@ __global__ __launch_bounds__(256) void schedule_kernel(const int32_t* __restrict
         r = peak * 0.5 * (1.0 + cos(M_PI * (double)(s - warmup) / (double)(total - warmup)));
     for (int k = threadIdx.x; k < S; k += blockDim.x) {
         if (lam) lam[k] = lv;
-        if (lr) lr[k] = r;
+        // a scene whose run has stopped (phase 2) keeps its poses
+        if (lr) lr[k] = (phase && phase[k] == 2) ? 0.0 : r;
     }
 }
 
@@ -118,9 +120,9 @@ void launch_pose_step(double* poses, double* m, double* v, const double* grad, i
 
 void launch_schedule(const int32_t* step, int32_t n_scenes, float lambda0, float lambda1,
                      int32_t anneal_steps, double peak_lr, int32_t warmup, int32_t total,
-                     float* lambda_out, double* lr_out, hipStream_t s) {
+                     float* lambda_out, double* lr_out, const int32_t* phase, hipStream_t s) {
     schedule_kernel<<<1, 256, 0, s>>>(step, n_scenes, lambda0, lambda1, anneal_steps, peak_lr,
-                                      warmup, total, lambda_out, lr_out);
+                                      warmup, total, lambda_out, lr_out, phase);
     EPO_CHECK_LAUNCH();
 }
 
@@ -153,6 +155,6 @@ extern "C" epo_status epo_schedule(const int32_t* step, int32_t n_scenes, float 
         EPO_REQUIRE(warmup >= 1 && total > warmup && anneal_steps >= 0,
                     "schedule lengths out of range");
         launch_schedule(step, n_scenes, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
-                        lambda_out, lr_out, as_stream(stream));
+                        lambda_out, lr_out, nullptr, as_stream(stream));
     });
 }

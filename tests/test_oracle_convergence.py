@@ -72,3 +72,19 @@ def test_dual_phase_switches_then_stops():
     # MA_7 = mean(.05,.05,.05) ... first s with three such = 9
     assert dp.switch_step[1] == 9
     assert phases[-1] == 2 and phases[4] == 1 and phases[3] == 0
+
+
+def test_loop_with_convergence_freezes_a_stopped_scene():
+    from oracle import cost, loop
+    from synth import make
+    p = make("c1")
+    h = loop.run_with_convergence(cost.OracleProblem(p), p.poses_init, 60, w1=5, eps1=0.15,
+                                  w2=8, eps2=0.1)
+    stop = h["switch_steps"][0][1]
+    assert stop is not None and h["switch_steps"][0][0] < stop
+    th = np.array(h["theta"])[:, 0]
+    # the steps after the stop move nothing (Exp(0) P = P bitwise); theta of
+    # identical rotations is not exactly 0 only because acos amplifies the
+    # rounding of tr(R R^T) next to 3
+    assert np.all(th[stop + 1:] < 1e-5)
+    assert np.all(np.array(h["phase"])[stop:, 0] == 2)
