@@ -170,6 +170,8 @@ extern "C" epo_status epo_convergence_update(epo_plan plan, const double* poses,
     return guarded([&] {
         EPO_REQUIRE(plan && poses, "null argument");
         Plan& p = *reinterpret_cast<Plan*>(plan);
+        EPO_REQUIRE(p.max_views_per_scene <= kConvMaxViews,
+                    "a scene has more views than the convergence kernel supports");
         EPO_HIP(hipSetDevice(p.device));
         hipStream_t s = as_stream(stream);
         launch_convergence(p, poses, theta95, s);

@@ -572,6 +572,8 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
         EPO_HIP(hipSetDevice(p.device));
         EPO_REQUIRE(lambda0 <= p.params.lambda_max && lambda1 <= p.params.lambda_max,
                     "schedule clamp above the plan's lambda_max");
+        EPO_REQUIRE(!with_convergence || p.max_views_per_scene <= kConvMaxViews,
+                    "a scene has more views than the convergence kernel supports");
         hipStream_t user = as_stream(stream);
         EPO_HIP(hipStreamSynchronize(user));
         release_graph(p);
