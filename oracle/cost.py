@@ -107,14 +107,20 @@ class OracleProblem:
 
     # ------------------------------------------------------------------
     def direction(self, d: int, poses: np.ndarray, lam: float, params: CostParams,
-                  frozen=None, per_residual=False):
+                  frozen=None, per_residual=False, K=None, depth=None):
         """Residual sums of directed pair d.  Returns a dict with S, n, G_tgt,
-        G_src (6-vectors, left twists of the target and source pose) and the
-        discrete decisions taken (for frozen-branch finite differences)."""
+        G_src (6-vectors, left twists of the target and source pose), the
+        focal-scale sums F_tgt, F_src, the per-pixel depth derivatives dZ of the
+        source edge pixels, and the discrete decisions taken (for frozen-branch
+        finite differences).  `K` (V x 4) and `depth` ({view: Z array}) replace
+        the problem's intrinsics / edge depths when given."""
         i, j = int(self.pairs[d, 0]), int(self.pairs[d, 1])
         u, v, Z = self.pts[i]
-        fxi, fyi, cxi, cyi = self.K[i]
-        fxj, fyj, cxj, cyj = self.K[j]
+        if depth is not None and i in depth:
+            Z = depth[i]
+        Kx = self.K if K is None else K
+        fxi, fyi, cxi, cyi = Kx[i]
+        fxj, fyj, cxj, cyj = Kx[j]
         Wj, Hj = int(self.W[j]), int(self.H[j])
         Dj = self.D[j]
         Ri, ti = poses[i][:, :3], poses[i][:, 3]
@@ -170,8 +176,19 @@ class OracleProblem:
         g_tgt = np.concatenate([a, np.cross(Xp, a)], axis=1)
         b = a @ (Rj @ Ri.T)                        # rows: R_i R_j^T a
         g_src = -np.concatenate([b, np.cross(Xc, b)], axis=1)
+        # depth of the source pixel: X_c = Z r, so dX'/dZ = R_j R_i^T r, and
+        # dH/dZ = a . (R_j R_i^T r) = b . r
+        r = np.stack([(u - cxi) / fxi, (v - cyi) / fyi, np.ones_like(u)], axis=1)
+        dZ = np.einsum("nk,nk->n", b, r)
+        # focal scales f = f0 (1 + gamma), derivatives at gamma = 0:
+        #   target: u' = f_j X'_x / z + cx_j, so du'/dgamma_j = f_j X'_x / z
+        #   source: dX_c/dgamma_i = -Z ((u - cx)/f_i, (v - cy)/f_i, 0)
+        F_tgt = drho * (dDdu * fxj * Xp[:, 0] + dDdv * fyj * Xp[:, 1]) / zz
+        dXc = np.stack([-Z * (u - cxi) / fxi, -Z * (v - cyi) / fyi, np.zeros_like(u)], axis=1)
+        F_src = np.einsum("nk,nk->n", b, dXc)
         out = dict(S=float(rho.sum()), n=int(valid.sum()), n_src=int(u.size),
                    G_tgt=g_tgt.sum(axis=0), G_src=g_src.sum(axis=0),
+                   F_tgt=float(F_tgt.sum()), F_src=float(F_src.sum()), dZ=dZ,
                    decisions=dict(valid=valid, x0=x0, y0=y0, unclamped=unclamped, quad=quad))
         if per_residual:
             out.update(rho=rho, valid=valid, up=up, vp=vp, Dval=Dval, g_tgt=g_tgt, g_src=g_src)
@@ -188,8 +205,10 @@ class OracleProblem:
         return L, w, scale
 
     def evaluate(self, poses: np.ndarray, lam, params: CostParams = CostParams(),
-                 frozen=None, pair_ids=None):
-        """Loss per scene, per-pair S, n, L_d, G, and the gradient per view."""
+                 frozen=None, pair_ids=None, K=None, depth=None):
+        """Loss per scene, per-pair S, n, L_d, G, the gradient per view, the
+        focal-scale gradient per view (grad_focal) and the depth gradient of
+        every edge pixel (grad_depth: {view: array in edge-pixel order})."""
         lam = np.broadcast_to(np.asarray(lam, np.float64), (self.n_scenes,))
         D = self.pairs.shape[0]
         ids = range(D) if pair_ids is None else pair_ids
@@ -198,23 +217,37 @@ class OracleProblem:
         n_src = np.zeros(D, np.int64)
         G_tgt = np.zeros((D, 6))
         G_src = np.zeros((D, 6))
+        F_tgt = np.zeros(D)
+        F_src = np.zeros(D)
+        dZ = {}
         decisions = {}
         for d in ids:
             s = int(self.scene_of_pair[d])
             r = self.direction(d, poses, float(lam[s]), params,
-                               frozen=None if frozen is None else frozen[d])
+                               frozen=None if frozen is None else frozen[d], K=K, depth=depth)
             S[d], n[d], n_src[d] = r["S"], r["n"], r["n_src"]
             G_tgt[d], G_src[d] = r["G_tgt"], r["G_src"]
+            F_tgt[d], F_src[d] = r["F_tgt"], r["F_src"]
+            dZ[d] = r["dZ"]
             decisions[d] = r["decisions"]
         L, w, scale = self.weights(S, n, n_src, params)
         loss = np.zeros(self.n_scenes)
         grad = np.zeros((self.V, 6))
+        grad_focal = np.zeros(self.V)
+        grad_depth = {}
         for d in ids:
             s = int(self.scene_of_pair[d])
+            i, j = int(self.pairs[d, 0]), int(self.pairs[d, 1])
             loss[s] += scale[d] * L[d]
-            grad[self.pairs[d, 1]] += w[d] * G_tgt[d]
-            grad[self.pairs[d, 0]] += w[d] * G_src[d]
-        return dict(loss=loss, grad=grad, S=S, n=n, L=L, w=w, G_tgt=G_tgt, G_src=G_src,
+            grad[j] += w[d] * G_tgt[d]
+            grad[i] += w[d] * G_src[d]
+            grad_focal[j] += w[d] * F_tgt[d]
+            grad_focal[i] += w[d] * F_src[d]
+            if i not in grad_depth:
+                grad_depth[i] = np.zeros(self.pts[i][0].size)
+            grad_depth[i] += w[d] * dZ[d]
+        return dict(loss=loss, grad=grad, grad_focal=grad_focal, grad_depth=grad_depth, S=S, n=n,
+                    L=L, w=w, G_tgt=G_tgt, G_src=G_src, F_tgt=F_tgt, F_src=F_src,
                     decisions=decisions)
 
 
@@ -250,8 +283,47 @@ def fd_gradient(op: OracleProblem, poses: np.ndarray, lam, params: CostParams = 
     return g
 
 
-def _frozen_loss(op, poses, lam, params, frozen, base):
-    r = op.evaluate(poses, lam, params, frozen=frozen)
+def fd_focal(op: OracleProblem, poses: np.ndarray, lam, params: CostParams = CostParams(),
+             h: float = 1e-6, views=None):
+    """Frozen-branch central differences of the scene loss in each view's
+    focal scale gamma (fx and fy multiplied by 1 + gamma)."""
+    base = op.evaluate(poses, lam, params)
+    frozen = base["decisions"]
+    views = range(op.V) if views is None else views
+    g = np.zeros(op.V)
+    for v in views:
+        s = int(op.scene_of_view[v])
+        Kp, Km = op.K.copy(), op.K.copy()
+        Kp[v, :2] *= 1.0 + h
+        Km[v, :2] *= 1.0 - h
+        lp = _frozen_loss(op, poses, lam, params, frozen, base, K=Kp)
+        lm = _frozen_loss(op, poses, lam, params, frozen, base, K=Km)
+        g[v] = (lp[s] - lm[s]) / (2.0 * h)
+    return g
+
+
+def fd_depth(op: OracleProblem, poses: np.ndarray, lam, view: int, pixels,
+             params: CostParams = CostParams(), h: float = 1e-6):
+    """Frozen-branch central differences of the scene loss in the depth of the
+    given edge pixels (indices into the view's edge-pixel order)."""
+    base = op.evaluate(poses, lam, params)
+    frozen = base["decisions"]
+    s = int(op.scene_of_view[view])
+    Z = op.pts[view][2]
+    out = []
+    for p in pixels:
+        Zp, Zm = Z.copy(), Z.copy()
+        step = h * Z[p]
+        Zp[p] += step
+        Zm[p] -= step
+        lp = _frozen_loss(op, poses, lam, params, frozen, base, depth={view: Zp})
+        lm = _frozen_loss(op, poses, lam, params, frozen, base, depth={view: Zm})
+        out.append((lp[s] - lm[s]) / (2.0 * step))
+    return np.array(out)
+
+
+def _frozen_loss(op, poses, lam, params, frozen, base, K=None, depth=None):
+    r = op.evaluate(poses, lam, params, frozen=frozen, K=K, depth=depth)
     # denominators fixed at the base point
     L, w, scale = op.weights(r["S"], base["n"], op_n_src(op, base), params)
     loss = np.zeros(op.n_scenes)

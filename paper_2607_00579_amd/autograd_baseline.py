@@ -69,6 +69,10 @@ class TorchEdgeCost:
         Kp = torch.as_tensor(K64, device=dev)[view_of_pt]
         self.Xc = torch.stack([(u - Kp[:, 2]) / Kp[:, 0] * z, (v - Kp[:, 3]) / Kp[:, 1] * z, z],
                               dim=0).to(dtype)                       # (3, P)
+        # the unlifted points, for the form with focal and depth leaves
+        self.uvz = torch.stack([u, v, z], dim=0).to(dtype)
+        self.K0 = torch.as_tensor(K64, device=dev).to(dtype)
+        self.view_of_pt = view_of_pt
         # batches of whole pairs, padded to the longest source in the batch
         self.n_src = counts[self.pairs_np[:, 0]]
         self.batches = []
@@ -112,7 +116,7 @@ class TorchEdgeCost:
         t = t0 + (Wh * t0[:, None, :]).sum(2) + rho
         return R, t
 
-    def _batch(self, R, t, lam, a, b, nmax):
+    def _batch(self, R, t, lam, a, b, nmax, gamma=None, dz=None):
         dt = self.dtype
         dev = self.device
         pi = torch.as_tensor(self.pairs_np[a:b, 0], device=dev)
@@ -123,11 +127,21 @@ class TorchEdgeCost:
         tji = tj - (Rji * ti[:, None, :]).sum(-1)
         Rji, tji = Rji.to(dt), tji.to(dt)
         idx, mask, cnt = self._indices(a, b, nmax)
-        X, Y, Z = self.Xc[0][idx], self.Xc[1][idx], self.Xc[2][idx]       # (b, n)
+        if gamma is None:
+            X, Y, Z = self.Xc[0][idx], self.Xc[1][idx], self.Xc[2][idx]   # (b, n)
+            Kj = self.K[pj]
+        else:
+            # lift inside the graph: f = f0 (1 + gamma), Z = Z0 + dz
+            Ks = self.K0 * torch.stack([1 + gamma, 1 + gamma, torch.ones_like(gamma),
+                                        torch.ones_like(gamma)], dim=1).to(dt)
+            Ki = Ks[pi]
+            Kj = Ks[pj]
+            Z = (self.uvz[2] + dz.to(dt))[idx]
+            X = (self.uvz[0][idx] - Ki[:, 2:3]) / Ki[:, 0:1] * Z
+            Y = (self.uvz[1][idx] - Ki[:, 3:4]) / Ki[:, 1:2] * Z
         xp = Rji[:, 0, 0:1] * X + Rji[:, 0, 1:2] * Y + Rji[:, 0, 2:3] * Z + tji[:, 0:1]
         yp = Rji[:, 1, 0:1] * X + Rji[:, 1, 1:2] * Y + Rji[:, 1, 2:3] * Z + tji[:, 1:2]
         zp = Rji[:, 2, 0:1] * X + Rji[:, 2, 1:2] * Y + Rji[:, 2, 2:3] * Z + tji[:, 2:3]
-        Kj = self.K[pj]
         Wj = torch.as_tensor(self.W_np[self.pairs_np[a:b, 1]], device=dev)[:, None]
         Hj = torch.as_tensor(self.H_np[self.pairs_np[a:b, 1]], device=dev)[:, None]
         front = zp > self.z_min
@@ -159,8 +173,11 @@ class TorchEdgeCost:
         L = torch.where(den > 0, S / den.clamp(min=1).to(dt), torch.zeros_like(S))
         return S, n, L
 
-    def loss_and_grad(self, poses0, lam, want_pairs=False):
-        """Loss per scene and d(loss)/d(xi) per view at xi = 0 (autograd)."""
+    def loss_and_grad(self, poses0, lam, want_pairs=False, intrinsics_depth=False):
+        """Loss per scene and d(loss)/d(xi) per view at xi = 0 (autograd).
+        With intrinsics_depth, also d(loss)/d(gamma) per view (focal scale,
+        f = f0 (1 + gamma)) and d(loss)/dZ per edge point, at gamma = 0 and
+        the given depths."""
         dev = self.device
         poses0 = torch.as_tensor(np.asarray(poses0) if not torch.is_tensor(poses0) else poses0,
                                  device=dev, dtype=torch.float64)
@@ -170,12 +187,17 @@ class TorchEdgeCost:
             lam_t = torch.as_tensor(np.broadcast_to(np.asarray(lam, np.float64),
                                                     (self.n_scenes,)).copy(), device=dev).to(self.dtype)
         xi = torch.zeros(self.n_views, 6, dtype=torch.float64, device=dev, requires_grad=True)
+        gamma = dz = None
+        if intrinsics_depth:
+            gamma = torch.zeros(self.n_views, dtype=torch.float64, device=dev, requires_grad=True)
+            dz = torch.zeros(self.uvz.shape[1], dtype=torch.float64, device=dev,
+                             requires_grad=True)
         loss = torch.zeros(self.n_scenes, dtype=self.dtype, device=dev)
         sop = torch.as_tensor(self.scene_of_pair_np, device=dev)
         pair_S, pair_n = [], []
         for (a, b, nmax) in self.batches:
             R, t = self._poses(xi, poses0)
-            S, n, L = self._batch(R, t, lam_t, a, b, nmax)
+            S, n, L = self._batch(R, t, lam_t, a, b, nmax, gamma, dz)
             contrib = self.pair_scale[a:b] * L
             per_scene = torch.zeros(self.n_scenes, dtype=self.dtype, device=dev).index_add(
                 0, sop[a:b], contrib)
@@ -186,6 +208,10 @@ class TorchEdgeCost:
                 pair_n.append(n)
         out = dict(loss=loss, grad=xi.grad.detach() if xi.grad is not None
                    else torch.zeros_like(xi))
+        if intrinsics_depth:
+            out["grad_focal"] = gamma.grad.detach() if gamma.grad is not None else \
+                torch.zeros_like(gamma)
+            out["grad_depth"] = dz.grad.detach() if dz.grad is not None else torch.zeros_like(dz)
         if want_pairs:
             out["S"] = torch.cat(pair_S)
             out["n"] = torch.cat(pair_n)

@@ -227,3 +227,27 @@ def test_golden_trajectories_match_generator():
     for name in ("c1", "c2"):
         g = np.load(os.path.join(here, f"{name}_trajectory.npz"), allow_pickle=False)
         assert str(g["checksum"]) == input_checksum(make(name)), name
+
+
+def test_focal_and_depth_gradients_vs_finite_differences(c1):
+    """Frozen-branch central differences in each view's focal scale gamma
+    (f = f0 (1 + gamma)) and in the depth of single edge pixels."""
+    p, op = c1
+    for lam in (10.0, 3.0):
+        r = op.evaluate(p.poses_init, lam)
+        fd = cost.fd_focal(op, p.poses_init, lam)
+        assert np.abs(fd - r["grad_focal"]).max() < 1e-7 * np.abs(r["grad_focal"]).max()
+        for v in range(p.n_views):
+            gz = r["grad_depth"][v]
+            idx = np.concatenate([np.argsort(-np.abs(gz))[:4], [0, gz.size - 1]])
+            fdz = cost.fd_depth(op, p.poses_init, lam, v, idx)
+            assert np.abs(fdz - gz[idx]).max() < 1e-7 * np.abs(gz).max()
+
+
+def test_depth_gradient_of_a_pure_translation_fixture():
+    """Shifted pair at exact zero cost: every residual sits on an edge pixel
+    (D = 0, zero slope), so the depth and focal gradients vanish exactly."""
+    p = fixtures.shifted_pair()
+    r = cost.OracleProblem(p).evaluate(p.poses_init, 10.0)
+    assert np.all(r["grad_focal"] == 0.0)
+    assert all(np.all(g == 0.0) for g in r["grad_depth"].values())
