@@ -212,6 +212,49 @@ EPO_API epo_status epo_edge_cost_bwd(epo_plan plan, const double* poses, const f
                              const double* upstream, double* grad, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * 3b. Focal-length and depth refinement (paper Sec. 3 "Camera Refinement",
+ * "Depth Refinement"; the intrinsics update and depth module of the forward
+ * loop, supplementary Alg. EPO.Forward).  Per view v and edge pixel p:
+ *   f_v = f0_v (1 + gamma_v)     (fx and fy scale together; cx, cy fixed)
+ *   Z_p = Z0_p alpha_p + beta_p
+ * where f0, Z0 are the intrinsics and depths the plan was built with.
+ *
+ * epo_plan_set_refinement sets the current gamma, alpha, beta (device
+ * pointers, read during the call's kernels only):
+ *   gamma        float64 [V], or NULL = all 0
+ *   alpha, beta  float32 [n_records] in the plan's record order (see
+ *                epo_plan_view_records: records of view v are
+ *                [offset_v, offset_v + count_v), views in order), both or
+ *                neither; NULL = alpha 1, beta 0
+ * The refined focal length is float32(f0 * (1 + gamma)) (product in float64)
+ * and the refined depth float32(fma(Z0, alpha, beta)) in float64.  Later cost
+ * launches (and replays of a captured iteration) use the refined values.  A
+ * refined focal length that is not finite and > 0, or a depth that is not
+ * finite, sets bit 2 of the device status word.  The first call with depths
+ * allocates a copy of Z0 (4 bytes per record); no synchronisation.
+ *
+ * epo_edge_cost_refine: loss and every gradient of the joint phase in one
+ * call (each output may be NULL, outputs overwritten):
+ *   upstream    float64 [n_scenes] scale of each scene's loss, or NULL = 1
+ *   loss        float64 [n_scenes]  (not scaled by upstream)
+ *   grad        float64 [V][6]      pose left twists, as epo_edge_cost_bwd
+ *   grad_gamma  float64 [V]         dloss[scene(v)]/dgamma_v
+ *   grad_alpha  float64 [n_records] dloss/dalpha_p = Z0_p dloss/dZ_p
+ *   grad_beta   float64 [n_records] dloss/dbeta_p  = dloss/dZ_p
+ * grad_gamma comes from a variant of the fused kernel that also sums the
+ * focal terms of both views of every pair; grad_alpha / grad_beta from a
+ * second, source-major pass (one thread per edge record, pairs out of its
+ * view in a fixed order): no atomics, bitwise reproducible.  No allocation,
+ * no synchronisation, capture-safe.
+ * ------------------------------------------------------------------------- */
+EPO_API epo_status epo_plan_set_refinement(epo_plan plan, const double* gamma, const float* alpha,
+                                   const float* beta, void* stream);
+EPO_API epo_status epo_edge_cost_refine(epo_plan plan, const double* poses, const float* lambda,
+                                const double* upstream, double* loss, double* grad,
+                                double* grad_gamma, double* grad_alpha, double* grad_beta,
+                                void* stream);
+
+/* ---------------------------------------------------------------------------
  * 4. pose_step
  * Adam on left twists with an SE(3) update, in float64 (optimizer of Sec. 4
  * "Implementation Details" with beta = (0.9, 0.999); the pose refiner network
@@ -323,7 +366,8 @@ EPO_API epo_status epo_plan_autotune(epo_plan plan, const double* poses, const f
 EPO_API epo_status epo_plan_set_options(epo_plan plan, const epo_plan_options* options, void* stream);
 
 /* Device status word of the plan, OR-ed by the kernels: bit 0 = a non-finite
- * per-pair sum was seen, bit 1 = a lambda above lambda_max was seen.  Copies
+ * per-pair sum was seen, bit 1 = a lambda above lambda_max was seen, bit 2 = a
+ * refined focal length or depth was not finite (or a focal length <= 0).  Copies
  * to *flags (host) after synchronising `stream`, then clears the word. */
 EPO_API epo_status epo_get_device_status(epo_plan plan, int32_t* flags, void* stream);
 

@@ -51,6 +51,8 @@ _SIGS = {
     "epo_plan_view_records": [P, I32, P, I64, P],
     "epo_edge_cost_fwd": [P, P, P, P, P, P, P, P, P],
     "epo_edge_cost_bwd": [P, P, P, P, P, P],
+    "epo_plan_set_refinement": [P, P, P, P, P],
+    "epo_edge_cost_refine": [P, P, P, P, P, P, P, P, P, P],
     "epo_pose_step": [P, P, P, P, I32, P, P, P, F64, F64, F64, P, P],
     "epo_schedule": [P, I32, F32, F32, I32, F64, I32, I32, P, P, P],
     "epo_iteration_capture": [P, P, P, P, P, P, P, P, F32, F32, I32, F64, I32, I32, F64, F64,
@@ -160,6 +162,17 @@ def edge_cost_fwd(plan, poses, lam, loss, pair_cost, pair_valid, pair_grad, grad
 def edge_cost_bwd(plan, poses, lam, upstream, grad, stream):
     _check(load().epo_edge_cost_bwd(plan, _ptr(poses), _ptr(lam), _ptr(upstream), _ptr(grad),
                                     stream))
+
+
+def plan_set_refinement(plan, gamma, alpha, beta, stream):
+    _check(load().epo_plan_set_refinement(plan, _ptr(gamma), _ptr(alpha), _ptr(beta), stream))
+
+
+def edge_cost_refine(plan, poses, lam, upstream, loss, grad, grad_gamma, grad_alpha, grad_beta,
+                     stream):
+    _check(load().epo_edge_cost_refine(plan, _ptr(poses), _ptr(lam), _ptr(upstream), _ptr(loss),
+                                       _ptr(grad), _ptr(grad_gamma), _ptr(grad_alpha),
+                                       _ptr(grad_beta), stream))
 
 
 def pose_step(poses, m, v, grad, n_views, scene_of_view, fixed_mask, lr, beta1, beta2, eps, step,

@@ -140,6 +140,54 @@ class EdgePlan:
         _lib.edge_cost_bwd(self.handle, poses, lam_t, up, g, _stream(self.device))
         return g
 
+    # ------------------------------------------------------------------
+    # focal-length and depth refinement
+    def record_pixels(self) -> np.ndarray:
+        """(n_records, 3) int64 rows (view, x, y) of the edge records in the
+        plan's order, the order of alpha, beta and the depth gradients."""
+        out = []
+        for v in range(self.n_views):
+            r = self.view_records(v)
+            out.append(np.stack([np.full(r.size, v, np.int64), (r & 0xFFFF).astype(np.int64),
+                                 ((r >> np.uint64(16)) & np.uint64(0xFFFF)).astype(np.int64)],
+                                axis=1))
+        return np.concatenate(out) if out else np.zeros((0, 3), np.int64)
+
+    def set_refinement(self, gamma=None, alpha=None, beta=None):
+        """f_v = f0_v (1 + gamma_v) and Z_p = Z0_p alpha_p + beta_p on the
+        device (gamma float64 [V]; alpha, beta float32 [n_records]); None
+        restores the values the plan was built with."""
+        if gamma is not None and gamma.numel() != self.n_views:
+            raise ValueError(f"gamma needs {self.n_views} values, got {gamma.numel()}")
+        for name, t in (("alpha", alpha), ("beta", beta)):
+            if t is not None and t.numel() != self.n_records:
+                raise ValueError(f"{name} needs {self.n_records} values, got {t.numel()}")
+        g = None if gamma is None else gamma.to(self.device, torch.float64).contiguous()
+        a = None if alpha is None else alpha.to(self.device, torch.float32).contiguous()
+        b = None if beta is None else beta.to(self.device, torch.float32).contiguous()
+        _lib.plan_set_refinement(self.handle, g, a, b, _stream(self.device))
+
+    def refine(self, poses, lam, upstream=None, loss=True, grad=True, focal=True, depth=True):
+        """Loss and the gradients of the joint phase: pose twists [V, 6],
+        focal scales gamma [V], per-record depth scale alpha and shift beta
+        [n_records]."""
+        lam_t = self.lam_tensor(lam)
+        o = {}
+        if loss:
+            o["loss"] = self._f64(self.n_scenes)
+        if grad:
+            o["grad"] = self._f64(self.n_views, 6)
+        if focal:
+            o["grad_gamma"] = self._f64(self.n_views)
+        if depth:
+            o["grad_alpha"] = self._f64(self.n_records)
+            o["grad_beta"] = self._f64(self.n_records)
+        up = None if upstream is None else upstream.to(self.device, torch.float64).contiguous()
+        _lib.edge_cost_refine(self.handle, poses, lam_t, up, o.get("loss"), o.get("grad"),
+                              o.get("grad_gamma"), o.get("grad_alpha"), o.get("grad_beta"),
+                              _stream(self.device))
+        return o
+
     def pose_step(self, poses, m, v, grad, lr, step, fixed_mask=None, beta1=0.9, beta2=0.999,
                   eps=1e-8):
         if not torch.is_tensor(lr):
@@ -214,3 +262,24 @@ class EdgeCostFn(torch.autograd.Function):
             return scale * g, None, None, None, None
         g = plan.cost_bwd(ctx.poses, ctx.lam, upstream=grad_loss.to(torch.float64).contiguous())
         return g, None, None, None, None
+
+
+class EdgeRefineFn(torch.autograd.Function):
+    """loss[s] of every scene as a differentiable function of the pose twists
+    xi (V x 6, derivative at xi = 0), the focal scales gamma [V] and the
+    per-record depth scale alpha and shift beta [n_records] (derivatives at
+    the given values, which the forward pass installs in the plan).  The
+    backward pass is the hand-written adjoint: one refinement call with the
+    upstream gradient (recompute)."""
+
+    @staticmethod
+    def forward(ctx, xi, gamma, alpha, beta, plan: EdgePlan, poses, lam):
+        plan.set_refinement(gamma.detach(), alpha.detach(), beta.detach())
+        ctx.plan, ctx.poses, ctx.lam = plan, poses, lam
+        return plan.refine(poses, lam, grad=False, focal=False, depth=False)["loss"]
+
+    @staticmethod
+    def backward(ctx, grad_loss):
+        o = ctx.plan.refine(ctx.poses, ctx.lam, upstream=grad_loss.to(torch.float64).contiguous(),
+                            loss=False)
+        return (o["grad"], o["grad_gamma"], o["grad_alpha"], o["grad_beta"], None, None, None)

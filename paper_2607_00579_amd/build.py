@@ -20,7 +20,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "libepo.so")
-SOURCES = ["edt.hip", "edge_cost.hip", "reduce.hip", "pose.hip", "converge.hip", "plan.hip"]
+SOURCES = ["edt.hip", "edge_cost.hip", "reduce.hip", "pose.hip", "converge.hip", "refine.hip",
+           "plan.hip"]
 ARCH = "gfx950"
 
 COMMON = [

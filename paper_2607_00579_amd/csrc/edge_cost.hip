@@ -21,12 +21,15 @@
 //     (A_u, A_v, w) / z   and   (y_n w - A_v, A_u - x_n w, x_n A_v - y_n A_u)
 //   (the translation block is dH/dX', the rotation block X' x dH/dX', in
 //   which the depth cancels).
+// A refinement variant of the same kernel also sums the focal-scale terms of
+// both views (Sec. 3 Camera Refinement); the per-pixel depth gradient comes
+// from a second, source-major pass in refine.hip.
 // Each thread adds its float32 residual terms in float64; each workgroup
 // reduces its tile to eight float64 partial sums (S, n, G[6]) with wave64
 // butterflies and an LDS step across its four waves.  Everything above the
 // tile is float64 in a fixed order too: per pair (tiles in order), per
 // pose (g_j += w_d G_d, g_i += -w_d Ad(T_ji)^T G_d), per scene.
-#include "epo_internal.h"
+#include "residual.h"
 
 namespace epo {
 namespace {
@@ -97,121 +100,44 @@ __global__ __launch_bounds__(256) void pair_setup_kernel(
 // ---------------------------------------------------------------------------
 // fused residual + adjoint + tile reduction
 // ---------------------------------------------------------------------------
-template <int FMT>
-struct Taps;
-
-// float32 texture: four gathers
-template <>
-struct Taps<1> {
-    __device__ static inline void load(const uint32_t* __restrict__ tex, int idx, int W,
-                                       const float* /*lut*/, float& d00, float& d10, float& d01,
-                                       float& d11) {
-        const float* t = reinterpret_cast<const float*>(tex);
-        d00 = t[idx];
-        d10 = t[idx + 1];
-        d01 = t[idx + W];
-        d11 = t[idx + W + 1];
-    }
-};
-
-// saturated u8 quads: one gather, four LDS look-ups of sqrt(k)
-template <>
-struct Taps<2> {
-    __device__ static inline void load(const uint32_t* __restrict__ tex, int idx, int /*W*/,
-                                       const float* lut, float& d00, float& d10, float& d01,
-                                       float& d11) {
-        const uint32_t q = tex[idx];
-        d00 = lut[q & 0xffu];
-        d10 = lut[(q >> 8) & 0xffu];
-        d01 = lut[(q >> 16) & 0xffu];
-        d11 = lut[q >> 24];
-    }
-};
-
-// float32 quads: the four float32 taps of the cell in one 16-byte gather
-template <>
-struct Taps<3> {
-    __device__ static inline void load(const uint32_t* __restrict__ tex, int idx, int /*W*/,
-                                       const float* /*lut*/, float& d00, float& d10, float& d01,
-                                       float& d11) {
-        const float4 q = reinterpret_cast<const float4*>(tex)[idx];
-        d00 = q.x;
-        d10 = q.y;
-        d01 = q.z;
-        d11 = q.w;
-    }
-};
 
 // per-thread sums: every float32 residual term is added in float64 (the
 // pose-gradient sums cancel strongly, up to a few hundred in
-// sum |term| / |sum|), the valid count in integers
+// sum |term| / |sum|), the valid count in integers; ft, fs are the focal-scale
+// sums of the refinement variant
 struct Acc {
     double S, g0, g1, g2, g3, g4, g5;
     int n;
+    double ft, fs;
 };
 
-template <int FMT>
-__device__ inline void residual(const uint2 rec, bool active, const PairDesc& pd,
-                                const uint32_t* __restrict__ texj, const float* lut, float delta,
-                                double zmin, Acc& a) {
-    // projected coordinate in float64 (full rate on CDNA4 with packed FP32
-    // off): it decides the bilinear cell, an integer, exactly as the oracle
-    const double u = (double)(rec.x & 0xffffu);
-    const double v = (double)(rec.x >> 16);
-    const double Z = (double)__uint_as_float(rec.y);
-    const double Xx = fma(Z, fma(pd.M[0], u, fma(pd.M[1], v, pd.M[2])), pd.t[0]);
-    const double Xy = fma(Z, fma(pd.M[3], u, fma(pd.M[4], v, pd.M[5])), pd.t[1]);
-    const double Xz = fma(Z, fma(pd.M[6], u, fma(pd.M[7], v, pd.M[8])), pd.t[2]);
-    // 1 / z: hardware reciprocal refined by one Newton step, which squares its
-    // relative error (exact when z is a power of two; the parity tests hold
-    // the valid counts and cells to the float64 oracle); z <= 0, inf or NaN
-    // end as invalid
-    double rzd = __builtin_amdgcn_rcp(Xz);
-    rzd = fma(rzd, fma(-Xz, rzd, 1.0), rzd);
-    const double xnd = Xx * rzd, ynd = Xy * rzd;          // normalised target coordinates
-    const double upd = fma(pd.fxd, xnd, pd.cxd);
-    const double vpd = fma(pd.fyd, ynd, pd.cyd);
-    // 0 <= u' < W - 1 holds exactly when the cell column floor(u') lies in
-    // [0, W - 2]: one unsigned compare of the (saturating) integer cell index.
-    // Depth is finite (checked when the plan is built), so u' is NaN only if
-    // z is, and then z > z_min already fails.
-    const double fx0 = floor(upd), fy0 = floor(vpd);
-    const int x0 = (int)fx0, y0 = (int)fy0;
-    const bool valid = active && (Xz > zmin) && ((unsigned)x0 < (unsigned)pd.wcells) &&
-                       ((unsigned)y0 < (unsigned)pd.hcells);
-    // invalid residuals may carry inf/NaN coordinates: zero everything that
-    // reaches a product with a zero weight
-    const float al = valid ? (float)(upd - fx0) : 0.0f;
-    const float be = valid ? (float)(vpd - fy0) : 0.0f;
-    const int idx = valid ? (y0 * pd.width + x0) : 0;
-    const float xn = valid ? (float)xnd : 0.0f;
-    const float yn = valid ? (float)ynd : 0.0f;
-    const float rzv = valid ? (float)rzd : 0.0f;
-    float d00, d10, d01, d11;
-    Taps<FMT>::load(texj, idx, pd.width, lut, d00, d10, d01, d11);
-    const float e0 = d10 - d00, e1 = d11 - d01;
-    const float f0 = d01 - d00, f1 = d11 - d10;
-    const float gu = fmaf(be, e1 - e0, e0);
-    const float gv = fmaf(al, f1 - f0, f0);
-    const float D = fmaf(be, gv, fmaf(al, e0, d00));
-    const bool unclamped = D < pd.lambda;
-    const float dh = fminf(D, pd.lambda);      // D is finite here (masked cell)
-    const bool quad = dh <= delta;
-    float rho = quad ? 0.5f * dh * dh : delta * (dh - 0.5f * delta);
-    float drho = unclamped ? (quad ? dh : delta) : 0.0f;
-    rho = valid ? rho : 0.0f;
-    drho = valid ? drho : 0.0f;
-    const float Au = drho * gu * pd.fx;
-    const float Av = drho * gv * pd.fy;
-    const float w = -fmaf(Au, xn, Av * yn);
-    a.S += (double)rho;
-    a.n += valid ? 1 : 0;
-    a.g0 += (double)(Au * rzv);
-    a.g1 += (double)(Av * rzv);
-    a.g2 += (double)(w * rzv);
-    a.g3 += (double)fmaf(yn, w, -Av);
-    a.g4 += (double)fmaf(-xn, w, Au);
-    a.g5 += (double)fmaf(xn, Av, -yn * Au);
+// refinement variant (EXT): besides the pose terms, per pair
+//   F_t = sum of f_j dH/df_j = sum of (A_u x_n + A_v y_n) = sum of -w
+//         (u', v' scale with the target focal length),
+//   F_s = sum of f_i dH/df_i = sum of Z (dH/dX') . (c - m)
+//         (X_c = Z ((u - cx)/fx, (v - cy)/fy, 1) and fx, fy scale together, so
+//         dX'/dlog f_i = Z R_ji (-(u - cx)/fx, -(v - cy)/fy, 0) = Z (c - m) with
+//         c = R_ji e_z the third column of R_ji)
+template <int FMT, bool EXT>
+__device__ __forceinline__ void residual(const uint2 rec, bool active, const PairDesc& pd,
+                                         const uint32_t* __restrict__ texj, const float* lut,
+                                         float delta, double zmin, const double* c3, Acc& a) {
+    const Residual r = eval_residual<FMT>(rec, active, pd, texj, lut, delta, zmin);
+    a.S += (double)r.rho;
+    a.n += r.valid ? 1 : 0;
+    a.g0 += (double)(r.Au * r.rz);
+    a.g1 += (double)(r.Av * r.rz);
+    a.g2 += (double)(r.w * r.rz);
+    a.g3 += (double)fmaf(r.yn, r.w, -r.Av);
+    a.g4 += (double)fmaf(-r.xn, r.w, r.Au);
+    a.g5 += (double)fmaf(r.xn, r.Av, -r.yn * r.Au);
+    if constexpr (EXT) {
+        a.ft -= (double)r.w;
+        const float cx = (float)(c3[0] - r.mx), cy = (float)(c3[1] - r.my),
+                    cz = (float)(c3[2] - r.mz);
+        const float zr = __uint_as_float(rec.y) * r.rz;
+        a.fs += (double)(zr * fmaf(r.Au, cx, fmaf(r.Av, cy, r.w * cz)));
+    }
 }
 
 __device__ inline double wave_sum(double x) {
@@ -220,17 +146,30 @@ __device__ inline double wave_sum(double x) {
     return x;
 }
 
-template <int FMT, int P>
-__device__ inline void do_tile(int64_t t, const uint2* __restrict__ records,
-                               const uint32_t* __restrict__ tex, const Tile* __restrict__ tiles,
-                               const PairDesc* __restrict__ desc, Partial* __restrict__ partials,
-                               const float* lut, double (*red)[8], float delta, double zmin) {
+// per-tile sums: S, n, G[6] into partials[t]; the refinement variant adds
+// F_t, F_s into ext_partials[2 t ..]
+template <int FMT, int P, bool EXT>
+__device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ records,
+                                        const uint32_t* __restrict__ tex,
+                                        const Tile* __restrict__ tiles,
+                                        const PairDesc* __restrict__ desc,
+                                        const double* __restrict__ rel,
+                                        Partial* __restrict__ partials,
+                                        double* __restrict__ ext_partials, const float* lut,
+                                        double (*red)[10], float delta, double zmin) {
     const int tid = threadIdx.x;
     const Tile tl = tiles[t];
     const PairDesc pd = desc[tl.pair];
     const uint32_t* texj = tex + pd.tex_off;
     const uint2* rec = records + tl.rec;
-    Acc a{0, 0, 0, 0, 0, 0, 0, 0};
+    double c3[3] = {0.0, 0.0, 0.0};
+    if constexpr (EXT) {
+        const double* R = rel + 12 * (int64_t)tl.pair;
+        c3[0] = R[2];
+        c3[1] = R[5];
+        c3[2] = R[8];
+    }
+    Acc a{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     // two residuals in flight per thread (about 50 VGPRs, so the SIMD keeps
     // eight waves to hide the record load and the dependent tap gather);
     // unrolling all P would multiply the float64 live ranges
@@ -248,32 +187,49 @@ __device__ inline void do_tile(int64_t t, const uint2* __restrict__ records,
         }
 #pragma unroll
         for (int k = 0; k < U; ++k)
-            residual<FMT>(r[k], (k0 + k) * kBlock + tid < tl.count, pd, texj, lut, delta, zmin,
-                          a);
+            residual<FMT, EXT>(r[k], (k0 + k) * kBlock + tid < tl.count, pd, texj, lut, delta,
+                               zmin, c3, a);
     }
-    double s[8] = {a.S, (double)a.n, a.g0, a.g1, a.g2, a.g3, a.g4, a.g5};
+    constexpr int NS = EXT ? 10 : 8;
+    double s[NS];
+    s[0] = a.S;
+    s[1] = (double)a.n;
+    s[2] = a.g0;
+    s[3] = a.g1;
+    s[4] = a.g2;
+    s[5] = a.g3;
+    s[6] = a.g4;
+    s[7] = a.g5;
+    if constexpr (EXT) {
+        s[8] = a.ft;
+        s[9] = a.fs;
+    }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) s[k] = wave_sum(s[k]);
+    for (int k = 0; k < NS; ++k) s[k] = wave_sum(s[k]);
     const int wave = tid >> 6, lane = tid & 63;
     if (lane == 0) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) red[wave][k] = s[k];
+        for (int k = 0; k < NS; ++k) red[wave][k] = s[k];
     }
     __syncthreads();
-    if (tid < 8) {
+    if (tid < NS) {
         const double x = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-        partials[t].v[tid] = x;
+        if (tid < 8)
+            partials[t].v[tid] = x;
+        else
+            ext_partials[2 * t + (tid - 8)] = x;
     }
 }
 
-template <int FMT, int P>
+template <int FMT, int P, bool EXT>
 __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
     const uint2* __restrict__ records, const uint32_t* __restrict__ tex,
     const Tile* __restrict__ tiles, const PairDesc* __restrict__ desc,
-    Partial* __restrict__ partials, const int64_t* __restrict__ xcd_begin, int32_t n_queues,
+    const double* __restrict__ rel, Partial* __restrict__ partials,
+    double* __restrict__ ext_partials, const int64_t* __restrict__ xcd_begin, int32_t n_queues,
     int32_t* __restrict__ counters, int32_t persistent, float delta, double zmin) {
     __shared__ float lut[256];
-    __shared__ double red[4][8];
+    __shared__ double red[4][10];
     __shared__ int64_t claim;
     if (FMT == 2) lut[threadIdx.x] = sqrtf((float)threadIdx.x);
     __syncthreads();
@@ -283,7 +239,8 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
         // tiles of queue q (consecutive target views) stay on one XCD's L2
         const int64_t t = xcd_begin[q0] + blockIdx.x / (unsigned)n_queues;
         if (t >= xcd_begin[q0 + 1]) return;
-        do_tile<FMT, P>(t, records, tex, tiles, desc, partials, lut, red, delta, zmin);
+        do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials, lut, red,
+                             delta, zmin);
         return;
     }
     // persistent: claim tiles from the own queue, then from the others
@@ -296,13 +253,14 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
             const int64_t t = claim;
             __syncthreads();
             if (t >= end) break;
-            do_tile<FMT, P>(t, records, tex, tiles, desc, partials, lut, red, delta, zmin);
+            do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials, lut,
+                                 red, delta, zmin);
             __syncthreads();
         }
     }
 }
 
-template <int FMT, int P>
+template <int FMT, int P, bool EXT>
 void launch_cost_kernel(Plan& p, hipStream_t s) {
     const uint32_t* tex = FMT == 2   ? p.tex.p
                           : FMT == 3 ? reinterpret_cast<const uint32_t*>(p.tex_q32.p)
@@ -320,30 +278,40 @@ void launch_cost_kernel(Plan& p, hipStream_t s) {
         grid = (unsigned)(per_q * nq);
     }
     if (grid == 0) return;
-    edge_cost_kernel<FMT, P><<<grid, kBlock, 0, s>>>(
-        reinterpret_cast<const uint2*>(p.records.p), tex, p.tiles.p, p.pair_desc.p, p.partials.p,
-        p.xcd_begin_d.p, nq, p.counters.p,
+    edge_cost_kernel<FMT, P, EXT><<<grid, kBlock, 0, s>>>(
+        reinterpret_cast<const uint2*>(p.records.p), tex, p.tiles.p, p.pair_desc.p, p.pair_rel.p,
+        p.partials.p, EXT ? p.ext_partials.p : nullptr, p.xcd_begin_d.p, nq, p.counters.p,
         p.opt.persistent == 1 ? 1 : 0, p.params.huber_delta, p.params.z_min);
     EPO_CHECK_LAUNCH();
 }
 
-template <int FMT>
+template <int FMT, bool EXT>
 void launch_cost_fmt(Plan& p, hipStream_t s) {
     switch (p.opt.points_per_thread) {
-        case 1: launch_cost_kernel<FMT, 1>(p, s); break;
-        case 2: launch_cost_kernel<FMT, 2>(p, s); break;
-        case 4: launch_cost_kernel<FMT, 4>(p, s); break;
-        case 8: launch_cost_kernel<FMT, 8>(p, s); break;
-        case 16: launch_cost_kernel<FMT, 16>(p, s); break;
+        case 1: launch_cost_kernel<FMT, 1, EXT>(p, s); break;
+        case 2: launch_cost_kernel<FMT, 2, EXT>(p, s); break;
+        case 4: launch_cost_kernel<FMT, 4, EXT>(p, s); break;
+        case 8: launch_cost_kernel<FMT, 8, EXT>(p, s); break;
+        case 16: launch_cost_kernel<FMT, 16, EXT>(p, s); break;
         default: throw Failure{EPO_ERR_UNSUPPORTED, "points_per_thread must be 1, 2, 4, 8 or 16"};
     }
+}
+
+template <bool EXT>
+void launch_cost_variant(Plan& p, hipStream_t s) {
+    if (p.opt.texture_format == 2)
+        launch_cost_fmt<2, EXT>(p, s);
+    else if (p.opt.texture_format == 3)
+        launch_cost_fmt<3, EXT>(p, s);
+    else
+        launch_cost_fmt<1, EXT>(p, s);
 }
 
 }  // namespace
 
 void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss,
                  double* pair_cost, int32_t* pair_valid, double* pair_grad, double* grad,
-                 const double* upstream, hipStream_t s) {
+                 const double* upstream, hipStream_t s, const RefineOut* ext) {
     if (p.D > 0) {
         pair_setup_kernel<<<(unsigned)ceil_div(std::max(p.D, 16), 256), 256, 0, s>>>(
             poses, p.K_d.p, p.wh_d.p, p.view_offset_d.p, p.pair_static.p, lambda,
@@ -351,18 +319,19 @@ void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss
         EPO_CHECK_LAUNCH();
         const bool timed = p.timing;
         if (timed) EPO_HIP(hipEventRecord(p.ev0, s));
-        if (p.opt.texture_format == 2)
-            launch_cost_fmt<2>(p, s);
-        else if (p.opt.texture_format == 3)
-            launch_cost_fmt<3>(p, s);
+        if (ext && ext->grad_gamma)
+            launch_cost_variant<true>(p, s);
         else
-            launch_cost_fmt<1>(p, s);
+            launch_cost_variant<false>(p, s);
         if (timed) {
             EPO_HIP(hipEventRecord(p.ev1, s));
             p.timed_once = true;
         }
     }
-    launch_reductions(p, loss, pair_cost, pair_valid, pair_grad, grad, upstream, s);
+    launch_reductions(p, loss, pair_cost, pair_valid, pair_grad, grad, upstream, s,
+                      ext ? ext->grad_gamma : nullptr);
+    if (ext && (ext->grad_alpha || ext->grad_beta))
+        launch_depth_grad(p, upstream, ext->grad_alpha, ext->grad_beta, s);
 }
 
 }  // namespace epo

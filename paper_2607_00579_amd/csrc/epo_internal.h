@@ -169,6 +169,8 @@ struct Plan {
     DevBuf<Partial> partials;             // T
     DevBuf<double> pair_sum;              // D x 8: S, n, G[6] (float64)
     DevBuf<double> pair_w;                // D: weight w_d
+    DevBuf<double> ext_partials;          // T x 2: focal-scale sums F_t, F_s per tile
+    DevBuf<double> pair_ext;              // D x 2: F_t, F_s per pair
     DevBuf<int32_t> view_in_idx, view_in_ptr;     // CSR: pairs with tgt == v
     DevBuf<int32_t> view_out_idx, view_out_ptr;   // CSR: pairs with src == v
     DevBuf<int32_t> scene_ptr;            // CSR: pairs of scene s are [scene_ptr[s], scene_ptr[s+1]) of scene_pairs
@@ -183,6 +185,12 @@ struct Plan {
     DevBuf<int32_t> conv_phase;           // S (read by the schedule kernel)
     epo_convergence_params conv{25, 0.5f, 50, 0.1f};
     DevBuf<double> grad_scratch;          // V x 6 (graph iteration)
+    // focal and depth refinement: f = f0 (1 + gamma_v), Z = Z0 alpha + beta
+    DevBuf<float> K0_d;                   // V x 4 intrinsics as given (K_d holds the refined ones)
+    DevBuf<double> gamma_d;               // V: current focal scales gamma
+    DevBuf<float> z0;                     // n_records depths as given (allocated on first update)
+    DevBuf<Tile> vblocks;                 // 256-record blocks of each view (pair = view)
+    int64_t n_vblocks = 0;
     DevBuf<float> lambda_buf;             // S (graph iteration)
     DevBuf<double> lr_buf;                // S (graph iteration)
     int64_t n_tiles = 0;
@@ -205,12 +213,21 @@ struct Plan {
 // schedule (tile list) construction; (re)allocates tiles and partials
 void build_tiles(Plan& p, hipStream_t stream);
 
+// outputs of the refinement variant (each may be null)
+struct RefineOut {
+    double* grad_gamma;     // V: dL/dgamma_v
+    double* grad_alpha;     // n_records: dL/dalpha = Z0 dL/dZ
+    double* grad_beta;      // n_records: dL/dbeta = dL/dZ
+};
+
 // launches of the per-iteration pipeline (no allocation, no sync)
 void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss,
                  double* pair_cost, int32_t* pair_valid, double* pair_grad, double* grad,
-                 const double* upstream, hipStream_t stream);
+                 const double* upstream, hipStream_t stream, const RefineOut* ext = nullptr);
 void launch_reductions(Plan& p, double* loss, double* pair_cost, int32_t* pair_valid,
                        double* pair_grad, double* grad, const double* upstream,
+                       hipStream_t stream, double* grad_gamma = nullptr);
+void launch_depth_grad(Plan& p, const double* upstream, double* grad_alpha, double* grad_beta,
                        hipStream_t stream);
 void launch_pose_step(double* poses, double* m, double* v, const double* grad, int32_t n_views,
                       const int32_t* scene_of_view, const uint8_t* fixed, const double* lr,

@@ -215,6 +215,7 @@ void build_tiles(Plan& p, hipStream_t s) {
     upload(p.pair_static, ps, s);
     upload(p.xcd_begin_d, p.xcd_begin, s);
     p.partials.alloc((size_t)std::max<int64_t>(p.n_tiles, 1));
+    p.ext_partials.alloc(2 * (size_t)std::max<int64_t>(p.n_tiles, 1));
     EPO_HIP(hipStreamSynchronize(s));
 }
 
@@ -324,6 +325,9 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         }
         upload(p->wh_d, wh, s);
         upload(p->K_d, p->K, s);
+        upload(p->K0_d, p->K, s);
+        p->gamma_d.alloc(n_views);
+        EPO_HIP(hipMemsetAsync(p->gamma_d.p, 0, sizeof(double) * n_views, s));
         upload(p->view_offset_d, p->view_offset, s);
         upload(p->scene_of_view_d, p->scene_of_view, s);
 
@@ -355,6 +359,17 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         p->rec_off.assign(n_views + 1, 0);
         for (int v = 0; v < n_views; ++v) p->rec_off[v] = tile_rec.empty() ? 0 : tile_rec[tile_first[v]];
         p->rec_off[n_views] = acc;
+        {
+            // 256-record blocks of each view for the source-major depth pass
+            std::vector<Tile> vb;
+            for (int v = 0; v < n_views; ++v)
+                for (int64_t c = p->rec_off[v]; c < p->rec_off[v + 1]; c += 256)
+                    vb.push_back(Tile{v, (int32_t)std::min<int64_t>(256, p->rec_off[v + 1] - c), c});
+            EPO_REQUIRE((int64_t)vb.size() < (int64_t)INT32_MAX, "too many record blocks");
+            p->n_vblocks = (int64_t)vb.size();
+            upload(p->vblocks, vb, s);
+            EPO_HIP(hipStreamSynchronize(s));
+        }
         DevBuf<int64_t> tile_rec_d;
         upload(tile_rec_d, tile_rec, s);
         p->records.alloc((size_t)std::max<int64_t>(acc, 1));
@@ -416,6 +431,7 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         p->pair_rel.alloc(12 * (size_t)std::max(n_pairs, 1));
         p->pair_sum.alloc(8 * (size_t)std::max(n_pairs, 1));
         p->pair_w.alloc(std::max(n_pairs, 1));
+        p->pair_ext.alloc(2 * (size_t)std::max(n_pairs, 1));
         p->counters.alloc(16);
         p->status.alloc(1);
         EPO_HIP(hipMemsetAsync(p->counters.p, 0, 16 * sizeof(int32_t), s));

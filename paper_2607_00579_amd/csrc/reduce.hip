@@ -8,6 +8,11 @@
 //              (the source pose sees the target's left perturbation moved
 //              through the relative pose: T_ji Exp(-xi_i) = Exp(-Ad(T_ji) xi_i) T_ji)
 //   per scene  loss = sum over its pairs of (2 / |D_scene|) L_d (Eqs. L, L_ij)
+//   refinement (Sec. 3 Camera Refinement): with the per-pair focal sums F_t
+//              (target) and F_s (source), each f dH/df,
+//              dL/dgamma_v = (sum over pairs into v of w_d F_t
+//                             + sum over pairs out of v of w_d F_s) / (1 + gamma_v)
+//              (f = f0 (1 + gamma), so dL/dgamma = f0 dL/df = f dL/df / (1 + gamma))
 // One thread per pair; one wave64 per pose (lanes stride over the pose's pairs,
 // then a butterfly); one workgroup per scene (threads stride over its pairs,
 // then wave butterflies and an LDS step).
@@ -23,8 +28,9 @@ __device__ inline double wave_sum64(double x) {
 }
 
 __global__ __launch_bounds__(256) void reduce_pairs_kernel(
-    const Partial* __restrict__ partials, const PairStatic* __restrict__ ps, int32_t D,
-    int32_t norm_mode, double* __restrict__ pair_sum, double* __restrict__ pair_w,
+    const Partial* __restrict__ partials, const double* __restrict__ ext_partials,
+    const PairStatic* __restrict__ ps, int32_t D, int32_t norm_mode,
+    double* __restrict__ pair_sum, double* __restrict__ pair_w, double* __restrict__ pair_ext,
     double* __restrict__ pair_cost, int32_t* __restrict__ pair_valid,
     double* __restrict__ pair_grad, int32_t* __restrict__ status) {
     const int d = blockIdx.x * blockDim.x + threadIdx.x;
@@ -35,6 +41,16 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(
         const Partial pt = partials[st.first_tile + k];
 #pragma unroll
         for (int c = 0; c < 8; ++c) s[c] += pt.v[c];
+    }
+    if (ext_partials) {
+        double ft = 0.0, fs = 0.0;
+        for (int k = 0; k < st.n_tiles; ++k) {
+            ft += ext_partials[2 * (int64_t)(st.first_tile + k)];
+            fs += ext_partials[2 * (int64_t)(st.first_tile + k) + 1];
+        }
+        if (!isfinite(ft) || !isfinite(fs)) atomicOr(status, 1);
+        pair_ext[2 * d] = ft;
+        pair_ext[2 * d + 1] = fs;
     }
     const double den = norm_mode == 0 ? s[1] : (double)st.n_src;
     const double L = den > 0 ? s[0] / den : 0.0;
@@ -57,16 +73,20 @@ __global__ __launch_bounds__(256) void reduce_views_kernel(
     const double* __restrict__ rel, const int32_t* __restrict__ in_ptr,
     const int32_t* __restrict__ in_idx, const int32_t* __restrict__ out_ptr,
     const int32_t* __restrict__ out_idx, const int32_t* __restrict__ scene_of_view, int32_t V,
-    const double* __restrict__ upstream, double* __restrict__ grad) {
+    const double* __restrict__ upstream, double* __restrict__ grad,
+    const double* __restrict__ pair_ext, const double* __restrict__ gamma,
+    double* __restrict__ grad_gamma) {
     const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (v >= V) return;                       // whole wave leaves together
     double g[6] = {0, 0, 0, 0, 0, 0};
+    double gf = 0.0;
     for (int k = in_ptr[v] + lane; k < in_ptr[v + 1]; k += 64) {
         const int d = in_idx[k];
         const double w = pair_w[d];
 #pragma unroll
         for (int c = 0; c < 6; ++c) g[c] += w * pair_sum[8 * d + 2 + c];
+        if (grad_gamma) gf += w * pair_ext[2 * d];
     }
     //   Ad^T (G_r, G_w) = (R^T G_r, R^T (G_w - t x G_r))
     for (int k = out_ptr[v] + lane; k < out_ptr[v + 1]; k += 64) {
@@ -83,15 +103,22 @@ __global__ __launch_bounds__(256) void reduce_views_kernel(
             g[r] -= w * (R[0 + r] * G[0] + R[3 + r] * G[1] + R[6 + r] * G[2]);
             g[3 + r] -= w * (R[0 + r] * c0 + R[3 + r] * c1 + R[6 + r] * c2);
         }
+        if (grad_gamma) gf += w * pair_ext[2 * d + 1];
     }
+    const double up = upstream ? upstream[scene_of_view[v]] : 1.0;
+    if (grad) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) g[c] = wave_sum64(g[c]);
-    if (lane < 6) {
-        const double up = upstream ? upstream[scene_of_view[v]] : 1.0;
-        double x = g[0];
+        for (int c = 0; c < 6; ++c) g[c] = wave_sum64(g[c]);
+        if (lane < 6) {
+            double x = g[0];
 #pragma unroll
-        for (int c = 1; c < 6; ++c) x = lane == c ? g[c] : x;
-        grad[6 * v + lane] = up * x;
+            for (int c = 1; c < 6; ++c) x = lane == c ? g[c] : x;
+            grad[6 * v + lane] = up * x;
+        }
+    }
+    if (grad_gamma) {
+        gf = wave_sum64(gf);
+        if (lane == 0) grad_gamma[v] = up * gf / (1.0 + gamma[v]);
     }
 }
 
@@ -118,17 +145,20 @@ __global__ __launch_bounds__(256) void reduce_scenes_kernel(
 }  // namespace
 
 void launch_reductions(Plan& p, double* loss, double* pair_cost, int32_t* pair_valid,
-                       double* pair_grad, double* grad, const double* upstream, hipStream_t s) {
+                       double* pair_grad, double* grad, const double* upstream, hipStream_t s,
+                       double* grad_gamma) {
     if (p.D > 0) {
         reduce_pairs_kernel<<<(unsigned)ceil_div(p.D, 256), 256, 0, s>>>(
-            p.partials.p, p.pair_static.p, p.D, p.params.norm_mode, p.pair_sum.p, p.pair_w.p,
-            pair_cost, pair_valid, pair_grad, p.status.p);
+            p.partials.p, grad_gamma ? p.ext_partials.p : nullptr, p.pair_static.p, p.D,
+            p.params.norm_mode, p.pair_sum.p, p.pair_w.p, p.pair_ext.p, pair_cost, pair_valid,
+            pair_grad, p.status.p);
         EPO_CHECK_LAUNCH();
     }
-    if (grad) {
+    if (grad || grad_gamma) {
         reduce_views_kernel<<<(unsigned)ceil_div(p.V, 4), 256, 0, s>>>(
             p.pair_sum.p, p.pair_w.p, p.pair_rel.p, p.view_in_ptr.p, p.view_in_idx.p,
-            p.view_out_ptr.p, p.view_out_idx.p, p.scene_of_view_d.p, p.V, upstream, grad);
+            p.view_out_ptr.p, p.view_out_idx.p, p.scene_of_view_d.p, p.V, upstream, grad,
+            p.pair_ext.p, p.gamma_d.p, grad_gamma);
         EPO_CHECK_LAUNCH();
     }
     if (loss) {

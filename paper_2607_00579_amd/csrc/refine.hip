@@ -1,0 +1,169 @@
+// Focal-length and depth refinement on the device (paper Sec. 3 "Camera
+// Refinement" and "Depth Refinement"; the intrinsics update and the depth
+// module of Alg. EPO.Forward):
+//   f_v = f0_v (1 + gamma_v)        (fx and fy of view v scale together)
+//   Z_p = Z0_p alpha_p + beta_p     (per edge pixel p of every view)
+// The plan keeps the intrinsics and depths it was built with (f0, Z0); an
+// update rewrites the intrinsics used by the pair set-up and the depth field
+// of the edge records in place, so every later cost launch (and a captured
+// iteration) sees the refined values.
+//
+// Depth gradient, source-major: the per-pixel derivative
+//   dL/dZ_p = sum over pairs d out of view i of w_d (dH/dX') . m_d(p)
+// (X' = Z m + t, m = R_ji K_i^-1 (u, v, 1)^T) needs the pair weights w_d, which
+// exist only after the pair-major pass has counted the valid residuals.  So
+// this second pass gives one thread to each edge record of view i and walks
+// the pairs out of i in a fixed order, adding in float64: no atomics, bitwise
+// reproducible.  dL/dbeta_p = dL/dZ_p and dL/dalpha_p = Z0_p dL/dZ_p.
+#include "residual.h"
+
+namespace epo {
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ __launch_bounds__(256) void refine_intrinsics_kernel(
+    const float* __restrict__ K0, const double* __restrict__ gamma, float* __restrict__ K,
+    double* __restrict__ gamma_state, int32_t V, int32_t* __restrict__ status) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const double g = gamma ? gamma[v] : 0.0;
+    const double s = 1.0 + g;
+    // float64 product of the float32 focal length, rounded once to float32
+    const float fx = (float)((double)K0[4 * v] * s);
+    const float fy = (float)((double)K0[4 * v + 1] * s);
+    if (!(fx > 0.0f) || !(fy > 0.0f) || !isfinite(fx) || !isfinite(fy)) atomicOr(status, 4);
+    K[4 * v] = fx;
+    K[4 * v + 1] = fy;
+    K[4 * v + 2] = K0[4 * v + 2];
+    K[4 * v + 3] = K0[4 * v + 3];
+    gamma_state[v] = g;
+}
+
+__global__ __launch_bounds__(256) void snapshot_depth_kernel(const uint2* __restrict__ records,
+                                                             float* __restrict__ z0, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) z0[k] = __uint_as_float(records[k].y);
+}
+
+__global__ __launch_bounds__(256) void refine_depth_kernel(const float* __restrict__ z0,
+                                                           const float* __restrict__ alpha,
+                                                           const float* __restrict__ beta,
+                                                           uint2* __restrict__ records, int64_t n,
+                                                           int32_t* __restrict__ status) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    // Z0 alpha is exact in float64 (two float32 factors), so this is one
+    // rounding to float64 followed by one to float32
+    const float z = alpha ? (float)fma((double)z0[k], (double)alpha[k], (double)beta[k]) : z0[k];
+    if (!isfinite(z)) atomicOr(status, 4);
+    records[k].y = __float_as_uint(z);
+}
+
+template <int FMT>
+__global__ __launch_bounds__(kBlock) void depth_grad_kernel(
+    const uint2* __restrict__ records, const uint32_t* __restrict__ tex,
+    const Tile* __restrict__ vblocks, const PairDesc* __restrict__ desc,
+    const double* __restrict__ pair_w, const int32_t* __restrict__ out_ptr,
+    const int32_t* __restrict__ out_idx, const int32_t* __restrict__ scene_of_view,
+    const double* __restrict__ upstream, const float* __restrict__ z0, float delta, double zmin,
+    double* __restrict__ grad_alpha, double* __restrict__ grad_beta) {
+    __shared__ float lut[256];
+    if (FMT == 2) lut[threadIdx.x] = sqrtf((float)threadIdx.x);
+    __syncthreads();
+    const Tile b = vblocks[blockIdx.x];
+    const int i = b.pair;                       // source view of this block
+    const bool active = (int)threadIdx.x < b.count;
+    const int64_t k = b.rec + threadIdx.x;
+    const uint2 rec = active ? records[k] : make_uint2(0u, 0u);
+    double acc = 0.0;
+    const int e1 = out_ptr[i + 1];
+    for (int e = out_ptr[i]; e < e1; ++e) {
+        const int d = out_idx[e];
+        const double wd = pair_w[d];
+        if (wd == 0.0) continue;                // no valid residual in pair d
+        const PairDesc pd = desc[d];
+        const Residual r = eval_residual<FMT>(rec, active, pd, tex + pd.tex_off, lut, delta, zmin);
+        // dH/dZ = (dH/dX') . m, dH/dX' = (A_u, A_v, w) / z
+        const float dz =
+            r.rz * fmaf(r.Au, (float)r.mx, fmaf(r.Av, (float)r.my, r.w * (float)r.mz));
+        acc = fma(wd, (double)dz, acc);
+    }
+    if (!active) return;
+    const double g = (upstream ? upstream[scene_of_view[i]] : 1.0) * acc;
+    if (grad_beta) grad_beta[k] = g;
+    if (grad_alpha) grad_alpha[k] = g * (double)(z0 ? z0[k] : __uint_as_float(rec.y));
+}
+
+template <int FMT>
+void launch_depth_fmt(Plan& p, const uint32_t* tex, const double* upstream, double* grad_alpha,
+                      double* grad_beta, hipStream_t s) {
+    depth_grad_kernel<FMT><<<(unsigned)p.n_vblocks, kBlock, 0, s>>>(
+        reinterpret_cast<const uint2*>(p.records.p), tex, p.vblocks.p, p.pair_desc.p, p.pair_w.p,
+        p.view_out_ptr.p, p.view_out_idx.p, p.scene_of_view_d.p, upstream, p.z0.p,
+        p.params.huber_delta, p.params.z_min, grad_alpha, grad_beta);
+    EPO_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+void launch_depth_grad(Plan& p, const double* upstream, double* grad_alpha, double* grad_beta,
+                       hipStream_t s) {
+    if (p.n_vblocks == 0) return;
+    if (p.opt.texture_format == 2)
+        launch_depth_fmt<2>(p, p.tex.p, upstream, grad_alpha, grad_beta, s);
+    else if (p.opt.texture_format == 3)
+        launch_depth_fmt<3>(p, reinterpret_cast<const uint32_t*>(p.tex_q32.p), upstream,
+                            grad_alpha, grad_beta, s);
+    else
+        launch_depth_fmt<1>(p, reinterpret_cast<const uint32_t*>(p.tex_f32.p), upstream,
+                            grad_alpha, grad_beta, s);
+}
+
+}  // namespace epo
+
+using namespace epo;
+
+extern "C" epo_status epo_plan_set_refinement(epo_plan plan, const double* gamma,
+                                              const float* alpha, const float* beta,
+                                              void* stream) {
+    return guarded([&] {
+        EPO_REQUIRE(plan, "null plan");
+        EPO_REQUIRE((alpha == nullptr) == (beta == nullptr),
+                    "alpha and beta must be given together");
+        Plan& p = *reinterpret_cast<Plan*>(plan);
+        EPO_HIP(hipSetDevice(p.device));
+        hipStream_t s = as_stream(stream);
+        refine_intrinsics_kernel<<<(unsigned)ceil_div(p.V, 256), 256, 0, s>>>(
+            p.K0_d.p, gamma, p.K_d.p, p.gamma_d.p, p.V, p.status.p);
+        EPO_CHECK_LAUNCH();
+        const int64_t n = p.rec_off.back();
+        if (n == 0) return;
+        if (!p.z0.p) {
+            // first depth update: keep the depths the plan was built with
+            if (!alpha) return;
+            p.z0.alloc((size_t)n);
+            snapshot_depth_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(
+                reinterpret_cast<const uint2*>(p.records.p), p.z0.p, n);
+            EPO_CHECK_LAUNCH();
+        }
+        refine_depth_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(
+            p.z0.p, alpha, beta, reinterpret_cast<uint2*>(p.records.p), n, p.status.p);
+        EPO_CHECK_LAUNCH();
+    });
+}
+
+extern "C" epo_status epo_edge_cost_refine(epo_plan plan, const double* poses,
+                                           const float* lambda, const double* upstream,
+                                           double* loss, double* grad, double* grad_gamma,
+                                           double* grad_alpha, double* grad_beta, void* stream) {
+    return guarded([&] {
+        EPO_REQUIRE(plan, "null plan");
+        EPO_REQUIRE(poses && lambda, "poses and lambda are required");
+        Plan& p = *reinterpret_cast<Plan*>(plan);
+        EPO_HIP(hipSetDevice(p.device));
+        const RefineOut out{grad_gamma, grad_alpha, grad_beta};
+        launch_cost(p, poses, lambda, loss, nullptr, nullptr, nullptr, grad, upstream,
+                    as_stream(stream), &out);
+    });
+}

@@ -1,0 +1,139 @@
+// One edge-alignment residual and its adjoint terms (paper Eqs. pi, d_ij,
+// Sec. A1.2 "Per-iteration kernels"), shared by the pair-major fused kernel
+// and the source-major depth-gradient kernel.
+//
+// For a source edge record (u, v, Z) of view i and the descriptor of pair
+// i -> j:
+//   m  = M (u, v, 1)^T with M = R_ji K_i^-1 (the unit-depth ray in the target
+//        frame), X' = Z m + t_ji (float64);
+//   z  = X'_z; x_n = X'_x / z, y_n = X'_y / z; u' = fx_j x_n + cx_j, v' likewise;
+//   valid iff z > z_min and 0 <= u' < W_j - 1 and 0 <= v' < H_j - 1;
+//   D  = bilinear sample of DTF_j in the cell floor(u'), floor(v');
+//   rho = Huber(min(D, lambda)), rho' its derivative (0 where D >= lambda);
+//   A_u = rho' dD/du' fx_j, A_v = rho' dD/dv' fy_j, w = -(A_u x_n + A_v y_n),
+//   so that dH/dX' = (A_u, A_v, w) / z.
+#pragma once
+
+#include "epo_internal.h"
+
+namespace epo {
+
+template <int FMT>
+struct Taps;
+
+// float32 texture: four gathers
+template <>
+struct Taps<1> {
+    __device__ static inline void load(const uint32_t* __restrict__ tex, int idx, int W,
+                                       const float* /*lut*/, float& d00, float& d10, float& d01,
+                                       float& d11) {
+        const float* t = reinterpret_cast<const float*>(tex);
+        d00 = t[idx];
+        d10 = t[idx + 1];
+        d01 = t[idx + W];
+        d11 = t[idx + W + 1];
+    }
+};
+
+// saturated u8 quads: one gather, four LDS look-ups of sqrt(k)
+template <>
+struct Taps<2> {
+    __device__ static inline void load(const uint32_t* __restrict__ tex, int idx, int /*W*/,
+                                       const float* lut, float& d00, float& d10, float& d01,
+                                       float& d11) {
+        const uint32_t q = tex[idx];
+        d00 = lut[q & 0xffu];
+        d10 = lut[(q >> 8) & 0xffu];
+        d01 = lut[(q >> 16) & 0xffu];
+        d11 = lut[q >> 24];
+    }
+};
+
+// float32 quads: the four float32 taps of the cell in one 16-byte gather
+template <>
+struct Taps<3> {
+    __device__ static inline void load(const uint32_t* __restrict__ tex, int idx, int /*W*/,
+                                       const float* /*lut*/, float& d00, float& d10, float& d01,
+                                       float& d11) {
+        const float4 q = reinterpret_cast<const float4*>(tex)[idx];
+        d00 = q.x;
+        d10 = q.y;
+        d01 = q.z;
+        d11 = q.w;
+    }
+};
+
+struct Residual {
+    float rho;              // Huber value (0 if invalid)
+    float Au, Av, w;        // adjoint terms (0 if invalid)
+    float xn, yn, rz;       // normalised target coordinates, 1 / z (0 if invalid)
+    bool valid;
+    double mx, my, mz;      // unit-depth ray m = M (u, v, 1)^T in the target frame
+};
+
+template <int FMT>
+__device__ __forceinline__ Residual eval_residual(const uint2 rec, bool active,
+                                                  const PairDesc& pd,
+                                                  const uint32_t* __restrict__ texj,
+                                                  const float* lut, float delta, double zmin) {
+    Residual r;
+    // projected coordinate in float64 (full rate on CDNA4 with packed FP32
+    // off): it decides the bilinear cell, an integer, exactly as the oracle
+    const double u = (double)(rec.x & 0xffffu);
+    const double v = (double)(rec.x >> 16);
+    const double Z = (double)__uint_as_float(rec.y);
+    r.mx = fma(pd.M[0], u, fma(pd.M[1], v, pd.M[2]));
+    r.my = fma(pd.M[3], u, fma(pd.M[4], v, pd.M[5]));
+    r.mz = fma(pd.M[6], u, fma(pd.M[7], v, pd.M[8]));
+    const double Xx = fma(Z, r.mx, pd.t[0]);
+    const double Xy = fma(Z, r.my, pd.t[1]);
+    const double Xz = fma(Z, r.mz, pd.t[2]);
+    // 1 / z: hardware reciprocal refined by one Newton step, which squares its
+    // relative error (exact when z is a power of two; the parity tests hold
+    // the valid counts and cells to the float64 oracle); z <= 0, inf or NaN
+    // end as invalid
+    double rzd = __builtin_amdgcn_rcp(Xz);
+    rzd = fma(rzd, fma(-Xz, rzd, 1.0), rzd);
+    const double xnd = Xx * rzd, ynd = Xy * rzd;          // normalised target coordinates
+    const double upd = fma(pd.fxd, xnd, pd.cxd);
+    const double vpd = fma(pd.fyd, ynd, pd.cyd);
+    // 0 <= u' < W - 1 holds exactly when the cell column floor(u') lies in
+    // [0, W - 2]: one unsigned compare of the (saturating) integer cell index.
+    // Depths and focal lengths are finite (checked when the plan is built and
+    // flagged by the refinement update), so u' is NaN only if z is, and then
+    // z > z_min already fails; should a non-finite value get through anyway,
+    // NaN converts to cell 0, so every read stays inside the texture.
+    const double fx0 = floor(upd), fy0 = floor(vpd);
+    const int x0 = (int)fx0, y0 = (int)fy0;
+    const bool valid = active && (Xz > zmin) && ((unsigned)x0 < (unsigned)pd.wcells) &&
+                       ((unsigned)y0 < (unsigned)pd.hcells);
+    // invalid residuals may carry inf/NaN coordinates: zero everything that
+    // reaches a product with a zero weight
+    const float al = valid ? (float)(upd - fx0) : 0.0f;
+    const float be = valid ? (float)(vpd - fy0) : 0.0f;
+    const int idx = valid ? (y0 * pd.width + x0) : 0;
+    r.xn = valid ? (float)xnd : 0.0f;
+    r.yn = valid ? (float)ynd : 0.0f;
+    r.rz = valid ? (float)rzd : 0.0f;
+    float d00, d10, d01, d11;
+    Taps<FMT>::load(texj, idx, pd.width, lut, d00, d10, d01, d11);
+    const float e0 = d10 - d00, e1 = d11 - d01;
+    const float f0 = d01 - d00, f1 = d11 - d10;
+    const float gu = fmaf(be, e1 - e0, e0);
+    const float gv = fmaf(al, f1 - f0, f0);
+    const float D = fmaf(be, gv, fmaf(al, e0, d00));
+    const bool unclamped = D < pd.lambda;
+    const float dh = fminf(D, pd.lambda);      // D is finite here (masked cell)
+    const bool quad = dh <= delta;
+    float rho = quad ? 0.5f * dh * dh : delta * (dh - 0.5f * delta);
+    float drho = unclamped ? (quad ? dh : delta) : 0.0f;
+    r.rho = valid ? rho : 0.0f;
+    drho = valid ? drho : 0.0f;
+    r.Au = drho * gu * pd.fx;
+    r.Av = drho * gv * pd.fy;
+    r.w = -fmaf(r.Au, r.xn, r.Av * r.yn);
+    r.valid = valid;
+    return r;
+}
+
+}  // namespace epo

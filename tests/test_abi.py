@@ -62,6 +62,12 @@ def test_version_and_error_paths(lib):
                         None)
     with pytest.raises(lib.EpoError):
         lib.pose_step(None, None, None, None, 2, None, None, None, 0.9, 0.999, 1e-8, None, None)
+    with pytest.raises(lib.EpoError) as e:
+        lib.plan_set_refinement(None, None, None, None, None)
+    assert e.value.status == lib.ERR_INVALID_ARG and "null plan" in str(e.value)
+    with pytest.raises(lib.EpoError) as e:
+        lib.edge_cost_refine(None, None, None, None, None, None, None, None, None, None)
+    assert e.value.status == lib.ERR_INVALID_ARG
     # zero views is a valid no-op for the distance transform
     lib.build_distance_fields(None, None, None, None, 0, None, None, None)
 

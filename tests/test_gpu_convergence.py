@@ -15,7 +15,10 @@ pytestmark = pytest.mark.gpu
 
 
 def two_scene_problem():
-    return pack(list(problem("c2").scenes) + list(problem("c1").scenes), "c2+c1")
+    # generated here: problems read back from the on-disk input cache carry
+    # packed arrays only, not their scenes
+    from synth.scenes import config_c1, config_c2
+    return pack(list(config_c2().scenes) + list(config_c1().scenes), "c2+c1")
 
 
 def test_signal_and_phases_on_a_given_pose_sequence(gpu):
