@@ -118,10 +118,12 @@ struct Acc {
 //         (X_c = Z ((u - cx)/fx, (v - cy)/fy, 1) and fx, fy scale together, so
 //         dX'/dlog f_i = Z R_ji (-(u - cx)/fx, -(v - cy)/fy, 0) = Z (c - m) with
 //         c = R_ji e_z the third column of R_ji)
+//   and it returns the residual's depth derivative dH/dZ (stored for the
+//   source-major depth pass)
 template <int FMT, bool EXT>
-__device__ __forceinline__ void residual(const uint2 rec, bool active, const PairDesc& pd,
-                                         const uint32_t* __restrict__ texj, const float* lut,
-                                         float delta, double zmin, const double* c3, Acc& a) {
+__device__ __forceinline__ float residual(const uint2 rec, bool active, const PairDesc& pd,
+                                          const uint32_t* __restrict__ texj, const float* lut,
+                                          float delta, double zmin, const double* c3, Acc& a) {
     const Residual r = eval_residual<FMT>(rec, active, pd, texj, lut, delta, zmin);
     a.S += (double)r.rho;
     a.n += r.valid ? 1 : 0;
@@ -137,7 +139,9 @@ __device__ __forceinline__ void residual(const uint2 rec, bool active, const Pai
                     cz = (float)(c3[2] - r.mz);
         const float zr = __uint_as_float(rec.y) * r.rz;
         a.fs += (double)(zr * fmaf(r.Au, cx, fmaf(r.Av, cy, r.w * cz)));
+        return depth_derivative(r);
     }
+    return 0.0f;
 }
 
 __device__ inline double wave_sum(double x) {
@@ -147,7 +151,8 @@ __device__ inline double wave_sum(double x) {
 }
 
 // per-tile sums: S, n, G[6] into partials[t]; the refinement variant adds
-// F_t, F_s into ext_partials[2 t ..]
+// F_t, F_s into ext_partials[2 t ..] and, if dz is given, stores every
+// residual's depth derivative at dz[res_base[pair] + record]
 template <int FMT, int P, bool EXT>
 __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ records,
                                         const uint32_t* __restrict__ tex,
@@ -155,7 +160,9 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
                                         const PairDesc* __restrict__ desc,
                                         const double* __restrict__ rel,
                                         Partial* __restrict__ partials,
-                                        double* __restrict__ ext_partials, const float* lut,
+                                        double* __restrict__ ext_partials,
+                                        const int64_t* __restrict__ res_base,
+                                        float* __restrict__ dz, const float* lut,
                                         double (*red)[10], float delta, double zmin) {
     const int tid = threadIdx.x;
     const Tile tl = tiles[t];
@@ -163,11 +170,13 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
     const uint32_t* texj = tex + pd.tex_off;
     const uint2* rec = records + tl.rec;
     double c3[3] = {0.0, 0.0, 0.0};
+    float* dzt = nullptr;
     if constexpr (EXT) {
         const double* R = rel + 12 * (int64_t)tl.pair;
         c3[0] = R[2];
         c3[1] = R[5];
         c3[2] = R[8];
+        if (dz) dzt = dz + res_base[tl.pair] + tl.rec;
     }
     Acc a{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     // two residuals in flight per thread (about 50 VGPRs, so the SIMD keeps
@@ -186,9 +195,12 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
             r[k] = idx < tl.count ? rec[idx] : make_uint2(0u, 0u);
         }
 #pragma unroll
-        for (int k = 0; k < U; ++k)
-            residual<FMT, EXT>(r[k], (k0 + k) * kBlock + tid < tl.count, pd, texj, lut, delta,
-                               zmin, c3, a);
+        for (int k = 0; k < U; ++k) {
+            const int idx = (k0 + k) * kBlock + tid;
+            const float g = residual<FMT, EXT>(r[k], idx < tl.count, pd, texj, lut, delta, zmin,
+                                               c3, a);
+            if (EXT && dzt && idx < tl.count) dzt[idx] = g;
+        }
     }
     constexpr int NS = EXT ? 10 : 8;
     double s[NS];
@@ -226,7 +238,8 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
     const uint2* __restrict__ records, const uint32_t* __restrict__ tex,
     const Tile* __restrict__ tiles, const PairDesc* __restrict__ desc,
     const double* __restrict__ rel, Partial* __restrict__ partials,
-    double* __restrict__ ext_partials, const int64_t* __restrict__ xcd_begin, int32_t n_queues,
+    double* __restrict__ ext_partials, const int64_t* __restrict__ res_base,
+    float* __restrict__ dz, const int64_t* __restrict__ xcd_begin, int32_t n_queues,
     int32_t* __restrict__ counters, int32_t persistent, float delta, double zmin) {
     __shared__ float lut[256];
     __shared__ double red[4][10];
@@ -239,8 +252,8 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
         // tiles of queue q (consecutive target views) stay on one XCD's L2
         const int64_t t = xcd_begin[q0] + blockIdx.x / (unsigned)n_queues;
         if (t >= xcd_begin[q0 + 1]) return;
-        do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials, lut, red,
-                             delta, zmin);
+        do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials, res_base,
+                             dz, lut, red, delta, zmin);
         return;
     }
     // persistent: claim tiles from the own queue, then from the others
@@ -253,15 +266,15 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
             const int64_t t = claim;
             __syncthreads();
             if (t >= end) break;
-            do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials, lut,
-                                 red, delta, zmin);
+            do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials,
+                                 res_base, dz, lut, red, delta, zmin);
             __syncthreads();
         }
     }
 }
 
 template <int FMT, int P, bool EXT>
-void launch_cost_kernel(Plan& p, hipStream_t s) {
+void launch_cost_kernel(Plan& p, float* dz, hipStream_t s) {
     const uint32_t* tex = FMT == 2   ? p.tex.p
                           : FMT == 3 ? reinterpret_cast<const uint32_t*>(p.tex_q32.p)
                                      : reinterpret_cast<const uint32_t*>(p.tex_f32.p);
@@ -280,31 +293,32 @@ void launch_cost_kernel(Plan& p, hipStream_t s) {
     if (grid == 0) return;
     edge_cost_kernel<FMT, P, EXT><<<grid, kBlock, 0, s>>>(
         reinterpret_cast<const uint2*>(p.records.p), tex, p.tiles.p, p.pair_desc.p, p.pair_rel.p,
-        p.partials.p, EXT ? p.ext_partials.p : nullptr, p.xcd_begin_d.p, nq, p.counters.p,
+        p.partials.p, EXT ? p.ext_partials.p : nullptr, p.pair_res_base.p, dz, p.xcd_begin_d.p,
+        nq, p.counters.p,
         p.opt.persistent == 1 ? 1 : 0, p.params.huber_delta, p.params.z_min);
     EPO_CHECK_LAUNCH();
 }
 
 template <int FMT, bool EXT>
-void launch_cost_fmt(Plan& p, hipStream_t s) {
+void launch_cost_fmt(Plan& p, float* dz, hipStream_t s) {
     switch (p.opt.points_per_thread) {
-        case 1: launch_cost_kernel<FMT, 1, EXT>(p, s); break;
-        case 2: launch_cost_kernel<FMT, 2, EXT>(p, s); break;
-        case 4: launch_cost_kernel<FMT, 4, EXT>(p, s); break;
-        case 8: launch_cost_kernel<FMT, 8, EXT>(p, s); break;
-        case 16: launch_cost_kernel<FMT, 16, EXT>(p, s); break;
+        case 1: launch_cost_kernel<FMT, 1, EXT>(p, dz, s); break;
+        case 2: launch_cost_kernel<FMT, 2, EXT>(p, dz, s); break;
+        case 4: launch_cost_kernel<FMT, 4, EXT>(p, dz, s); break;
+        case 8: launch_cost_kernel<FMT, 8, EXT>(p, dz, s); break;
+        case 16: launch_cost_kernel<FMT, 16, EXT>(p, dz, s); break;
         default: throw Failure{EPO_ERR_UNSUPPORTED, "points_per_thread must be 1, 2, 4, 8 or 16"};
     }
 }
 
 template <bool EXT>
-void launch_cost_variant(Plan& p, hipStream_t s) {
+void launch_cost_variant(Plan& p, float* dz, hipStream_t s) {
     if (p.opt.texture_format == 2)
-        launch_cost_fmt<2, EXT>(p, s);
+        launch_cost_fmt<2, EXT>(p, dz, s);
     else if (p.opt.texture_format == 3)
-        launch_cost_fmt<3, EXT>(p, s);
+        launch_cost_fmt<3, EXT>(p, dz, s);
     else
-        launch_cost_fmt<1, EXT>(p, s);
+        launch_cost_fmt<1, EXT>(p, dz, s);
 }
 
 }  // namespace
@@ -319,10 +333,14 @@ void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss
         EPO_CHECK_LAUNCH();
         const bool timed = p.timing;
         if (timed) EPO_HIP(hipEventRecord(p.ev0, s));
-        if (ext && ext->grad_gamma)
-            launch_cost_variant<true>(p, s);
+        // the refinement variant runs for focal gradients, and for depth
+        // gradients when the per-residual derivatives can be stored
+        const bool depth = ext && (ext->grad_alpha || ext->grad_beta);
+        float* dz = depth && p.dz.p ? p.dz.p : nullptr;
+        if (ext && (ext->grad_gamma || dz))
+            launch_cost_variant<true>(p, dz, s);
         else
-            launch_cost_variant<false>(p, s);
+            launch_cost_variant<false>(p, nullptr, s);
         if (timed) {
             EPO_HIP(hipEventRecord(p.ev1, s));
             p.timed_once = true;
@@ -331,7 +349,7 @@ void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss
     launch_reductions(p, loss, pair_cost, pair_valid, pair_grad, grad, upstream, s,
                       ext ? ext->grad_gamma : nullptr);
     if (ext && (ext->grad_alpha || ext->grad_beta))
-        launch_depth_grad(p, upstream, ext->grad_alpha, ext->grad_beta, s);
+        launch_depth_grad(p, upstream, ext->grad_alpha, ext->grad_beta, p.D > 0 && p.dz.p, s);
 }
 
 }  // namespace epo

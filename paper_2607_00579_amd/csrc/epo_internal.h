@@ -189,6 +189,10 @@ struct Plan {
     DevBuf<float> K0_d;                   // V x 4 intrinsics as given (K_d holds the refined ones)
     DevBuf<double> gamma_d;               // V: current focal scales gamma
     DevBuf<float> z0;                     // n_records depths as given (allocated on first update)
+    DevBuf<int64_t> pair_res_base;        // D: residual (d, record k) at pair_res_base[d] + k
+    DevBuf<float> dz;                     // n_residuals dH/dZ per residual (allocated on first
+                                          // update when it fits; else the depth pass recomputes)
+    bool dz_declined = false;             // no room for dz: recompute form only
     DevBuf<Tile> vblocks;                 // 256-record blocks of each view (pair = view)
     int64_t n_vblocks = 0;
     DevBuf<float> lambda_buf;             // S (graph iteration)
@@ -228,7 +232,7 @@ void launch_reductions(Plan& p, double* loss, double* pair_cost, int32_t* pair_v
                        double* pair_grad, double* grad, const double* upstream,
                        hipStream_t stream, double* grad_gamma = nullptr);
 void launch_depth_grad(Plan& p, const double* upstream, double* grad_alpha, double* grad_beta,
-                       hipStream_t stream);
+                       bool stored, hipStream_t stream);
 void launch_pose_step(double* poses, double* m, double* v, const double* grad, int32_t n_views,
                       const int32_t* scene_of_view, const uint8_t* fixed, const double* lr,
                       double b1, double b2, double eps, int32_t* step, hipStream_t stream);

@@ -391,8 +391,11 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         // ---- residual count, CSR lists
         p->n_residuals = 0;
         std::vector<std::vector<int32_t>> in(n_views), outl(n_views), sc(S);
+        std::vector<int64_t> res_base(std::max(n_pairs, 1), 0);
         for (int d = 0; d < n_pairs; ++d) {
             const int i = p->pairs[2 * d], j = p->pairs[2 * d + 1];
+            // residual (d, record k) sits at res_base[d] + k in per-residual buffers
+            res_base[d] = p->n_residuals - p->rec_off[i];
             p->n_residuals += p->rec_off[i + 1] - p->rec_off[i];
             in[j].push_back(d);
             outl[i].push_back(d);
@@ -409,6 +412,8 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
             upload(idx, hi, s);
             EPO_HIP(hipStreamSynchronize(s));
         };
+        upload(p->pair_res_base, res_base, s);
+        EPO_HIP(hipStreamSynchronize(s));
         csr(in, p->view_in_ptr, p->view_in_idx);
         csr(outl, p->view_out_ptr, p->view_out_idx);
         csr(sc, p->scene_ptr, p->scene_pairs);

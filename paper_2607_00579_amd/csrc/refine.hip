@@ -12,9 +12,15 @@
 //   dL/dZ_p = sum over pairs d out of view i of w_d (dH/dX') . m_d(p)
 // (X' = Z m + t, m = R_ji K_i^-1 (u, v, 1)^T) needs the pair weights w_d, which
 // exist only after the pair-major pass has counted the valid residuals.  So
-// this second pass gives one thread to each edge record of view i and walks
-// the pairs out of i in a fixed order, adding in float64: no atomics, bitwise
+// a second pass gives one thread to each edge record of view i and walks the
+// pairs out of i in a fixed order, adding in float64: no atomics, bitwise
 // reproducible.  dL/dbeta_p = dL/dZ_p and dL/dalpha_p = Z0_p dL/dZ_p.
+// Two forms of that pass, with bitwise identical results:
+//   stored     the pair-major refinement kernel has written every residual's
+//              dH/dZ (float32, 4 bytes per residual); the pass only gathers
+//              them (coalesced: consecutive records of one pair are adjacent)
+//   recompute  no room for that buffer: the pass evaluates every residual
+//              again from the record, the pair descriptor and the texture.
 #include "residual.h"
 
 namespace epo {
@@ -84,15 +90,38 @@ __global__ __launch_bounds__(kBlock) void depth_grad_kernel(
         if (wd == 0.0) continue;                // no valid residual in pair d
         const PairDesc pd = desc[d];
         const Residual r = eval_residual<FMT>(rec, active, pd, tex + pd.tex_off, lut, delta, zmin);
-        // dH/dZ = (dH/dX') . m, dH/dX' = (A_u, A_v, w) / z
-        const float dz =
-            r.rz * fmaf(r.Au, (float)r.mx, fmaf(r.Av, (float)r.my, r.w * (float)r.mz));
-        acc = fma(wd, (double)dz, acc);
+        acc = fma(wd, (double)depth_derivative(r), acc);
     }
     if (!active) return;
     const double g = (upstream ? upstream[scene_of_view[i]] : 1.0) * acc;
     if (grad_beta) grad_beta[k] = g;
     if (grad_alpha) grad_alpha[k] = g * (double)(z0 ? z0[k] : __uint_as_float(rec.y));
+}
+
+__global__ __launch_bounds__(256) void depth_gather_kernel(
+    const float* __restrict__ dz, const int64_t* __restrict__ res_base,
+    const Tile* __restrict__ vblocks, const double* __restrict__ pair_w,
+    const int32_t* __restrict__ out_ptr, const int32_t* __restrict__ out_idx,
+    const int32_t* __restrict__ scene_of_view, const double* __restrict__ upstream,
+    const float* __restrict__ z0, const uint2* __restrict__ records,
+    double* __restrict__ grad_alpha, double* __restrict__ grad_beta) {
+    const Tile b = vblocks[blockIdx.x];
+    const int i = b.pair;
+    if ((int)threadIdx.x >= b.count) return;
+    const int64_t k = b.rec + threadIdx.x;
+    double acc = 0.0;
+    const int e1 = out_ptr[i + 1];
+    // same pairs, same order and same float32 terms as the recompute form
+#pragma unroll 4
+    for (int e = out_ptr[i]; e < e1; ++e) {
+        const int d = out_idx[e];
+        const double wd = pair_w[d];
+        const float g = dz[res_base[d] + k];
+        acc = wd != 0.0 ? fma(wd, (double)g, acc) : acc;
+    }
+    const double gr = (upstream ? upstream[scene_of_view[i]] : 1.0) * acc;
+    if (grad_beta) grad_beta[k] = gr;
+    if (grad_alpha) grad_alpha[k] = gr * (double)(z0 ? z0[k] : __uint_as_float(records[k].y));
 }
 
 template <int FMT>
@@ -108,8 +137,16 @@ void launch_depth_fmt(Plan& p, const uint32_t* tex, const double* upstream, doub
 }  // namespace
 
 void launch_depth_grad(Plan& p, const double* upstream, double* grad_alpha, double* grad_beta,
-                       hipStream_t s) {
+                       bool stored, hipStream_t s) {
     if (p.n_vblocks == 0) return;
+    if (stored) {
+        depth_gather_kernel<<<(unsigned)p.n_vblocks, kBlock, 0, s>>>(
+            p.dz.p, p.pair_res_base.p, p.vblocks.p, p.pair_w.p, p.view_out_ptr.p,
+            p.view_out_idx.p, p.scene_of_view_d.p, upstream, p.z0.p,
+            reinterpret_cast<const uint2*>(p.records.p), grad_alpha, grad_beta);
+        EPO_CHECK_LAUNCH();
+        return;
+    }
     if (p.opt.texture_format == 2)
         launch_depth_fmt<2>(p, p.tex.p, upstream, grad_alpha, grad_beta, s);
     else if (p.opt.texture_format == 3)
@@ -134,6 +171,16 @@ extern "C" epo_status epo_plan_set_refinement(epo_plan plan, const double* gamma
         Plan& p = *reinterpret_cast<Plan*>(plan);
         EPO_HIP(hipSetDevice(p.device));
         hipStream_t s = as_stream(stream);
+        if (!p.dz.p && p.n_residuals > 0 && !p.dz_declined) {
+            // room for the per-residual depth derivatives: use at most half
+            // of the free device memory, else keep recomputing them
+            size_t free_b = 0, total_b = 0;
+            EPO_HIP(hipMemGetInfo(&free_b, &total_b));
+            if ((uint64_t)p.n_residuals * sizeof(float) <= free_b / 2)
+                p.dz.alloc((size_t)p.n_residuals);
+            else
+                p.dz_declined = true;
+        }
         refine_intrinsics_kernel<<<(unsigned)ceil_div(p.V, 256), 256, 0, s>>>(
             p.K0_d.p, gamma, p.K_d.p, p.gamma_d.p, p.V, p.status.p);
         EPO_CHECK_LAUNCH();

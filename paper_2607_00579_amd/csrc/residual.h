@@ -136,4 +136,11 @@ __device__ __forceinline__ Residual eval_residual(const uint2 rec, bool active,
     return r;
 }
 
+// dH/dZ of the source pixel's depth: X' = Z m + t, so dH/dZ = (dH/dX') . m
+// (one expression shared by the kernel that stores it and the one that
+// recomputes it, so both give the same float32 value)
+__device__ __forceinline__ float depth_derivative(const Residual& r) {
+    return r.rz * fmaf(r.Au, (float)r.mx, fmaf(r.Av, (float)r.my, r.w * (float)r.mz));
+}
+
 }  // namespace epo

@@ -180,3 +180,19 @@ def test_refine_focal_vs_oracle_finite_differences(gpu):
     e = rel_norm_err(g, fd)
     say(f"c1: focal gradient vs central differences {e:.2e}")
     assert e < TOL
+
+
+def test_depth_pass_stored_and_recomputed_forms_agree_bitwise(gpu):
+    """Before the first refinement update the depth pass re-evaluates every
+    residual; afterwards it gathers the derivatives stored by the fused
+    refinement kernel.  Same terms in the same order: identical bits."""
+    p = problem("c2")
+    plan = plan_for(p)
+    P = torch.from_numpy(p.poses_init.copy()).cuda()
+    up = torch.tensor([1.5], dtype=torch.float64, device="cuda")
+    first = plan.refine(P, 7.0, upstream=up)
+    plan.set_refinement()                  # identity state; allocates the derivative buffer
+    second = plan.refine(P, 7.0, upstream=up)
+    for k in first:
+        assert torch.equal(first[k], second[k]), k
+    assert float(first["grad_beta"].abs().max()) > 0
