@@ -67,7 +67,10 @@ typedef enum epo_status {
  *                default 1 px): H(d) = d^2/2 for d <= delta, else
  *                delta (d - delta/2)
  *   z_min        a projection is valid only if the target-camera depth
- *                exceeds z_min (default 1e-4)
+ *                exceeds z_min (default 1e-4); must be in [1e-6, 1e6].  With
+ *                depths and translations below 1e30 in magnitude every
+ *                intermediate stays finite; beyond that a sum may become
+ *                non-finite, which sets bit 0 of the device status word
  *   norm_mode    0: per-direction mean over valid residuals (Alg. 3,
  *                default); 1: sum over the source edge count |E_i| (Eq. L_ij)
  *   lambda_max   largest clamp lambda the plan will be called with (default

@@ -101,14 +101,21 @@ __global__ __launch_bounds__(256) void pair_setup_kernel(
 // fused residual + adjoint + tile reduction
 // ---------------------------------------------------------------------------
 
-// per-thread sums: every float32 residual term is added in float64 (the
-// pose-gradient sums cancel strongly, up to a few hundred in
-// sum |term| / |sum|), the valid count in integers; ft, fs are the focal-scale
-// sums of the refinement variant
+// per-thread sums: the float32 terms of the U residuals a thread has in flight
+// are added in float32 (one more rounding, of the size of each term's own
+// product rounding), then into float64 (the pose-gradient sums cancel
+// strongly, up to a few hundred in sum |term| / |sum|); the valid count in
+// integers; ft, fs are the focal-scale sums of the refinement variant
 struct Acc {
     double S, g0, g1, g2, g3, g4, g5;
     int n;
     double ft, fs;
+};
+
+// the float32 terms of one residual
+struct Terms {
+    float S, g0, g1, g2, g3, g4, g5, ft, fs, dz;
+    int n;
 };
 
 // refinement variant (EXT): besides the pose terms, per pair
@@ -117,31 +124,33 @@ struct Acc {
 //   F_s = sum of f_i dH/df_i = sum of Z (dH/dX') . (c - m)
 //         (X_c = Z ((u - cx)/fx, (v - cy)/fy, 1) and fx, fy scale together, so
 //         dX'/dlog f_i = Z R_ji (-(u - cx)/fx, -(v - cy)/fy, 0) = Z (c - m) with
-//         c = R_ji e_z the third column of R_ji)
-//   and it returns the residual's depth derivative dH/dZ (stored for the
-//   source-major depth pass)
+//         c = R_ji e_z the third column of R_ji),
+//   and the residual's depth derivative dH/dZ (stored for the source-major
+//   depth pass)
 template <int FMT, bool EXT>
-__device__ __forceinline__ float residual(const uint2 rec, bool active, const PairDesc& pd,
+__device__ __forceinline__ Terms residual(const uint2 rec, bool active, const PairDesc& pd,
                                           const uint32_t* __restrict__ texj, const float* lut,
-                                          float delta, double zmin, const double* c3, Acc& a) {
+                                          float delta, double zmin, const double* c3) {
     const Residual r = eval_residual<FMT>(rec, active, pd, texj, lut, delta, zmin);
-    a.S += (double)r.rho;
-    a.n += r.valid ? 1 : 0;
-    a.g0 += (double)(r.Au * r.rz);
-    a.g1 += (double)(r.Av * r.rz);
-    a.g2 += (double)(r.w * r.rz);
-    a.g3 += (double)fmaf(r.yn, r.w, -r.Av);
-    a.g4 += (double)fmaf(-r.xn, r.w, r.Au);
-    a.g5 += (double)fmaf(r.xn, r.Av, -r.yn * r.Au);
+    Terms t;
+    t.S = r.rho;
+    t.n = r.valid ? 1 : 0;
+    t.g0 = r.Au * r.rz;
+    t.g1 = r.Av * r.rz;
+    t.g2 = r.w * r.rz;
+    t.g3 = fmaf(r.yn, r.w, -r.Av);
+    t.g4 = fmaf(-r.xn, r.w, r.Au);
+    t.g5 = fmaf(r.xn, r.Av, -r.yn * r.Au);
+    t.ft = t.fs = t.dz = 0.0f;
     if constexpr (EXT) {
-        a.ft -= (double)r.w;
+        t.ft = -r.w;
         const float cx = (float)(c3[0] - r.mx), cy = (float)(c3[1] - r.my),
                     cz = (float)(c3[2] - r.mz);
         const float zr = __uint_as_float(rec.y) * r.rz;
-        a.fs += (double)(zr * fmaf(r.Au, cx, fmaf(r.Av, cy, r.w * cz)));
-        return depth_derivative(r);
+        t.fs = zr * fmaf(r.Au, cx, fmaf(r.Av, cy, r.w * cz));
+        t.dz = depth_derivative(r);
     }
-    return 0.0f;
+    return t;
 }
 
 __device__ inline double wave_sum(double x) {
@@ -189,17 +198,41 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
 #pragma unroll 1
     for (int k0 = 0; k0 < rows; k0 += U) {
         uint2 r[U];
+        // rows past the tile's end load its last record (in bounds, so both
+        // loads issue back to back without a branch) and are masked
+#pragma unroll
+        for (int k = 0; k < U; ++k) r[k] = rec[min((k0 + k) * kBlock + tid, tl.count - 1)];
+        Terms tt[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int idx = (k0 + k) * kBlock + tid;
-            r[k] = idx < tl.count ? rec[idx] : make_uint2(0u, 0u);
+            tt[k] = residual<FMT, EXT>(r[k], idx < tl.count, pd, texj, lut, delta, zmin, c3);
+            if (EXT && dzt && idx < tl.count) dzt[idx] = tt[k].dz;
         }
 #pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int idx = (k0 + k) * kBlock + tid;
-            const float g = residual<FMT, EXT>(r[k], idx < tl.count, pd, texj, lut, delta, zmin,
-                                               c3, a);
-            if (EXT && dzt && idx < tl.count) dzt[idx] = g;
+        for (int k = 1; k < U; ++k) {
+            tt[0].S += tt[k].S;
+            tt[0].n += tt[k].n;
+            tt[0].g0 += tt[k].g0;
+            tt[0].g1 += tt[k].g1;
+            tt[0].g2 += tt[k].g2;
+            tt[0].g3 += tt[k].g3;
+            tt[0].g4 += tt[k].g4;
+            tt[0].g5 += tt[k].g5;
+            tt[0].ft += tt[k].ft;
+            tt[0].fs += tt[k].fs;
+        }
+        a.S += (double)tt[0].S;
+        a.n += tt[0].n;
+        a.g0 += (double)tt[0].g0;
+        a.g1 += (double)tt[0].g1;
+        a.g2 += (double)tt[0].g2;
+        a.g3 += (double)tt[0].g3;
+        a.g4 += (double)tt[0].g4;
+        a.g5 += (double)tt[0].g5;
+        if constexpr (EXT) {
+            a.ft += (double)tt[0].ft;
+            a.fs += (double)tt[0].fs;
         }
     }
     constexpr int NS = EXT ? 10 : 8;

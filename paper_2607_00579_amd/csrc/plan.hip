@@ -259,7 +259,8 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         p->params = params ? *params : epo_cost_params{1.0f, 1e-4f, 0, 10.0f};
         EPO_REQUIRE(p->params.huber_delta > 0 && std::isfinite(p->params.huber_delta),
                     "huber_delta must be > 0");
-        EPO_REQUIRE(std::isfinite(p->params.z_min), "z_min must be finite");
+        EPO_REQUIRE(p->params.z_min >= 1e-6f && p->params.z_min <= 1e6f,
+                    "z_min must be in [1e-6, 1e6]");
         EPO_REQUIRE(p->params.norm_mode == 0 || p->params.norm_mode == 1, "norm_mode must be 0 or 1");
         EPO_REQUIRE(p->params.lambda_max > 0 && std::isfinite(p->params.lambda_max),
                     "lambda_max must be > 0");

@@ -90,31 +90,35 @@ __device__ __forceinline__ Residual eval_residual(const uint2 rec, bool active,
     const double Xz = fma(Z, r.mz, pd.t[2]);
     // 1 / z: hardware reciprocal refined by one Newton step, which squares its
     // relative error (exact when z is a power of two; the parity tests hold
-    // the valid counts and cells to the float64 oracle); z <= 0, inf or NaN
-    // end as invalid
-    double rzd = __builtin_amdgcn_rcp(Xz);
-    rzd = fma(rzd, fma(-Xz, rzd, 1.0), rzd);
+    // the valid counts and cells to the float64 oracle).  It is taken of
+    // max(z, z_min), so every coordinate below stays finite for invalid
+    // residuals too (z <= z_min fails the validity test on z itself) and only
+    // the tap index needs masking
+    const double zc = fmax(Xz, zmin);
+    double rzd = __builtin_amdgcn_rcp(zc);
+    rzd = fma(rzd, fma(-zc, rzd, 1.0), rzd);
     const double xnd = Xx * rzd, ynd = Xy * rzd;          // normalised target coordinates
     const double upd = fma(pd.fxd, xnd, pd.cxd);
     const double vpd = fma(pd.fyd, ynd, pd.cyd);
     // 0 <= u' < W - 1 holds exactly when the cell column floor(u') lies in
     // [0, W - 2]: one unsigned compare of the (saturating) integer cell index.
     // Depths and focal lengths are finite (checked when the plan is built and
-    // flagged by the refinement update), so u' is NaN only if z is, and then
-    // z > z_min already fails; should a non-finite value get through anyway,
-    // NaN converts to cell 0, so every read stays inside the texture.
+    // flagged by the refinement update), so u' is finite; should a non-finite
+    // value get through anyway, NaN converts to cell 0, so every read stays
+    // inside the texture.
     const double fx0 = floor(upd), fy0 = floor(vpd);
     const int x0 = (int)fx0, y0 = (int)fy0;
     const bool valid = active && (Xz > zmin) && ((unsigned)x0 < (unsigned)pd.wcells) &&
                        ((unsigned)y0 < (unsigned)pd.hcells);
-    // invalid residuals may carry inf/NaN coordinates: zero everything that
-    // reaches a product with a zero weight
-    const float al = valid ? (float)(upd - fx0) : 0.0f;
-    const float be = valid ? (float)(vpd - fy0) : 0.0f;
+    // an invalid residual reads the taps of cell (0, 0) and gets zero weight
+    // (rho = rho' = 0) below; its coordinates are finite, so every product
+    // with that zero weight is zero
+    const float al = (float)(upd - fx0);
+    const float be = (float)(vpd - fy0);
     const int idx = valid ? (y0 * pd.width + x0) : 0;
-    r.xn = valid ? (float)xnd : 0.0f;
-    r.yn = valid ? (float)ynd : 0.0f;
-    r.rz = valid ? (float)rzd : 0.0f;
+    r.xn = (float)xnd;
+    r.yn = (float)ynd;
+    r.rz = (float)rzd;
     float d00, d10, d01, d11;
     Taps<FMT>::load(texj, idx, pd.width, lut, d00, d10, d01, d11);
     const float e0 = d10 - d00, e1 = d11 - d01;
@@ -123,7 +127,7 @@ __device__ __forceinline__ Residual eval_residual(const uint2 rec, bool active,
     const float gv = fmaf(al, f1 - f0, f0);
     const float D = fmaf(be, gv, fmaf(al, e0, d00));
     const bool unclamped = D < pd.lambda;
-    const float dh = fminf(D, pd.lambda);      // D is finite here (masked cell)
+    const float dh = unclamped ? D : pd.lambda;    // min(D, lambda); D is finite
     const bool quad = dh <= delta;
     float rho = quad ? 0.5f * dh * dh : delta * (dh - 0.5f * delta);
     float drho = unclamped ? (quad ? dh : delta) : 0.0f;

@@ -127,3 +127,11 @@ def test_plan_create_rejects_unsupported_texture(lib):
 def test_struct_layouts(lib):
     assert C.sizeof(lib.CostParams) == 16
     assert C.sizeof(lib.PlanOptions) == 16
+
+
+@pytest.mark.parametrize("z_min", [0.0, -1.0, 1e-9, 1e7, float("nan")])
+def test_plan_create_rejects_z_min_out_of_range(lib, z_min):
+    _host_only()
+    with pytest.raises(lib.EpoError) as e:
+        lib.plan_create(**_plan_args(params=lib.CostParams(1.0, z_min, 0, 10.0)))
+    assert e.value.status == lib.ERR_INVALID_ARG and "z_min" in str(e.value)
