@@ -108,14 +108,13 @@ __global__ __launch_bounds__(256) void pair_setup_kernel(
 // integers; ft, fs are the focal-scale sums of the refinement variant
 struct Acc {
     double S, g0, g1, g2, g3, g4, g5;
-    int n;
     double ft, fs;
 };
 
 // the float32 terms of one residual
 struct Terms {
     float S, g0, g1, g2, g3, g4, g5, ft, fs, dz;
-    int n;
+    bool valid;
 };
 
 // refinement variant (EXT): besides the pose terms, per pair
@@ -134,7 +133,7 @@ __device__ __forceinline__ Terms residual(const uint2 rec, bool active, const Pa
     const Residual r = eval_residual<FMT>(rec, active, pd, texj, lut, delta, zmin);
     Terms t;
     t.S = r.rho;
-    t.n = r.valid ? 1 : 0;
+    t.valid = r.valid;
     t.g0 = r.Au * r.rz;
     t.g1 = r.Av * r.rz;
     t.g2 = r.w * r.rz;
@@ -187,7 +186,8 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
         c3[2] = R[8];
         if (dz) dzt = dz + res_base[tl.pair] + tl.rec;
     }
-    Acc a{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    Acc a{0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int n = 0;                                  // valid residuals of this thread
     // two residuals in flight per thread (about 50 VGPRs, so the SIMD keeps
     // eight waves to hide the record load and the dependent tap gather);
     // unrolling all P would multiply the float64 live ranges
@@ -199,20 +199,24 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
     for (int k0 = 0; k0 < rows; k0 += U) {
         uint2 r[U];
         // rows past the tile's end load its last record (in bounds, so both
-        // loads issue back to back without a branch) and are masked
+        // loads issue back to back without a branch) and are masked; the
+        // offset from the tile's first record is a 32-bit byte offset
 #pragma unroll
-        for (int k = 0; k < U; ++k) r[k] = rec[min((k0 + k) * kBlock + tid, tl.count - 1)];
+        for (int k = 0; k < U; ++k)
+            r[k] = *reinterpret_cast<const uint2*>(
+                reinterpret_cast<const char*>(rec) +
+                ((uint32_t)min((k0 + k) * kBlock + tid, tl.count - 1) << 3));
         Terms tt[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int idx = (k0 + k) * kBlock + tid;
             tt[k] = residual<FMT, EXT>(r[k], idx < tl.count, pd, texj, lut, delta, zmin, c3);
             if (EXT && dzt && idx < tl.count) dzt[idx] = tt[k].dz;
+            n += tt[k].valid ? 1 : 0;
         }
 #pragma unroll
         for (int k = 1; k < U; ++k) {
             tt[0].S += tt[k].S;
-            tt[0].n += tt[k].n;
             tt[0].g0 += tt[k].g0;
             tt[0].g1 += tt[k].g1;
             tt[0].g2 += tt[k].g2;
@@ -223,7 +227,6 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
             tt[0].fs += tt[k].fs;
         }
         a.S += (double)tt[0].S;
-        a.n += tt[0].n;
         a.g0 += (double)tt[0].g0;
         a.g1 += (double)tt[0].g1;
         a.g2 += (double)tt[0].g2;
@@ -237,8 +240,9 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
     }
     constexpr int NS = EXT ? 10 : 8;
     double s[NS];
+    const int wave = tid >> 6, lane = tid & 63;
     s[0] = a.S;
-    s[1] = (double)a.n;
+    s[1] = (double)n;
     s[2] = a.g0;
     s[3] = a.g1;
     s[4] = a.g2;
@@ -251,7 +255,6 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
     }
 #pragma unroll
     for (int k = 0; k < NS; ++k) s[k] = wave_sum(s[k]);
-    const int wave = tid >> 6, lane = tid & 63;
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < NS; ++k) red[wave][k] = s[k];

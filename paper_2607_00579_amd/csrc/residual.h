@@ -18,30 +18,39 @@
 
 namespace epo {
 
+// The tap loads address the view's texture with a 32-bit byte offset from a
+// wave-uniform base (the global_load "saddr" form: no 64-bit address
+// arithmetic per residual).  A view has at most 16384^2 pixels, so a 4-byte
+// texel offset fits in 32 bits; the 16-byte texels of format 3 do not, and use
+// a 64-bit index.
+__device__ __forceinline__ uint32_t texel32(const uint32_t* __restrict__ tex, uint32_t byte_off) {
+    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(tex) + byte_off);
+}
+
 template <int FMT>
 struct Taps;
 
 // float32 texture: four gathers
 template <>
 struct Taps<1> {
-    __device__ static inline void load(const uint32_t* __restrict__ tex, int idx, int W,
+    __device__ static inline void load(const uint32_t* __restrict__ tex, uint32_t idx, int W,
                                        const float* /*lut*/, float& d00, float& d10, float& d01,
                                        float& d11) {
-        const float* t = reinterpret_cast<const float*>(tex);
-        d00 = t[idx];
-        d10 = t[idx + 1];
-        d01 = t[idx + W];
-        d11 = t[idx + W + 1];
+        const uint32_t o = idx << 2, row = (uint32_t)W << 2;
+        d00 = __uint_as_float(texel32(tex, o));
+        d10 = __uint_as_float(texel32(tex, o + 4u));
+        d01 = __uint_as_float(texel32(tex, o + row));
+        d11 = __uint_as_float(texel32(tex, o + row + 4u));
     }
 };
 
 // saturated u8 quads: one gather, four LDS look-ups of sqrt(k)
 template <>
 struct Taps<2> {
-    __device__ static inline void load(const uint32_t* __restrict__ tex, int idx, int /*W*/,
+    __device__ static inline void load(const uint32_t* __restrict__ tex, uint32_t idx, int /*W*/,
                                        const float* lut, float& d00, float& d10, float& d01,
                                        float& d11) {
-        const uint32_t q = tex[idx];
+        const uint32_t q = texel32(tex, idx << 2);
         d00 = lut[q & 0xffu];
         d10 = lut[(q >> 8) & 0xffu];
         d01 = lut[(q >> 16) & 0xffu];
@@ -52,7 +61,7 @@ struct Taps<2> {
 // float32 quads: the four float32 taps of the cell in one 16-byte gather
 template <>
 struct Taps<3> {
-    __device__ static inline void load(const uint32_t* __restrict__ tex, int idx, int /*W*/,
+    __device__ static inline void load(const uint32_t* __restrict__ tex, uint32_t idx, int /*W*/,
                                        const float* /*lut*/, float& d00, float& d10, float& d01,
                                        float& d11) {
         const float4 q = reinterpret_cast<const float4*>(tex)[idx];
@@ -115,7 +124,8 @@ __device__ __forceinline__ Residual eval_residual(const uint2 rec, bool active,
     // with that zero weight is zero
     const float al = (float)(upd - fx0);
     const float be = (float)(vpd - fy0);
-    const int idx = valid ? (y0 * pd.width + x0) : 0;
+    // y0 < H and W are below 2^24 whenever the residual is valid
+    const uint32_t idx = valid ? (uint32_t)(__umul24(y0, pd.width) + x0) : 0u;
     r.xn = (float)xnd;
     r.yn = (float)ynd;
     r.rz = (float)rzd;
