@@ -186,7 +186,8 @@ EPO_API epo_status epo_plan_view_records(epo_plan plan, int32_t v, uint64_t* rec
  * kernel; supplementary Sec. A1.2 "Per-iteration kernels").
  * Per directed pair d = (i -> j): S_d = sum of H(min(D, lambda)) over valid
  * residuals, n_d = number of valid residuals, L_d = S_d / n_d (0 if n_d = 0);
- * loss[s] = (2 / |pairs of s|) sum_{d in s} L_d.
+ * loss[s] = (2 / |pairs of s|) sum_{d in s} L_d (with pair sub-sampling on,
+ * over the pairs drawn for this launch, see 3c).
  *
  *   poses       float64 [V][3][4]
  *   lambda      float32 [n_scenes] clamp per scene, each <= params.lambda_max
@@ -256,6 +257,36 @@ EPO_API epo_status epo_edge_cost_refine(epo_plan plan, const double* poses, cons
                                 const double* upstream, double* loss, double* grad,
                                 double* grad_gamma, double* grad_alpha, double* grad_beta,
                                 void* stream);
+
+/* ---------------------------------------------------------------------------
+ * 3c. Stochastic viewgraph sub-sampling (paper supplementary Sec. "Stochastic
+ * viewgraph sub-sampling"; pair budget M of Alg. EPO.Forward).  With a budget
+ * M > 0, every later cost launch of the plan (eager, and replays of an
+ * iteration captured afterwards) first draws, per scene, a fresh uniform
+ * random subset of min(|E_scene|, M) image pairs and evaluates only their
+ * directions; each scene's loss is then the mean over the evaluated
+ * directions, (2/|D_S|) sum_{d in D_S} L_d, and skipped pairs have zero cost,
+ * count, weight and gradient.  An image pair is an unordered {i, j}; pairs
+ * are numbered in order of first appearance in the plan's pair list.
+ *
+ * The draw is counter-based: pair g gets the key h(h(seed + step) + g), h the
+ * SplitMix64 output function (Steele, Lea, Flood, OOPSLA 2014), and the M
+ * pairs with the smallest (key, g) are taken.
+ *
+ *   budget  M image pairs per scene per step; 0 = every pair (sub-sampling off)
+ *   seed    64-bit seed of the draw
+ *   step    int32 [1] device step counter read at every launch (eager
+ *           launches); must stay valid while sampling is on.  A captured
+ *           iteration reads its own step counter instead (the one it
+ *           increments), so every replay draws a new subset.
+ * Synchronises `stream` and drops a captured iteration (capture again).
+ *
+ * epo_plan_sampled_pairs writes, per directed pair, 1 if it was evaluated by
+ * the plan's last cost launch and 0 if skipped (uint8 [n_pairs], device).
+ * ------------------------------------------------------------------------- */
+EPO_API epo_status epo_plan_set_pair_sampling(epo_plan plan, int32_t budget, uint64_t seed,
+                                      const int32_t* step, void* stream);
+EPO_API epo_status epo_plan_sampled_pairs(epo_plan plan, uint8_t* selected, void* stream);
 
 /* ---------------------------------------------------------------------------
  * 4. pose_step

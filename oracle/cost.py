@@ -195,23 +195,37 @@ class OracleProblem:
         return out
 
     # ------------------------------------------------------------------
-    def weights(self, S, n, n_src, params: CostParams):
-        """Per-pair mean L_d and weight w_d = (2/|D_scene|) / denominator."""
+    def weights(self, S, n, n_src, params: CostParams, selected=None):
+        """Per-pair mean L_d and weight w_d = (2/|D_scene|) / denominator.
+        With a boolean mask `selected` over directed pairs (a sub-sampled
+        step), |D_scene| counts the selected pairs of the scene and an
+        unselected pair has scale and weight 0."""
         den = n if params.norm_mode == 0 else n_src
         den = np.asarray(den, np.float64)
         L = np.where(den > 0, np.asarray(S) / np.where(den > 0, den, 1.0), 0.0)
-        scale = 2.0 / self.pairs_per_scene[self.scene_of_pair].astype(np.float64)
+        if selected is None:
+            count = self.pairs_per_scene
+            scale = 2.0 / count[self.scene_of_pair].astype(np.float64)
+        else:
+            selected = np.asarray(selected, bool)
+            count = np.bincount(self.scene_of_pair[selected], minlength=self.n_scenes)
+            scale = np.where(selected, 2.0 / np.maximum(count[self.scene_of_pair], 1), 0.0)
         w = np.where(den > 0, scale / np.where(den > 0, den, 1.0), 0.0)
         return L, w, scale
 
     def evaluate(self, poses: np.ndarray, lam, params: CostParams = CostParams(),
-                 frozen=None, pair_ids=None, K=None, depth=None):
+                 frozen=None, pair_ids=None, K=None, depth=None, selected=None):
         """Loss per scene, per-pair S, n, L_d, G, the gradient per view, the
         focal-scale gradient per view (grad_focal) and the depth gradient of
-        every edge pixel (grad_depth: {view: array in edge-pixel order})."""
+        every edge pixel (grad_depth: {view: array in edge-pixel order}).
+        `selected` (boolean mask over directed pairs) evaluates one
+        sub-sampled step: only those pairs, each scene's loss the mean over
+        its selected pairs."""
         lam = np.broadcast_to(np.asarray(lam, np.float64), (self.n_scenes,))
         D = self.pairs.shape[0]
         ids = range(D) if pair_ids is None else pair_ids
+        if selected is not None:
+            ids = [d for d in ids if selected[d]]
         S = np.zeros(D)
         n = np.zeros(D, np.int64)
         n_src = np.zeros(D, np.int64)
@@ -230,7 +244,7 @@ class OracleProblem:
             F_tgt[d], F_src[d] = r["F_tgt"], r["F_src"]
             dZ[d] = r["dZ"]
             decisions[d] = r["decisions"]
-        L, w, scale = self.weights(S, n, n_src, params)
+        L, w, scale = self.weights(S, n, n_src, params, selected)
         loss = np.zeros(self.n_scenes)
         grad = np.zeros((self.V, 6))
         grad_focal = np.zeros(self.V)

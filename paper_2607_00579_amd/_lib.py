@@ -52,6 +52,8 @@ _SIGS = {
     "epo_edge_cost_fwd": [P, P, P, P, P, P, P, P, P],
     "epo_edge_cost_bwd": [P, P, P, P, P, P],
     "epo_plan_set_refinement": [P, P, P, P, P],
+    "epo_plan_set_pair_sampling": [P, I32, C.c_uint64, P, P],
+    "epo_plan_sampled_pairs": [P, P, P],
     "epo_edge_cost_refine": [P, P, P, P, P, P, P, P, P, P],
     "epo_pose_step": [P, P, P, P, I32, P, P, P, F64, F64, F64, P, P],
     "epo_schedule": [P, I32, F32, F32, I32, F64, I32, I32, P, P, P],
@@ -166,6 +168,14 @@ def edge_cost_bwd(plan, poses, lam, upstream, grad, stream):
 
 def plan_set_refinement(plan, gamma, alpha, beta, stream):
     _check(load().epo_plan_set_refinement(plan, _ptr(gamma), _ptr(alpha), _ptr(beta), stream))
+
+
+def plan_set_pair_sampling(plan, budget, seed, step, stream):
+    _check(load().epo_plan_set_pair_sampling(plan, budget, seed, _ptr(step), stream))
+
+
+def plan_sampled_pairs(plan, selected, stream):
+    _check(load().epo_plan_sampled_pairs(plan, _ptr(selected), stream))
 
 
 def edge_cost_refine(plan, poses, lam, upstream, loss, grad, grad_gamma, grad_alpha, grad_beta,

@@ -188,6 +188,27 @@ class EdgePlan:
                               _stream(self.device))
         return o
 
+    # ------------------------------------------------------------------
+    # stochastic viewgraph sub-sampling
+    def set_pair_sampling(self, budget: int, seed: int = 0, step=None):
+        """Evaluate min(|E_scene|, budget) random image pairs per scene per
+        launch (0 = every pair).  `step` is the int32 device counter the draw
+        reads in eager launches (a captured iteration uses its own)."""
+        if budget and step is None:
+            raise ValueError("sub-sampling needs a device step counter")
+        if step is not None:
+            if step.dtype != torch.int32 or step.device != self.device or step.numel() != 1:
+                raise ValueError("step must be one int32 on the plan's device")
+            self._sample_step = step               # keep it alive while in use
+        _lib.plan_set_pair_sampling(self.handle, int(budget), int(seed) & ((1 << 64) - 1),
+                                    step if budget else None, _stream(self.device))
+
+    def sampled_pairs(self) -> torch.Tensor:
+        """Directed pairs evaluated by the last cost launch (bool [n_pairs])."""
+        out = torch.empty(max(self.n_pairs, 1), dtype=torch.uint8, device=self.device)
+        _lib.plan_sampled_pairs(self.handle, out, _stream(self.device))
+        return out[: self.n_pairs].bool()
+
     def pose_step(self, poses, m, v, grad, lr, step, fixed_mask=None, beta1=0.9, beta2=0.999,
                   eps=1e-8):
         if not torch.is_tensor(lr):

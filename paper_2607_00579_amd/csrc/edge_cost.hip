@@ -170,10 +170,14 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
                                         Partial* __restrict__ partials,
                                         double* __restrict__ ext_partials,
                                         const int64_t* __restrict__ res_base,
-                                        float* __restrict__ dz, const float* lut,
+                                        float* __restrict__ dz,
+                                        const double* __restrict__ pair_scale, const float* lut,
                                         double (*red)[10], float delta, double zmin) {
     const int tid = threadIdx.x;
     const Tile tl = tiles[t];
+    // a pair skipped by this step's sub-sampling: no work, no partials (the
+    // pair reduction reads none for it)
+    if (pair_scale[tl.pair] == 0.0) return;
     const PairDesc pd = desc[tl.pair];
     const uint32_t* texj = tex + pd.tex_off;
     const uint2* rec = records + tl.rec;
@@ -275,7 +279,8 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
     const Tile* __restrict__ tiles, const PairDesc* __restrict__ desc,
     const double* __restrict__ rel, Partial* __restrict__ partials,
     double* __restrict__ ext_partials, const int64_t* __restrict__ res_base,
-    float* __restrict__ dz, const int64_t* __restrict__ xcd_begin, int32_t n_queues,
+    float* __restrict__ dz, const double* __restrict__ pair_scale,
+    const int64_t* __restrict__ xcd_begin, int32_t n_queues,
     int32_t* __restrict__ counters, int32_t persistent, float delta, double zmin) {
     __shared__ float lut[256];
     __shared__ double red[4][10];
@@ -289,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
         const int64_t t = xcd_begin[q0] + blockIdx.x / (unsigned)n_queues;
         if (t >= xcd_begin[q0 + 1]) return;
         do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials, res_base,
-                             dz, lut, red, delta, zmin);
+                             dz, pair_scale, lut, red, delta, zmin);
         return;
     }
     // persistent: claim tiles from the own queue, then from the others
@@ -303,7 +308,7 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
             __syncthreads();
             if (t >= end) break;
             do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials,
-                                 res_base, dz, lut, red, delta, zmin);
+                                 res_base, dz, pair_scale, lut, red, delta, zmin);
             __syncthreads();
         }
     }
@@ -329,8 +334,8 @@ void launch_cost_kernel(Plan& p, float* dz, hipStream_t s) {
     if (grid == 0) return;
     edge_cost_kernel<FMT, P, EXT><<<grid, kBlock, 0, s>>>(
         reinterpret_cast<const uint2*>(p.records.p), tex, p.tiles.p, p.pair_desc.p, p.pair_rel.p,
-        p.partials.p, EXT ? p.ext_partials.p : nullptr, p.pair_res_base.p, dz, p.xcd_begin_d.p,
-        nq, p.counters.p,
+        p.partials.p, EXT ? p.ext_partials.p : nullptr, p.pair_res_base.p, dz, p.pair_scale.p,
+        p.xcd_begin_d.p, nq, p.counters.p,
         p.opt.persistent == 1 ? 1 : 0, p.params.huber_delta, p.params.z_min);
     EPO_CHECK_LAUNCH();
 }
@@ -363,6 +368,8 @@ void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss
                  double* pair_cost, int32_t* pair_valid, double* pair_grad, double* grad,
                  const double* upstream, hipStream_t s, const RefineOut* ext) {
     if (p.D > 0) {
+        // this step's pair subset (stochastic sub-sampling), if enabled
+        launch_pair_selection(p, p.capture_step ? p.capture_step : p.sample_step, s);
         pair_setup_kernel<<<(unsigned)ceil_div(std::max(p.D, 16), 256), 256, 0, s>>>(
             poses, p.K_d.p, p.wh_d.p, p.view_offset_d.p, p.pair_static.p, lambda,
             p.params.lambda_max, p.pair_desc.p, p.pair_rel.p, p.D, p.counters.p, 8, p.status.p);

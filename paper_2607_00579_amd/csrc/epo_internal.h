@@ -110,7 +110,7 @@ struct PairStatic {
     int32_t src, tgt, scene;
     int32_t first_tile, n_tiles;
     int32_t n_src;          // source edge count |E_i|
-    float scale;            // 2 / (pairs in the scene)
+    int32_t group;          // image pair {i, j} the direction belongs to
     int32_t pad;
 };
 
@@ -150,6 +150,7 @@ struct Plan {
     std::vector<int64_t> view_offset;     // V
     std::vector<int64_t> rec_off;         // V + 1 record offsets
     std::vector<int32_t> pairs;           // D x 2
+    std::vector<int32_t> group_host;      // D: image pair of each direction
     int64_t total_px = 0;
     int64_t n_residuals = 0;
 
@@ -169,6 +170,8 @@ struct Plan {
     DevBuf<Partial> partials;             // T
     DevBuf<double> pair_sum;              // D x 8: S, n, G[6] (float64)
     DevBuf<double> pair_w;                // D: weight w_d
+    DevBuf<double> pair_scale;            // D: 2 / (pairs of the scene in this step), 0 = skipped
+    DevBuf<double> pair_scale_all;        // D: 2 / (pairs of the scene): every pair evaluated
     DevBuf<double> ext_partials;          // T x 2: focal-scale sums F_t, F_s per tile
     DevBuf<double> pair_ext;              // D x 2: F_t, F_s per pair
     DevBuf<int32_t> view_in_idx, view_in_ptr;     // CSR: pairs with tgt == v
@@ -179,6 +182,19 @@ struct Plan {
     DevBuf<int64_t> xcd_begin_d;          // 9 entries: tile range of each queue
     DevBuf<int32_t> status;               // device status word
     DevBuf<int32_t> scene_view_ptr, scene_view_idx;   // CSR: views of each scene
+    // stochastic pair sub-sampling: image pairs (groups of one or two
+    // directions) numbered in order of first appearance in the pair list
+    int32_t n_groups = 0;
+    DevBuf<int32_t> group_of_pair;        // D: scene-major group slot of each direction
+    DevBuf<int32_t> group_npairs;         // G slots: directions held (1 or 2)
+    DevBuf<int32_t> group_id_sorted;      // G slots: group id (first-appearance order)
+    std::vector<int32_t> group_id_sorted_h;
+    DevBuf<int32_t> scene_group_ptr;      // S + 1: groups of scene s are [ptr[s], ptr[s+1])
+    DevBuf<uint8_t> group_sel;            // G slots: selected in the last launch
+    int32_t sample_budget = 0;            // M image pairs per scene per step; 0 = all
+    uint64_t sample_seed = 0;
+    const int32_t* sample_step = nullptr;   // device step counter read by the selection
+    const int32_t* capture_step = nullptr;  // the captured iteration's counter (during capture)
     int32_t max_views_per_scene = 0;
     DevBuf<double> conv_prev;             // V x 12 poses of the previous step
     DevBuf<ConvState> conv_state;         // S
@@ -216,6 +232,8 @@ struct Plan {
 
 // schedule (tile list) construction; (re)allocates tiles and partials
 void build_tiles(Plan& p, hipStream_t stream);
+// drops a captured iteration (after any change of what it would launch)
+void release_graph(Plan& p);
 
 // outputs of the refinement variant (each may be null)
 struct RefineOut {
@@ -241,6 +259,7 @@ void launch_schedule(const int32_t* step, int32_t n_scenes, float lambda0, float
                      float* lambda_out, double* lr_out, const int32_t* phase,
                      hipStream_t stream);
 void launch_convergence(Plan& p, const double* poses, double* theta_out, hipStream_t stream);
+void launch_pair_selection(Plan& p, const int32_t* step, hipStream_t stream);
 void launch_convergence_reset(Plan& p, const double* poses, hipStream_t stream);
 void build_texture(Plan& p, const int32_t* d2, hipStream_t stream);
 

@@ -27,6 +27,7 @@
 #include <cstring>
 #include <memory>
 #include <numeric>
+#include <unordered_map>
 
 #include "epo_internal.h"
 
@@ -154,14 +155,14 @@ void fill_default_options(Plan& p, epo_plan_options& o) {
     if (o.persistent == 0) o.persistent = 2;
 }
 
+}  // namespace
+
 void release_graph(Plan& p) {
     if (p.graph_exec) (void)hipGraphExecDestroy(p.graph_exec);
     if (p.graph) (void)hipGraphDestroy(p.graph);
     p.graph_exec = nullptr;
     p.graph = nullptr;
 }
-
-}  // namespace
 
 Plan::~Plan() {
     release_graph(*this);
@@ -193,7 +194,7 @@ void build_tiles(Plan& p, hipStream_t s) {
         st.scene = p.scene_of_view[i];
         st.first_tile = (int32_t)tiles.size();
         st.n_src = (int32_t)n;
-        st.scale = (float)(2.0 / (double)per_scene[st.scene]);
+        st.group = p.group_host[d];
         st.pad = 0;
         for (int64_t c = 0; c < n; c += ts) {
             Tile t;
@@ -302,6 +303,19 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
                         "pair " + std::to_string(d) + ": view index out of range");
             EPO_REQUIRE(p->scene_of_view[i] == p->scene_of_view[j],
                         "pair " + std::to_string(d) + ": views of different scenes");
+        }
+        {
+            // image pairs {i, j}: ids in order of first appearance
+            p->group_host.assign(n_pairs, 0);
+            std::unordered_map<uint64_t, int32_t> ids;
+            ids.reserve((size_t)n_pairs);
+            for (int d = 0; d < n_pairs; ++d) {
+                const uint64_t a = (uint64_t)std::min(p->pairs[2 * d], p->pairs[2 * d + 1]);
+                const uint64_t b = (uint64_t)std::max(p->pairs[2 * d], p->pairs[2 * d + 1]);
+                const auto it = ids.emplace((a << 32) | b, p->n_groups);
+                if (it.second) p->n_groups++;
+                p->group_host[d] = it.first->second;
+            }
         }
         if (options) {
             p->opt = *options;
@@ -425,6 +439,49 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
             for (const auto& l : sv)
                 p->max_views_per_scene = std::max<int32_t>(p->max_views_per_scene, (int32_t)l.size());
             csr(sv, p->scene_view_ptr, p->scene_view_idx);
+        }
+        {
+            // groups per scene (group ids increase with first appearance, and
+            // a scene's groups are listed in id order), directions per group,
+            // and the every-pair scales 2 / |D_scene|
+            std::vector<int32_t> g_np(std::max(p->n_groups, 1), 0), g_scene(std::max(p->n_groups, 1), 0);
+            for (int d = 0; d < n_pairs; ++d) {
+                g_np[p->group_host[d]] += 1;
+                g_scene[p->group_host[d]] = p->scene_of_view[p->pairs[2 * d]];
+            }
+            std::vector<std::vector<int32_t>> sg(S);
+            for (int g = 0; g < p->n_groups; ++g) sg[g_scene[g]].push_back(g);
+            std::vector<int32_t> gptr(S + 1, 0), gidx;
+            for (int k = 0; k < S; ++k) {
+                gptr[k + 1] = gptr[k] + (int32_t)sg[k].size();
+                gidx.insert(gidx.end(), sg[k].begin(), sg[k].end());
+            }
+            // the selection kernel walks a scene's groups as the id range
+            // [gptr[s], gptr[s+1]) of a scene-major renumbering
+            std::vector<int32_t> renum(std::max(p->n_groups, 1), 0);
+            for (int k = 0; k < (int)gidx.size(); ++k) renum[gidx[k]] = k;
+            std::vector<int32_t> gop(std::max(n_pairs, 1), 0), np_sorted(std::max(p->n_groups, 1), 0);
+            std::vector<int32_t> gid_sorted(std::max(p->n_groups, 1), 0);
+            for (int d = 0; d < n_pairs; ++d) gop[d] = renum[p->group_host[d]];
+            for (int g = 0; g < p->n_groups; ++g) {
+                np_sorted[renum[g]] = g_np[g];
+                gid_sorted[renum[g]] = g;
+            }
+            p->group_id_sorted_h = gid_sorted;
+            std::vector<int32_t> per_scene(S, 0);
+            for (int d = 0; d < n_pairs; ++d) per_scene[p->scene_of_view[p->pairs[2 * d]]]++;
+            std::vector<double> scale(std::max(n_pairs, 1), 0.0);
+            for (int d = 0; d < n_pairs; ++d)
+                scale[d] = 2.0 / (double)per_scene[p->scene_of_view[p->pairs[2 * d]]];
+            upload(p->group_of_pair, gop, s);
+            upload(p->group_npairs, np_sorted, s);
+            upload(p->group_id_sorted, gid_sorted, s);
+            upload(p->scene_group_ptr, gptr, s);
+            upload(p->pair_scale_all, scale, s);
+            upload(p->pair_scale, scale, s);
+            p->group_sel.alloc(std::max(p->n_groups, 1));
+            EPO_HIP(hipMemsetAsync(p->group_sel.p, 1, p->group_sel.n, s));
+            EPO_HIP(hipStreamSynchronize(s));
         }
         p->conv_prev.alloc(12 * (size_t)n_views);
         p->conv_state.alloc(S);
@@ -611,6 +668,7 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
             throw Failure{EPO_ERR_HIP, std::string("hipStreamBeginCapture: ") +
                                            hipGetErrorString(cap)};
         }
+        p.capture_step = step;               // the selection reads the iteration's counter
         try {
             launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
                             p.lambda_buf.p, p.lr_buf.p,
@@ -625,9 +683,11 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
             if (junk) (void)hipGraphDestroy(junk);
             (void)hipStreamDestroy(cs);
             p.timing = timing;
+            p.capture_step = nullptr;
             throw;
         }
         p.timing = timing;
+        p.capture_step = nullptr;
         hipError_t e = hipStreamEndCapture(cs, &p.graph);
         (void)hipStreamDestroy(cs);
         if (e != hipSuccess)

@@ -2,7 +2,9 @@
 // order (bitwise reproducible whatever the launch schedule):
 //   per pair   S_d, n_d, G_d = sum of its tiles in tile order; L_d = S_d / n_d
 //              (Alg. 3 mean over valid residuals; |E_i| in norm mode 1) and the
-//              pose weight w_d = (2 / |D_scene|) / n_d
+//              pose weight w_d = (2 / |D_scene|) / n_d, where |D_scene| counts
+//              the pairs evaluated in this step (all of them, or the
+//              sub-sampled ones; a skipped pair has scale and weight 0)
 //   per pose   g_v = sum over pairs into v of w_d G_d
 //                  - sum over pairs out of v of w_d Ad(T_ji)^T G_d
 //              (the source pose sees the target's left perturbation moved
@@ -29,22 +31,26 @@ __device__ inline double wave_sum64(double x) {
 
 __global__ __launch_bounds__(256) void reduce_pairs_kernel(
     const Partial* __restrict__ partials, const double* __restrict__ ext_partials,
-    const PairStatic* __restrict__ ps, int32_t D, int32_t norm_mode,
-    double* __restrict__ pair_sum, double* __restrict__ pair_w, double* __restrict__ pair_ext,
-    double* __restrict__ pair_cost, int32_t* __restrict__ pair_valid,
-    double* __restrict__ pair_grad, int32_t* __restrict__ status) {
+    const PairStatic* __restrict__ ps, const double* __restrict__ pair_scale, int32_t D,
+    int32_t norm_mode, double* __restrict__ pair_sum, double* __restrict__ pair_w,
+    double* __restrict__ pair_ext, double* __restrict__ pair_cost,
+    int32_t* __restrict__ pair_valid, double* __restrict__ pair_grad,
+    int32_t* __restrict__ status) {
     const int d = blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= D) return;
     const PairStatic st = ps[d];
+    const double scale = pair_scale[d];
+    // a pair skipped by the sub-sampling of this step ran no tiles: all zero
+    const int n_tiles = scale != 0.0 ? st.n_tiles : 0;
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < st.n_tiles; ++k) {
+    for (int k = 0; k < n_tiles; ++k) {
         const Partial pt = partials[st.first_tile + k];
 #pragma unroll
         for (int c = 0; c < 8; ++c) s[c] += pt.v[c];
     }
     if (ext_partials) {
         double ft = 0.0, fs = 0.0;
-        for (int k = 0; k < st.n_tiles; ++k) {
+        for (int k = 0; k < n_tiles; ++k) {
             ft += ext_partials[2 * (int64_t)(st.first_tile + k)];
             fs += ext_partials[2 * (int64_t)(st.first_tile + k) + 1];
         }
@@ -54,7 +60,7 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(
     }
     const double den = norm_mode == 0 ? s[1] : (double)st.n_src;
     const double L = den > 0 ? s[0] / den : 0.0;
-    const double w = den > 0 ? (double)st.scale / den : 0.0;
+    const double w = den > 0 ? scale / den : 0.0;
     if (!isfinite(s[0]) || !isfinite(s[2]) || !isfinite(s[5])) atomicOr(status, 1);
 #pragma unroll
     for (int c = 0; c < 8; ++c) pair_sum[8 * d + c] = s[c];
@@ -125,8 +131,8 @@ __global__ __launch_bounds__(256) void reduce_views_kernel(
 // one workgroup per scene
 __global__ __launch_bounds__(256) void reduce_scenes_kernel(
     const double* __restrict__ pair_sum, const PairStatic* __restrict__ ps,
-    const int32_t* __restrict__ scene_ptr, const int32_t* __restrict__ scene_pairs,
-    int32_t norm_mode, double* __restrict__ loss) {
+    const double* __restrict__ pair_scale, const int32_t* __restrict__ scene_ptr,
+    const int32_t* __restrict__ scene_pairs, int32_t norm_mode, double* __restrict__ loss) {
     __shared__ double part[4];
     const int s = blockIdx.x;
     double L = 0.0;
@@ -134,7 +140,7 @@ __global__ __launch_bounds__(256) void reduce_scenes_kernel(
         const int d = scene_pairs[k];
         const PairStatic st = ps[d];
         const double den = norm_mode == 0 ? pair_sum[8 * d + 1] : (double)st.n_src;
-        if (den > 0) L += (double)st.scale * (pair_sum[8 * d + 0] / den);
+        if (den > 0) L += pair_scale[d] * (pair_sum[8 * d + 0] / den);
     }
     L = wave_sum64(L);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = L;
@@ -149,9 +155,9 @@ void launch_reductions(Plan& p, double* loss, double* pair_cost, int32_t* pair_v
                        double* grad_gamma) {
     if (p.D > 0) {
         reduce_pairs_kernel<<<(unsigned)ceil_div(p.D, 256), 256, 0, s>>>(
-            p.partials.p, grad_gamma ? p.ext_partials.p : nullptr, p.pair_static.p, p.D,
-            p.params.norm_mode, p.pair_sum.p, p.pair_w.p, p.pair_ext.p, pair_cost, pair_valid,
-            pair_grad, p.status.p);
+            p.partials.p, grad_gamma ? p.ext_partials.p : nullptr, p.pair_static.p,
+            p.pair_scale.p, p.D, p.params.norm_mode, p.pair_sum.p, p.pair_w.p, p.pair_ext.p,
+            pair_cost, pair_valid, pair_grad, p.status.p);
         EPO_CHECK_LAUNCH();
     }
     if (grad || grad_gamma) {
@@ -163,8 +169,9 @@ void launch_reductions(Plan& p, double* loss, double* pair_cost, int32_t* pair_v
     }
     if (loss) {
         reduce_scenes_kernel<<<(unsigned)p.S, 256, 0, s>>>(p.pair_sum.p, p.pair_static.p,
-                                                            p.scene_ptr.p, p.scene_pairs.p,
-                                                            p.params.norm_mode, loss);
+                                                            p.pair_scale.p, p.scene_ptr.p,
+                                                            p.scene_pairs.p, p.params.norm_mode,
+                                                            loss);
         EPO_CHECK_LAUNCH();
     }
 }
