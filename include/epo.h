@@ -259,6 +259,37 @@ EPO_API epo_status epo_edge_cost_refine(epo_plan plan, const double* poses, cons
                                 void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Viewgraph estimation (paper Sec. 3 "Viewgraph Estimation", Sec. 4
+ * "Implementation Details"; construction kernels of the supplementary
+ * material).  For every candidate pair (i, j), each pixel p = (a s, b s) of
+ * the stride-s grid over image i with depth Z_i(p) > 0 (finite) is projected
+ * into j and back:
+ *   p_ij  = pi(K_i, K_j, P_i, P_j, Z_i; p)   (target depth must exceed z_min)
+ *   p_iji = pi(K_j, K_i, P_j, P_i, Z_j; p_ij), Z_j read at the pixel nearest to
+ *           p_ij (inside image j, depth > 0), back depth above z_min,
+ * and counted consistent when |p - p_iji|^2 < tau^2.  total[c] counts the grid
+ * points with depth, consistent[c] the consistent ones, and valid[c] =
+ * (total > 0 and consistent >= min_fraction * total).  The paper's values:
+ * tau = 3 px, min_fraction = 0.125.  Every decision is taken in float64 with
+ * one rounding per operation (no fused multiply-add) in a fixed order.
+ *
+ *   width, height, K, view_offset   host, per view (K = fx, fy, cx, cy)
+ *   depth        float32 dense depth maps, view v at view_offset[v] (elements),
+ *                row-major H x W (device)
+ *   poses        float64 [V][3][4] world->camera (device)
+ *   candidates   int32 [n_candidates][2] (i, j) (host)
+ *   consistent, total   int32 [n_candidates] (device, written)
+ *   valid        uint8 [n_candidates] (device, written) or NULL
+ * Setup-time call: allocates staging buffers and synchronises `stream`.
+ * ------------------------------------------------------------------------- */
+EPO_API epo_status epo_build_viewgraph(int32_t n_views, const int32_t* width, const int32_t* height,
+                               const float* K, const int64_t* view_offset, const float* depth,
+                               const double* poses, const int32_t* candidates,
+                               int32_t n_candidates, int32_t stride, double tau,
+                               double min_fraction, double z_min, int32_t* consistent,
+                               int32_t* total, uint8_t* valid, void* stream);
+
+/* ---------------------------------------------------------------------------
  * 3c. Stochastic viewgraph sub-sampling (paper supplementary Sec. "Stochastic
  * viewgraph sub-sampling"; pair budget M of Alg. EPO.Forward).  With a budget
  * M > 0, every later cost launch of the plan (eager, and replays of an

@@ -53,6 +53,7 @@ _SIGS = {
     "epo_edge_cost_bwd": [P, P, P, P, P, P],
     "epo_plan_set_refinement": [P, P, P, P, P],
     "epo_plan_set_pair_sampling": [P, I32, C.c_uint64, P, P],
+    "epo_build_viewgraph": [I32, P, P, P, P, P, P, P, I32, I32, F64, F64, F64, P, P, P, P],
     "epo_plan_sampled_pairs": [P, P, P],
     "epo_edge_cost_refine": [P, P, P, P, P, P, P, P, P, P],
     "epo_pose_step": [P, P, P, P, I32, P, P, P, F64, F64, F64, P, P],
@@ -168,6 +169,15 @@ def edge_cost_bwd(plan, poses, lam, upstream, grad, stream):
 
 def plan_set_refinement(plan, gamma, alpha, beta, stream):
     _check(load().epo_plan_set_refinement(plan, _ptr(gamma), _ptr(alpha), _ptr(beta), stream))
+
+
+def build_viewgraph(n_views, width, height, K, view_offset, depth, poses, candidates,
+                    n_candidates, stride, tau, min_fraction, z_min, consistent, total, valid,
+                    stream):
+    _check(load().epo_build_viewgraph(n_views, _ptr(width), _ptr(height), _ptr(K),
+                                      _ptr(view_offset), _ptr(depth), _ptr(poses),
+                                      _ptr(candidates), n_candidates, stride, tau, min_fraction,
+                                      z_min, _ptr(consistent), _ptr(total), _ptr(valid), stream))
 
 
 def plan_set_pair_sampling(plan, budget, seed, step, stream):

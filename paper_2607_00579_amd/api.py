@@ -40,6 +40,37 @@ def build_distance_fields(edge_flat: torch.Tensor, view_offset, width, height):
     return d2, dtf
 
 
+def build_viewgraph(depth_flat: torch.Tensor, width, height, K, view_offset, poses: torch.Tensor,
+                    scene_of_view, stride=4, tau=3.0, min_fraction=0.125, z_min=1e-4):
+    """Cycle-consistent reprojection test of every pair (i < j) of views of the
+    same scene.  Returns the candidates (int32 [n, 2], host), the device
+    counts (consistent, total), the validity flags and the directed pair list
+    (both directions of every valid pair, host int32 [m, 2])."""
+    dev = depth_flat.device
+    w = np.ascontiguousarray(width, np.int32)
+    h = np.ascontiguousarray(height, np.int32)
+    k = np.ascontiguousarray(K, np.float32).reshape(-1, 4)
+    vo = np.ascontiguousarray(view_offset, np.int64)[: w.size]
+    sov = np.ascontiguousarray(scene_of_view, np.int64)
+    n = w.size
+    iu, ju = np.triu_indices(n, 1)
+    same = sov[iu] == sov[ju]
+    cand = np.ascontiguousarray(np.stack([iu[same], ju[same]], axis=1).astype(np.int32))
+    nc = cand.shape[0]
+    cons = torch.zeros(max(nc, 1), dtype=torch.int32, device=dev)
+    tot = torch.zeros(max(nc, 1), dtype=torch.int32, device=dev)
+    valid = torch.zeros(max(nc, 1), dtype=torch.uint8, device=dev)
+    _lib.build_viewgraph(n, w, h, k, vo, depth_flat.contiguous(), poses.contiguous(), cand, nc,
+                         int(stride), float(tau), float(min_fraction), float(z_min), cons, tot,
+                         valid, _stream(dev))
+    v = valid[:nc].bool().cpu().numpy()
+    kept = cand[v]
+    directed = np.concatenate([kept, kept[:, ::-1]]).astype(np.int32) if kept.size else \
+        np.zeros((0, 2), np.int32)
+    return dict(candidates=cand, consistent=cons[:nc], total=tot[:nc], valid=valid[:nc].bool(),
+                pairs=np.ascontiguousarray(directed))
+
+
 class EdgePlan:
     """A problem resident on one GPU: edge records, sampling textures, tile
     schedule and per-iteration buffers, owned by a libepo plan."""
