@@ -206,6 +206,69 @@ def refine_timing(plan, poses, lam, steps, warmup, R):
     return res
 
 
+def sampled_timing(plan, prob, steps, warmup, budgets=(1024, 256, 64)):
+    """Captured iterations with stochastic viewgraph sub-sampling: each scene
+    evaluates min(|E_scene|, M) random image pairs per step (both
+    directions), a fresh draw every replay."""
+    import numpy as np
+    import torch
+    dev = plan.device
+    res = {}
+    counts = prob.edge_counts()
+    for M in budgets:
+        poses = torch.from_numpy(prob.poses_init.copy()).to(dev)
+        m = torch.zeros(prob.n_views, 6, dtype=torch.float64, device=dev)
+        v = torch.zeros_like(m)
+        step = torch.zeros(1, dtype=torch.int32, device=dev)
+        loss = torch.zeros(plan.n_scenes, dtype=torch.float64, device=dev)
+        plan.set_pair_sampling(M, 1, step)
+        plan.capture_iteration(poses, m, v, step, loss)
+        for _ in range(warmup):
+            plan.launch_iteration()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.launch_iteration()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        sel = plan.sampled_pairs().cpu().numpy()
+        r = int(counts[prob.pairs[sel, 0]].sum())
+        res[f"M={M}"] = {"ms_per_step": round(ms, 4), "directed_pairs": int(sel.sum()),
+                         "residuals_last_step": r, "residuals_per_s": r / (ms * 1e-3)}
+        log(f"sub-sampled M={M}: {ms:.3f} ms/step, {int(sel.sum())} of {sel.size} directed pairs")
+    plan.set_pair_sampling(0)
+    return res
+
+
+def viewgraph_timing(name="c3", stride=4):
+    """Viewgraph construction (cycle-consistent reprojection of a stride-4
+    pixel grid of every view into every other view of its scene and back) on
+    the 32-view workload with dense room depth."""
+    import numpy as np
+    import torch
+    from paper_2607_00579_amd.api import build_viewgraph
+    from synth import make
+    from synth.dense import dense_depth
+    p = make(name)
+    depth = torch.from_numpy(dense_depth(p, sigma=0.005, seed=1)).cuda()
+    poses = torch.from_numpy(p.poses_init.copy()).cuda()
+    args = (depth, p.width, p.height, p.K, p.view_offset, poses, p.scene_of_view)
+    build_viewgraph(*args, stride=stride)            # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = build_viewgraph(*args, stride=stride)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    trips = int(g["total"].sum().item())
+    log(f"viewgraph {name}: {ms:.2f} ms for {g['candidates'].shape[0]} candidate pairs")
+    return {"workload": f"{name}: {WORKLOADS[name]}", "candidates": int(g["candidates"].shape[0]),
+            "valid": int(g["valid"].sum().item()), "grid_stride": stride,
+            "round_trips": trips, "ms_wall": round(ms, 3),
+            "round_trips_per_s": trips / (ms * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +283,8 @@ def main():
     ap.add_argument("--options", default=None, help="JSON plan options (skips the autotuner)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only eager fused-kernel launches (for profilers)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the sub-sampled step and viewgraph timings")
     ap.add_argument("--refine-only", action="store_true",
                     help="only eager joint-phase calls with depth gradients (for profilers)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -342,6 +407,9 @@ def main():
 
     if not args.no_refine:
         out["refine"] = refine_timing(plan, poses, lam, args.steps, args.warmup, R_expected)
+    if not args.no_extras:
+        out["sub_sampled"] = sampled_timing(plan, prob, args.steps, args.warmup)
+        out["viewgraph"] = viewgraph_timing()
 
     # free what the baselines do not need
     dtf_flat = plan.dtf

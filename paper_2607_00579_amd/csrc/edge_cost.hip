@@ -280,36 +280,56 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
     const double* __restrict__ rel, Partial* __restrict__ partials,
     double* __restrict__ ext_partials, const int64_t* __restrict__ res_base,
     float* __restrict__ dz, const double* __restrict__ pair_scale,
-    const int64_t* __restrict__ xcd_begin, int32_t n_queues,
-    int32_t* __restrict__ counters, int32_t persistent, float delta, double zmin) {
+    const int64_t* __restrict__ xcd_begin, const int32_t* __restrict__ tile_list,
+    int32_t n_queues, int32_t* __restrict__ counters, int32_t persistent, int32_t chunk,
+    float delta, double zmin) {
+    // queue q holds entries [xcd_begin[q], xcd_begin[q + 1]) of the tile list:
+    // every tile in XCD order, or (with pair sub-sampling) the step's compacted
+    // list of the selected pairs' tiles, in the same order
     __shared__ float lut[256];
     __shared__ double red[4][10];
     __shared__ int64_t claim;
-    if (FMT == 2) lut[threadIdx.x] = sqrtf((float)threadIdx.x);
-    __syncthreads();
     const int q0 = (int)(blockIdx.x % (unsigned)n_queues);
     if (!persistent) {
         // one workgroup per tile; workgroup b runs on XCD b mod 8, so the
         // tiles of queue q (consecutive target views) stay on one XCD's L2
-        const int64_t t = xcd_begin[q0] + blockIdx.x / (unsigned)n_queues;
-        if (t >= xcd_begin[q0 + 1]) return;
+        const int64_t e = xcd_begin[q0] + blockIdx.x / (unsigned)n_queues;
+        if (e >= xcd_begin[q0 + 1]) return;
+        if (FMT == 2) lut[threadIdx.x] = sqrtf((float)threadIdx.x);
+        __syncthreads();
+        const int64_t t = tile_list ? (int64_t)tile_list[e] : e;
         do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials, res_base,
                              dz, pair_scale, lut, red, delta, zmin);
         return;
     }
-    // persistent: claim tiles from the own queue, then from the others
+    if (FMT == 2) lut[threadIdx.x] = sqrtf((float)threadIdx.x);
+    __syncthreads();
+    // persistent: claim runs of consecutive tiles from the own queue, then
+    // from the others.  One atomic per run: a queue's counter is one hot L2
+    // line, so a claim per tile would serialise on it.  The run length shrinks
+    // with the work left in the queue (as last seen by this workgroup), from
+    // `chunk` down to one tile, so the queues still drain evenly.
+    const int64_t per_queue = gridDim.x / (unsigned)n_queues;
     for (int qi = 0; qi < n_queues; ++qi) {
         const int q = (q0 + qi) % n_queues;
         const int64_t begin = xcd_begin[q], end = xcd_begin[q + 1];
+        int64_t seen = 0;                       // counter value at this workgroup's last claim
         for (;;) {
-            if (threadIdx.x == 0) claim = begin + atomicAdd(&counters[q], 1);
+            const int64_t left = end - begin - seen;
+            const int run = (int)max((int64_t)1, min((int64_t)chunk, left / (8 * per_queue)));
+            if (threadIdx.x == 0) claim = atomicAdd(&counters[q], run);
             __syncthreads();
-            const int64_t t = claim;
+            seen = claim;
+            const int64_t e0 = begin + seen;
             __syncthreads();
-            if (t >= end) break;
-            do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials,
-                                 res_base, dz, pair_scale, lut, red, delta, zmin);
-            __syncthreads();
+            if (e0 >= end) break;
+            const int64_t e1 = e0 + run < end ? e0 + run : end;
+            for (int64_t e = e0; e < e1; ++e) {
+                const int64_t t = tile_list ? (int64_t)tile_list[e] : e;
+                do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials,
+                                     res_base, dz, pair_scale, lut, red, delta, zmin);
+                __syncthreads();
+            }
         }
     }
 }
@@ -320,8 +340,11 @@ void launch_cost_kernel(Plan& p, float* dz, hipStream_t s) {
                           : FMT == 3 ? reinterpret_cast<const uint32_t*>(p.tex_q32.p)
                                      : reinterpret_cast<const uint32_t*>(p.tex_f32.p);
     const int nq = p.n_xcd_queues;
+    // with pair sub-sampling the step's tile count is known only on the
+    // device: workgroups claim tiles from the compacted queues (persistent)
+    const bool persistent = p.opt.persistent == 1 || p.sample_budget > 0;
     unsigned grid;
-    if (p.opt.persistent == 1) {
+    if (persistent) {
         int64_t want = (int64_t)p.n_cu * 8;
         want = std::min<int64_t>(want, ceil_div(p.n_tiles, 1) + nq);
         grid = (unsigned)(ceil_div(want, nq) * nq);
@@ -335,8 +358,9 @@ void launch_cost_kernel(Plan& p, float* dz, hipStream_t s) {
     edge_cost_kernel<FMT, P, EXT><<<grid, kBlock, 0, s>>>(
         reinterpret_cast<const uint2*>(p.records.p), tex, p.tiles.p, p.pair_desc.p, p.pair_rel.p,
         p.partials.p, EXT ? p.ext_partials.p : nullptr, p.pair_res_base.p, dz, p.pair_scale.p,
-        p.xcd_begin_d.p, nq, p.counters.p,
-        p.opt.persistent == 1 ? 1 : 0, p.params.huber_delta, p.params.z_min);
+        p.sample_budget > 0 ? p.qbegin_d.p : p.xcd_begin_d.p,
+        p.sample_budget > 0 ? p.tile_list.p : nullptr, nq, p.counters.p, persistent ? 1 : 0,
+        std::max(1, 16384 / p.tile_size), p.params.huber_delta, p.params.z_min);
     EPO_CHECK_LAUNCH();
 }
 
@@ -368,7 +392,8 @@ void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss
                  double* pair_cost, int32_t* pair_valid, double* pair_grad, double* grad,
                  const double* upstream, hipStream_t s, const RefineOut* ext) {
     if (p.D > 0) {
-        // this step's pair subset (stochastic sub-sampling), if enabled
+        // this step's pair subset (stochastic sub-sampling), if enabled, and
+        // the compacted list of its tiles
         launch_pair_selection(p, p.capture_step ? p.capture_step : p.sample_step, s);
         pair_setup_kernel<<<(unsigned)ceil_div(std::max(p.D, 16), 256), 256, 0, s>>>(
             poses, p.K_d.p, p.wh_d.p, p.view_offset_d.p, p.pair_static.p, lambda,

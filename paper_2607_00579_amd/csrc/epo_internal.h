@@ -180,6 +180,9 @@ struct Plan {
     DevBuf<int32_t> scene_pairs;
     DevBuf<int32_t> counters;             // work counters of the 8 XCD queues
     DevBuf<int64_t> xcd_begin_d;          // 9 entries: tile range of each queue
+    DevBuf<int32_t> tile_list;            // T: the step's selected tiles (pair sub-sampling)
+    DevBuf<int32_t> tile_blk;             // per 1024 tiles: selected count, then offset
+    DevBuf<int64_t> qbegin_d;             // 9 entries: queue ranges in tile_list
     DevBuf<int32_t> status;               // device status word
     DevBuf<int32_t> scene_view_ptr, scene_view_idx;   // CSR: views of each scene
     // stochastic pair sub-sampling: image pairs (groups of one or two

@@ -217,6 +217,9 @@ void build_tiles(Plan& p, hipStream_t s) {
     upload(p.xcd_begin_d, p.xcd_begin, s);
     p.partials.alloc((size_t)std::max<int64_t>(p.n_tiles, 1));
     p.ext_partials.alloc(2 * (size_t)std::max<int64_t>(p.n_tiles, 1));
+    p.tile_list.alloc((size_t)std::max<int64_t>(p.n_tiles, 1));
+    p.tile_blk.alloc((size_t)std::max<int64_t>(ceil_div(p.n_tiles, 1024), 1));
+    p.qbegin_d.alloc(nq + 1);
     EPO_HIP(hipStreamSynchronize(s));
 }
 

@@ -63,9 +63,13 @@ def test_device_subsets_on_the_batch_workload(gpu):
             say(f"c4 budget {budget} step {s}: {int(got.sum())} of {got.size} directed pairs")
 
 
-def test_sampled_step_cost_and_gradient(gpu):
+@pytest.mark.parametrize("options", [None, dict(persistent=1, points_per_thread=2),
+                                     dict(persistent=2, points_per_thread=1, tile_order=2)])
+def test_sampled_step_cost_and_gradient(gpu, options):
+    """Only the selected pairs' tiles run (compacted tile list), in both launch
+    forms and tile sizes."""
     p = problem("c2")
-    plan = plan_for(p)
+    plan = plan_for(p, options=options)
     P = torch.from_numpy(p.poses_init.copy()).cuda()
     step_t = torch.full((1,), 3, dtype=torch.int32, device="cuda")
     plan.set_pair_sampling(9, 77, step_t)
@@ -82,7 +86,7 @@ def test_sampled_step_cost_and_gradient(gpu):
     # sub-sampling off again: the full evaluation, bit for bit
     plan.set_pair_sampling(0)
     full = plan.cost(P, 10.0, grad=True)
-    plan2 = plan_for(p)
+    plan2 = plan_for(p, options=options)
     ref = plan2.cost(P, 10.0, grad=True)
     assert torch.equal(full["loss"], ref["loss"]) and torch.equal(full["grad"], ref["grad"])
 
