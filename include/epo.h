@@ -320,6 +320,49 @@ EPO_API epo_status epo_plan_set_pair_sampling(epo_plan plan, int32_t budget, uin
 EPO_API epo_status epo_plan_sampled_pairs(epo_plan plan, uint8_t* selected, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * 4b. The paper's pose parameterization (Sec. 3 "Pose Refinement", Sec. 4
+ * "Implementation Details"): per scene, every pose is produced from its
+ * initial pose P0 by
+ *     P = phi(P0 + MLP(P0)) + [0 | delta]
+ * MLP: six linear layers 12 -> 128 -> 128 -> 128 -> 128 -> 128 -> 12 on P0
+ * flattened row-major, ReLU after the first five, the first layer's output
+ * added to the third's (skip connection); phi orthonormalises the first two
+ * columns of the rotation block by Gram-Schmidt (6D representation); delta is
+ * a per-view translation offset.  Matrix products run in BF16 on the matrix
+ * cores with float32 accumulation: bf16 operands (weights rounded from their
+ * float32 values, activations and activation gradients stored in bf16), bias /
+ * ReLU / skip / masks on the float32 accumulators; weight and bias gradients
+ * and the MLP output float32; the pose algebra float64.
+ *
+ *   params      float32 [n_scenes][EPO_MLP_PARAMS]: W1 (128 x 12, row-major
+ *               out x in), b1, W2, b2, ..., W6 (12 x 128), b6
+ *   poses0      float64 [V][3][4] initial poses; delta float64 [V][3]
+ *   poses       float64 [V][3][4] (forward: written; backward: the forward's
+ *               output)
+ *   grad        float64 [V][6] left-twist gradient of the loss at `poses`
+ *   param_grad  float32 [n_scenes][EPO_MLP_PARAMS] (written);
+ *   delta_grad  float64 [V][3] (written)
+ * epo_mlp_setup allocates the activation store (once per plan; about 1.6 KB
+ * per view).  epo_mlp_backward uses the activations of the last forward.
+ * epo_mlp_step: AdamW (x <- x (1 - lr wd), then Adam with bias correction at
+ * step = *step + 1) on every parameter (wd_mlp) and delta (wd_delta), lr per
+ * scene [n_scenes]; increments *step.  No allocation after set-up, no
+ * synchronisation, capture-safe.
+ * ------------------------------------------------------------------------- */
+#define EPO_MLP_PARAMS 69260
+EPO_API epo_status epo_mlp_setup(epo_plan plan, void* stream);
+EPO_API epo_status epo_mlp_forward(epo_plan plan, const float* params, const double* poses0,
+                           const double* delta, double* poses, void* stream);
+EPO_API epo_status epo_mlp_backward(epo_plan plan, const float* params, const double* poses0,
+                            const double* poses, const double* grad, float* param_grad,
+                            double* delta_grad, void* stream);
+EPO_API epo_status epo_mlp_step(epo_plan plan, float* params, float* adam_m, float* adam_v,
+                        const float* param_grad, double* delta, double* delta_m,
+                        double* delta_v, const double* delta_grad, const double* lr,
+                        double beta1, double beta2, double eps, double wd_mlp, double wd_delta,
+                        int32_t* step, void* stream);
+
+/* ---------------------------------------------------------------------------
  * 4. pose_step
  * Adam on left twists with an SE(3) update, in float64 (optimizer of Sec. 4
  * "Implementation Details" with beta = (0.9, 0.999); the pose refiner network

@@ -54,6 +54,10 @@ _SIGS = {
     "epo_plan_set_refinement": [P, P, P, P, P],
     "epo_plan_set_pair_sampling": [P, I32, C.c_uint64, P, P],
     "epo_build_viewgraph": [I32, P, P, P, P, P, P, P, I32, I32, F64, F64, F64, P, P, P, P],
+    "epo_mlp_setup": [P, P],
+    "epo_mlp_forward": [P, P, P, P, P, P],
+    "epo_mlp_backward": [P, P, P, P, P, P, P, P],
+    "epo_mlp_step": [P, P, P, P, P, P, P, P, P, P, F64, F64, F64, F64, F64, P, P],
     "epo_plan_sampled_pairs": [P, P, P],
     "epo_edge_cost_refine": [P, P, P, P, P, P, P, P, P, P],
     "epo_pose_step": [P, P, P, P, I32, P, P, P, F64, F64, F64, P, P],
@@ -178,6 +182,30 @@ def build_viewgraph(n_views, width, height, K, view_offset, depth, poses, candid
                                       _ptr(view_offset), _ptr(depth), _ptr(poses),
                                       _ptr(candidates), n_candidates, stride, tau, min_fraction,
                                       z_min, _ptr(consistent), _ptr(total), _ptr(valid), stream))
+
+
+MLP_PARAMS = 69260
+
+
+def mlp_setup(plan, stream):
+    _check(load().epo_mlp_setup(plan, stream))
+
+
+def mlp_forward(plan, params, poses0, delta, poses, stream):
+    _check(load().epo_mlp_forward(plan, _ptr(params), _ptr(poses0), _ptr(delta), _ptr(poses),
+                                  stream))
+
+
+def mlp_backward(plan, params, poses0, poses, grad, param_grad, delta_grad, stream):
+    _check(load().epo_mlp_backward(plan, _ptr(params), _ptr(poses0), _ptr(poses), _ptr(grad),
+                                   _ptr(param_grad), _ptr(delta_grad), stream))
+
+
+def mlp_step(plan, params, m, v, param_grad, delta, dm, dv, delta_grad, lr, beta1, beta2, eps,
+             wd_mlp, wd_delta, step, stream):
+    _check(load().epo_mlp_step(plan, _ptr(params), _ptr(m), _ptr(v), _ptr(param_grad),
+                               _ptr(delta), _ptr(dm), _ptr(dv), _ptr(delta_grad), _ptr(lr),
+                               beta1, beta2, eps, wd_mlp, wd_delta, _ptr(step), stream))
 
 
 def plan_set_pair_sampling(plan, budget, seed, step, stream):

@@ -335,3 +335,65 @@ class EdgeRefineFn(torch.autograd.Function):
         o = ctx.plan.refine(ctx.poses, ctx.lam, upstream=grad_loss.to(torch.float64).contiguous(),
                             loss=False)
         return (o["grad"], o["grad_gamma"], o["grad_alpha"], o["grad_beta"], None, None, None)
+
+
+class PoseRefiner:
+    """The paper's pose parameterization on a plan: per scene a refiner MLP
+    (float32 parameters, bf16 matrix products) and per view a translation
+    offset, P = phi(P0 + MLP(P0)) + [0 | delta], trained with AdamW.  All
+    state is device tensors; forward / backward / step launch the library's
+    kernels on the current stream."""
+
+    def __init__(self, plan: EdgePlan, poses0: torch.Tensor, params: torch.Tensor | None = None,
+                 seed: int = 0):
+        dev = plan.device
+        self.plan = plan
+        self.poses0 = poses0.to(dev, torch.float64).contiguous()
+        if params is None:
+            params = torch.from_numpy(self.init_params(plan.n_scenes, seed))
+        if tuple(params.shape) != (plan.n_scenes, _lib.MLP_PARAMS):
+            raise ValueError(f"params must be ({plan.n_scenes}, {_lib.MLP_PARAMS})")
+        self.params = params.to(dev, torch.float32).contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.delta = torch.zeros(plan.n_views, 3, dtype=torch.float64, device=dev)
+        self.dm = torch.zeros_like(self.delta)
+        self.dv = torch.zeros_like(self.delta)
+        self.delta_grad = torch.zeros_like(self.delta)
+        self.poses = self.poses0.clone()
+        _lib.mlp_setup(plan.handle, _stream(dev))
+
+    @staticmethod
+    def init_params(n_scenes: int, seed: int = 0) -> np.ndarray:
+        """Kaiming-normal weights, zero biases, zero last layer (float32)."""
+        rng = np.random.default_rng(seed)
+        shapes = [(128, 12), (128, 128), (128, 128), (128, 128), (128, 128), (12, 128)]
+        th = np.zeros((n_scenes, _lib.MLP_PARAMS), np.float32)
+        for s in range(n_scenes):
+            o = 0
+            for k, (rows, cols) in enumerate(shapes):
+                if k < len(shapes) - 1:
+                    th[s, o:o + rows * cols] = rng.normal(0.0, np.sqrt(2.0 / cols), rows * cols)
+                o += rows * cols + rows
+        return th
+
+    def forward(self):
+        _lib.mlp_forward(self.plan.handle, self.params, self.poses0, self.delta, self.poses,
+                         _stream(self.plan.device))
+        return self.poses
+
+    def backward(self, grad: torch.Tensor):
+        _lib.mlp_backward(self.plan.handle, self.params, self.poses0, self.poses,
+                          grad.to(torch.float64).contiguous(), self.grad, self.delta_grad,
+                          _stream(self.plan.device))
+        return self.grad, self.delta_grad
+
+    def step(self, lr, step: torch.Tensor, beta1=0.9, beta2=0.999, eps=1e-8, wd_mlp=0.01,
+             wd_delta=0.1):
+        if not torch.is_tensor(lr):
+            lr = torch.full((self.plan.n_scenes,), float(lr), dtype=torch.float64,
+                            device=self.plan.device)
+        _lib.mlp_step(self.plan.handle, self.params, self.m, self.v, self.grad, self.delta,
+                      self.dm, self.dv, self.delta_grad, lr, beta1, beta2, eps, wd_mlp, wd_delta,
+                      step, _stream(self.plan.device))

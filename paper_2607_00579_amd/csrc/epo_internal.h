@@ -204,6 +204,12 @@ struct Plan {
     DevBuf<int32_t> conv_phase;           // S (read by the schedule kernel)
     epo_convergence_params conv{25, 0.5f, 50, 0.1f};
     DevBuf<double> grad_scratch;          // V x 6 (graph iteration)
+    // pose refiner MLP (allocated by its set-up call): per-scene rows padded
+    // to 64, bf16 activations (h0: 16 wide; h1..h5, relu of layer 3: 128 wide)
+    int64_t mlp_rows = 0;
+    DevBuf<int64_t> mlp_row_off;          // S + 1
+    DevBuf<uint16_t> mlp_act;             // mlp_rows x (16 + 6 x 128) bf16
+    DevBuf<float> mlp_out;                // mlp_rows x 12 MLP outputs
     // focal and depth refinement: f = f0 (1 + gamma_v), Z = Z0 alpha + beta
     DevBuf<float> K0_d;                   // V x 4 intrinsics as given (K_d holds the refined ones)
     DevBuf<double> gamma_d;               // V: current focal scales gamma
@@ -265,6 +271,15 @@ void launch_convergence(Plan& p, const double* poses, double* theta_out, hipStre
 void launch_pair_selection(Plan& p, const int32_t* step, hipStream_t stream);
 void launch_convergence_reset(Plan& p, const double* poses, hipStream_t stream);
 void build_texture(Plan& p, const int32_t* d2, hipStream_t stream);
+void mlp_setup(Plan& p, hipStream_t stream);
+void launch_mlp_forward(Plan& p, const float* params, const double* poses0, const double* delta,
+                        double* poses, hipStream_t stream);
+void launch_mlp_backward(Plan& p, const float* params, const double* poses0, const double* poses,
+                         const double* grad, float* param_grad, double* delta_grad,
+                         hipStream_t stream);
+void launch_adamw(Plan& p, float* params, float* m, float* v, const float* g, double* delta,
+                  double* dm, double* dv, const double* dg, const double* lr, double b1, double b2,
+                  double eps, double wd_mlp, double wd_delta, int32_t* step, hipStream_t stream);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

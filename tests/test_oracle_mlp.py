@@ -155,3 +155,13 @@ def test_adamw_first_step_closed_form():
     # zero learning rate: nothing moves, moments still update
     x2, m2, v2 = mlp.adamw(x, m, v, g, 2, 0.0, wd)
     assert np.array_equal(x2, x) and not np.array_equal(m2, m)
+
+
+def test_generator_and_library_agree_on_the_layout():
+    import re
+    from synth import refiner
+    hdr = open(__import__("os").path.join(__import__("os").path.dirname(__file__), "..",
+                                          "include", "epo.h")).read()
+    n = int(re.search(r"#define EPO_MLP_PARAMS (\d+)", hdr).group(1))
+    assert n == mlp.N_PARAMS == refiner.N_PARAMS
+    assert refiner.offsets() == mlp.OFFSETS
