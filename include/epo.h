@@ -356,6 +356,22 @@ EPO_API epo_status epo_mlp_forward(epo_plan plan, const float* params, const dou
 EPO_API epo_status epo_mlp_backward(epo_plan plan, const float* params, const double* poses0,
                             const double* poses, const double* grad, float* param_grad,
                             double* delta_grad, void* stream);
+/* One iteration of the loop with this parameterization, captured as a HIP
+ * graph and replayed with epo_iteration_launch: device schedule (lambda, lr;
+ * lr 0 for a scene stopped by the convergence test) -> fused cost + adjoint
+ * at `poses` -> epo_mlp_backward -> epo_mlp_step (advances *step) ->
+ * epo_mlp_forward of the new parameters into `poses` -> [pose-change test,
+ * with_convergence != 0].  Before the first replay `poses` must hold
+ * epo_mlp_forward of the current parameters (the backward reads that
+ * forward's activations), and, with the test, epo_convergence_reset must
+ * have been called on them.  Replaces a previously captured iteration; grad
+ * may be NULL (internal buffer).  Errors as epo_iteration_capture. */
+EPO_API epo_status epo_mlp_iteration_capture(
+    epo_plan plan, float* params, float* adam_m, float* adam_v, float* param_grad, double* delta,
+    double* delta_m, double* delta_v, double* delta_grad, const double* poses0, double* poses,
+    int32_t* step, double* loss, double* grad, float lambda0, float lambda1, int32_t anneal_steps,
+    double peak_lr, int32_t warmup, int32_t total, double beta1, double beta2, double eps,
+    double wd_mlp, double wd_delta, int32_t with_convergence, void* stream);
 EPO_API epo_status epo_mlp_step(epo_plan plan, float* params, float* adam_m, float* adam_v,
                         const float* param_grad, double* delta, double* delta_m,
                         double* delta_v, const double* delta_grad, const double* lr,

@@ -123,3 +123,66 @@ def run_with_convergence(op: OracleProblem, poses0: np.ndarray, n_iters: int,
     hist["final_poses"] = poses
     hist["switch_steps"] = [list(d.switch_step) for d in dual]
     return hist
+
+
+
+def run_mlp(op: OracleProblem, P0: np.ndarray, theta0: np.ndarray, n_iters: int,
+            params: CostParams = CostParams(), wd_mlp: float = 0.01, wd_delta: float = 0.1,
+            convergence=None):
+    """The loop with the paper's pose parameterization (Sec. 3 "Pose
+    Refinement", Sec. 4): the poses are phi(P0 + MLP(P0)) + [0 | delta] per
+    scene (P0: the initial poses, theta0: one parameter row per scene, delta
+    starting at zero); at step s the loss and its left-twist gradient are
+    evaluated at the current poses with lambda(s), the gradient goes back
+    through phi and the MLP, and AdamW steps the MLP parameters and delta with
+    lr(s).  `convergence = (w1, eps1, w2, eps2)` adds the dual-phase test on
+    theta_95 of consecutive poses per scene, as in run_with_convergence."""
+    from . import mlp
+    from .convergence import DualPhase, theta95
+    P0 = np.asarray(P0, np.float64)
+    S, sov = op.n_scenes, op.scene_of_view
+    rows = [np.flatnonzero(sov == k) for k in range(S)]
+    theta = np.asarray(theta0, np.float64).copy()
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    delta = np.zeros((op.V, 3))
+    dm = np.zeros_like(delta)
+    dv = np.zeros_like(delta)
+    dual = [DualPhase(*convergence) for _ in range(S)] if convergence else None
+
+    def poses_of(theta, delta):
+        out = np.zeros((op.V, 3, 4))
+        fw = []
+        for k in range(S):
+            o, cache = mlp.forward(theta[k], P0[rows[k]].reshape(-1, 12))
+            out[rows[k]] = mlp.assemble(P0[rows[k]], o, delta[rows[k]])
+            fw.append((o, cache))
+        return out, fw
+
+    poses, fw = poses_of(theta, delta)
+    hist = dict(loss=[], poses=[], theta=[], phase=[])
+    for s in range(n_iters):
+        lr = np.array([0.0 if dual and dual[k].phase == 2 else learning_rate(s)
+                       for k in range(S)])
+        r = op.evaluate(poses, clamp_lambda(s), params)
+        hist["loss"].append(r["loss"].copy())
+        hist["poses"].append(poses.copy())
+        g_delta = np.zeros_like(delta)
+        for k in range(S):
+            o, cache = fw[k]
+            d_o, g_delta[rows[k]] = mlp.pose_backward(P0[rows[k]], o, poses[rows[k]],
+                                                      r["grad"][rows[k]])
+            g = mlp.backward(theta[k], cache, d_o)
+            theta[k], m[k], v[k] = mlp.adamw(theta[k], m[k], v[k], g, s + 1, lr[k], wd_mlp)
+        delta, dm, dv = mlp.adamw(delta, dm, dv, g_delta, s + 1, lr[sov][:, None], wd_delta)
+        new, fw = poses_of(theta, delta)
+        if dual:
+            th = [theta95(new[rows[k]], poses[rows[k]]) for k in range(S)]
+            for k in range(S):
+                dual[k].update(th[k])
+            hist["theta"].append(th)
+            hist["phase"].append([d.phase for d in dual])
+        poses = new
+    hist["final_poses"] = poses
+    hist["params"], hist["delta"] = theta, delta
+    return hist

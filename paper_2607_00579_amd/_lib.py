@@ -58,6 +58,8 @@ _SIGS = {
     "epo_mlp_forward": [P, P, P, P, P, P],
     "epo_mlp_backward": [P, P, P, P, P, P, P, P],
     "epo_mlp_step": [P, P, P, P, P, P, P, P, P, P, F64, F64, F64, F64, F64, P, P],
+    "epo_mlp_iteration_capture": [P, P, P, P, P, P, P, P, P, P, P, P, P, P, F32, F32, I32, F64,
+                                  I32, I32, F64, F64, F64, F64, F64, I32, P],
     "epo_plan_sampled_pairs": [P, P, P],
     "epo_edge_cost_refine": [P, P, P, P, P, P, P, P, P, P],
     "epo_pose_step": [P, P, P, P, I32, P, P, P, F64, F64, F64, P, P],
@@ -206,6 +208,16 @@ def mlp_step(plan, params, m, v, param_grad, delta, dm, dv, delta_grad, lr, beta
     _check(load().epo_mlp_step(plan, _ptr(params), _ptr(m), _ptr(v), _ptr(param_grad),
                                _ptr(delta), _ptr(dm), _ptr(dv), _ptr(delta_grad), _ptr(lr),
                                beta1, beta2, eps, wd_mlp, wd_delta, _ptr(step), stream))
+
+
+def mlp_iteration_capture(plan, params, m, v, param_grad, delta, dm, dv, delta_grad, poses0,
+                          poses, step, loss, grad, lambda0, lambda1, anneal_steps, peak_lr, warmup,
+                          total, beta1, beta2, eps, wd_mlp, wd_delta, with_convergence, stream):
+    _check(load().epo_mlp_iteration_capture(
+        plan, _ptr(params), _ptr(m), _ptr(v), _ptr(param_grad), _ptr(delta), _ptr(dm), _ptr(dv),
+        _ptr(delta_grad), _ptr(poses0), _ptr(poses), _ptr(step), _ptr(loss), _ptr(grad), lambda0,
+        lambda1, anneal_steps, peak_lr, warmup, total, beta1, beta2, eps, wd_mlp, wd_delta,
+        1 if with_convergence else 0, stream))
 
 
 def plan_set_pair_sampling(plan, budget, seed, step, stream):

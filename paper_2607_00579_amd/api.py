@@ -389,6 +389,26 @@ class PoseRefiner:
                           _stream(self.plan.device))
         return self.grad, self.delta_grad
 
+    def capture_iteration(self, step: torch.Tensor, loss: torch.Tensor, grad=None,
+                          lambda0=10.0, lambda1=6.0, anneal_steps=1000, peak_lr=3e-3, warmup=25,
+                          total=2000, beta1=0.9, beta2=0.999, eps=1e-8, wd_mlp=0.01,
+                          wd_delta=0.1, convergence=False):
+        """Capture one iteration of the loop with this parameterization;
+        replay it with plan.launch_iteration().  Runs the forward once so
+        that `poses` and the stored activations belong to the current
+        parameters (and, with the convergence test, resets it there;
+        `convergence` is True or (w1, eps1, w2, eps2))."""
+        self.forward()
+        if convergence:
+            cp = tuple(convergence) if isinstance(convergence, (tuple, list)) else ()
+            self.plan.convergence_reset(self.poses, *cp)
+        self._graph_refs = (step, loss, grad)
+        _lib.mlp_iteration_capture(self.plan.handle, self.params, self.m, self.v, self.grad,
+                                   self.delta, self.dm, self.dv, self.delta_grad, self.poses0,
+                                   self.poses, step, loss, grad, lambda0, lambda1, anneal_steps,
+                                   peak_lr, warmup, total, beta1, beta2, eps, wd_mlp, wd_delta,
+                                   bool(convergence), _stream(self.plan.device))
+
     def step(self, lr, step: torch.Tensor, beta1=0.9, beta2=0.999, eps=1e-8, wd_mlp=0.01,
              wd_delta=0.1):
         if not torch.is_tensor(lr):

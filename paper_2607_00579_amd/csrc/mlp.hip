@@ -381,14 +381,18 @@ __global__ __launch_bounds__(256) void adamw_kernel(
     const double s = (double)(step[0] + 1);
     const double c1 = 1.0 - pow(b1, s), c2 = 1.0 - pow(b2, s);
     const int64_t total = n_params + 3 * (int64_t)n_views;
+    // 1 - beta formed in float64 before rounding: (1 - (float)0.999) is off
+    // by 1.3e-5 relative
+    const float b1f = (float)b1, b2f = (float)b2;
+    const float omb1 = (float)(1.0 - b1), omb2 = (float)(1.0 - b2);
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
          k += (int64_t)gridDim.x * blockDim.x) {
         if (k < n_params) {
             const float a = (float)lr[k / EPO_MLP_PARAMS];
             const float gk = g[k];
             float xk = x[k] * (1.0f - a * (float)wd_mlp);
-            const float mk = (float)b1 * m[k] + (1.0f - (float)b1) * gk;
-            const float vk = (float)b2 * v[k] + (1.0f - (float)b2) * gk * gk;
+            const float mk = b1f * m[k] + omb1 * gk;
+            const float vk = b2f * v[k] + omb2 * gk * gk;
             m[k] = mk;
             v[k] = vk;
             xk -= a * (mk / (float)c1) / (sqrtf(vk / (float)c2) + (float)eps);

@@ -699,6 +699,74 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
     });
 }
 
+extern "C" epo_status epo_mlp_iteration_capture(
+    epo_plan plan, float* params, float* adam_m, float* adam_v, float* param_grad, double* delta,
+    double* delta_m, double* delta_v, double* delta_grad, const double* poses0, double* poses,
+    int32_t* step, double* loss, double* grad, float lambda0, float lambda1,
+    int32_t anneal_steps, double peak_lr, int32_t warmup, int32_t total, double beta1,
+    double beta2, double eps, double wd_mlp, double wd_delta, int32_t with_convergence,
+    void* stream) {
+    return guarded([&] {
+        EPO_REQUIRE(plan && params && adam_m && adam_v && param_grad && delta && delta_m &&
+                        delta_v && delta_grad && poses0 && poses && step && loss,
+                    "null argument");
+        EPO_REQUIRE(warmup >= 1 && total > warmup && anneal_steps >= 0, "schedule out of range");
+        Plan& p = *reinterpret_cast<Plan*>(plan);
+        EPO_HIP(hipSetDevice(p.device));
+        EPO_REQUIRE(p.mlp_act.p, "call epo_mlp_setup first");
+        EPO_REQUIRE(lambda0 <= p.params.lambda_max && lambda1 <= p.params.lambda_max,
+                    "schedule clamp above the plan's lambda_max");
+        EPO_REQUIRE(!with_convergence || p.max_views_per_scene <= kConvMaxViews,
+                    "a scene has more views than the convergence kernel supports");
+        hipStream_t user = as_stream(stream);
+        EPO_HIP(hipStreamSynchronize(user));
+        release_graph(p);
+        double* g = grad ? grad : p.grad_scratch.p;
+        hipStream_t cs;
+        EPO_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        const bool timing = p.timing;
+        p.timing = false;
+        hipError_t cap = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (cap != hipSuccess) {
+            p.timing = timing;
+            (void)hipStreamDestroy(cs);
+            throw Failure{EPO_ERR_HIP, std::string("hipStreamBeginCapture: ") +
+                                           hipGetErrorString(cap)};
+        }
+        p.capture_step = step;
+        try {
+            // schedule -> cost and adjoint at the current poses -> refiner
+            // backward (activations of the forward that made them) -> AdamW
+            // (advances the step) -> poses of the new parameters ->
+            // (pose-change test)
+            launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
+                            p.lambda_buf.p, p.lr_buf.p,
+                            with_convergence ? p.conv_phase.p : nullptr, cs);
+            launch_cost(p, poses, p.lambda_buf.p, loss, nullptr, nullptr, nullptr, g, nullptr, cs);
+            launch_mlp_backward(p, params, poses0, poses, g, param_grad, delta_grad, cs);
+            launch_adamw(p, params, adam_m, adam_v, param_grad, delta, delta_m, delta_v,
+                         delta_grad, p.lr_buf.p, beta1, beta2, eps, wd_mlp, wd_delta, step, cs);
+            launch_mlp_forward(p, params, poses0, delta, poses, cs);
+            if (with_convergence) launch_convergence(p, poses, nullptr, cs);
+        } catch (...) {
+            hipGraph_t junk = nullptr;
+            (void)hipStreamEndCapture(cs, &junk);
+            if (junk) (void)hipGraphDestroy(junk);
+            (void)hipStreamDestroy(cs);
+            p.timing = timing;
+            p.capture_step = nullptr;
+            throw;
+        }
+        p.timing = timing;
+        p.capture_step = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &p.graph);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess)
+            throw Failure{EPO_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e)};
+        EPO_HIP(hipGraphInstantiate(&p.graph_exec, p.graph, nullptr, nullptr, 0));
+    });
+}
+
 extern "C" epo_status epo_iteration_launch(epo_plan plan, void* stream) {
     return guarded([&] {
         EPO_REQUIRE(plan, "null plan");

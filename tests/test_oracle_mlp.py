@@ -165,3 +165,47 @@ def test_generator_and_library_agree_on_the_layout():
     n = int(re.search(r"#define EPO_MLP_PARAMS (\d+)", hdr).group(1))
     assert n == mlp.N_PARAMS == refiner.N_PARAMS
     assert refiner.offsets() == mlp.OFFSETS
+
+
+def test_loop_first_step_closed_form():
+    """The loop with this parameterization, pinned by what its first step must
+    do.  With the last layer zero the first poses are the initial ones and
+    the loss is the plain loss there; only the last layer and delta receive
+    gradient (the hidden layers see a zero backward signal through W6 = 0).
+    Adam's first step moves every parameter by -lr g/(|g| + eps), so b6's
+    translation entries move by -lr sign(sum_v g_rho) and each delta by
+    -lr sign(g_rho) with g_rho the cost's own gradient at the initial poses;
+    the hidden layers do not move."""
+    from oracle import cost as ocost
+    from oracle import loop as oloop
+    from synth import make
+    p = make("c1")
+    op = ocost.OracleProblem(p)
+    th = mlp.init_params(np.random.default_rng(0))[None].astype(np.float64)
+    h = oloop.run_mlp(op, p.poses_init, th, 1)
+    # Gram-Schmidt returns a rotation block up to rounding
+    assert np.abs(h["poses"][0] - p.poses_init).max() < 1e-14
+    r = op.evaluate(h["poses"][0], oloop.clamp_lambda(0))
+    assert np.array_equal(h["loss"][0], r["loss"])
+    lr = oloop.learning_rate(0)
+    g_rho = r["grad"][:, :3]
+    want_delta = -lr * g_rho / (np.abs(g_rho) + 1e-8)
+    assert np.allclose(h["delta"], want_delta, rtol=1e-12, atol=0)
+    (wo6, bo6) = mlp.OFFSETS[5]
+    b6 = h["params"][0][bo6:bo6 + 12].reshape(3, 4)
+    gs = g_rho.sum(axis=0)
+    # the bias gradient sums bf16-rounded d_o, which moves g/(|g| + eps) by
+    # about eps |dg| / g^2 < 1e-9 relative here
+    assert np.allclose(b6[:, 3], -lr * gs / (np.abs(gs) + 1e-8), rtol=1e-9, atol=0)
+    assert np.array_equal(h["params"][0][:wo6], th[0][:wo6] * (1.0 - lr * 0.01))
+
+
+def test_loop_decreases_the_loss_c1():
+    from oracle import cost as ocost
+    from oracle import loop as oloop
+    from synth import make
+    p = make("c1")
+    op = ocost.OracleProblem(p)
+    th = mlp.init_params(np.random.default_rng(0))[None].astype(np.float64)
+    h = oloop.run_mlp(op, p.poses_init, th, 60)
+    assert h["loss"][-1][0] < 0.1 * h["loss"][0][0]
