@@ -89,7 +89,8 @@ typedef struct epo_plan_options {
     int32_t texture_format;     /* 1 = float32 taps of sqrt(d2) (4 gathers per sample);
                                    2 = one uint32 per pixel holding the four taps of the
                                    bilinear cell as min(d2, 255) bytes (1 gather per
-                                   sample; exact for lambda_max <= 14.5);
+                                   sample; exact for lambda_max <= 14.5), stored in
+                                   8 x 4 pixel blocks of 128 bytes;
                                    3 = the four float32 taps of the cell per pixel
                                    (one 16-byte gather per sample) */
     int32_t points_per_thread;  /* residuals per thread per tile: 1, 2, 4, 8 or 16

@@ -41,7 +41,8 @@ constexpr int kBlock = 256;
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void pair_setup_kernel(
     const double* __restrict__ poses, const float* __restrict__ K, const int32_t* __restrict__ wh,
-    const int64_t* __restrict__ view_off, const PairStatic* __restrict__ ps,
+    const int64_t* __restrict__ view_off, const int64_t* __restrict__ blk_off,
+    const PairStatic* __restrict__ ps,
     const float* __restrict__ lambda, float lambda_max, PairDesc* __restrict__ desc,
     double* __restrict__ rel, int32_t D, int32_t* __restrict__ counters, int32_t n_counters,
     int32_t* __restrict__ status) {
@@ -90,8 +91,12 @@ __global__ __launch_bounds__(256) void pair_setup_kernel(
     const float lam = lambda[st.scene];
     if (!(lam <= lambda_max)) atomicOr(status, 2);
     o.lambda = lam;
-    o.width = wh[2 * j + 0];
-    o.tex_off = view_off[j];
+    // texture addressing of the format in use: blocked u8 quads (blk_off
+    // given: width = 128 (blocks per row - 1), the row-of-blocks stride less
+    // the part that 32 y0 covers) or row-major per-pixel texels
+    o.width = blk_off ? 128 * ((wh[2 * j + 0] + kQuadBlockW - 1) / kQuadBlockW - 1)
+                      : wh[2 * j + 0];
+    o.tex_off = blk_off ? blk_off[j] : view_off[j];
     desc[d] = o;
     for (int k = 0; k < 9; ++k) rel[12 * d + k] = R[k];
     for (int k = 0; k < 3; ++k) rel[12 * d + 9 + k] = t[k];
@@ -202,20 +207,25 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
 #pragma unroll 1
     for (int k0 = 0; k0 < rows; k0 += U) {
         uint2 r[U];
-        // rows past the tile's end load its last record (in bounds, so both
-        // loads issue back to back without a branch) and are masked; the
-        // offset from the tile's first record is a 32-bit byte offset
+        // rows past the tile's end read the records that follow it (the
+        // record array carries kRecordPad zero records past its end, more
+        // than the at most U * kBlock - 1 rows a tile's last iteration
+        // overshoots) and are masked, so both loads issue back to back
+        // without a branch; the row base is wave-uniform and each lane adds
+        // its own fixed byte offset
+        const char* rowb = reinterpret_cast<const char*>(rec) + (size_t)k0 * kBlock * 8;
 #pragma unroll
         for (int k = 0; k < U; ++k)
-            r[k] = *reinterpret_cast<const uint2*>(
-                reinterpret_cast<const char*>(rec) +
-                ((uint32_t)min((k0 + k) * kBlock + tid, tl.count - 1) << 3));
+            r[k] = *reinterpret_cast<const uint2*>(rowb + ((uint32_t)tid << 3) + k * kBlock * 8);
         Terms tt[U];
 #pragma unroll
         for (int k = 0; k < U; ++k) {
-            const int idx = (k0 + k) * kBlock + tid;
-            tt[k] = residual<FMT, EXT>(r[k], idx < tl.count, pd, texj, lut, delta, zmin, c3);
-            if (EXT && dzt && idx < tl.count) dzt[idx] = tt[k].dz;
+            // row (k0 + k) kBlock + tid is inside the tile: compared against a
+            // wave-uniform limit, so no per-lane index arithmetic
+            const int left = tl.count - (k0 + k) * kBlock;
+            const bool in = tid < left;
+            tt[k] = residual<FMT, EXT>(r[k], in, pd, texj, lut, delta, zmin, c3);
+            if (EXT && dzt && in) dzt[(k0 + k) * kBlock + tid] = tt[k].dz;
             n += tt[k].valid ? 1 : 0;
         }
 #pragma unroll
@@ -273,7 +283,9 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
     }
 }
 
-template <int FMT, int P, bool EXT>
+// PERS: persistent work-queue launch (a separate instantiation, so the
+// one-workgroup-per-tile form carries none of the claim loop's registers)
+template <int FMT, int P, bool EXT, bool PERS>
 __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
     const uint2* __restrict__ records, const uint32_t* __restrict__ tex,
     const Tile* __restrict__ tiles, const PairDesc* __restrict__ desc,
@@ -281,8 +293,7 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
     double* __restrict__ ext_partials, const int64_t* __restrict__ res_base,
     float* __restrict__ dz, const double* __restrict__ pair_scale,
     const int64_t* __restrict__ xcd_begin, const int32_t* __restrict__ tile_list,
-    int32_t n_queues, int32_t* __restrict__ counters, int32_t persistent, int32_t chunk,
-    float delta, double zmin) {
+    int32_t n_queues, int32_t* __restrict__ counters, int32_t chunk, float delta, double zmin) {
     // queue q holds entries [xcd_begin[q], xcd_begin[q + 1]) of the tile list:
     // every tile in XCD order, or (with pair sub-sampling) the step's compacted
     // list of the selected pairs' tiles, in the same order
@@ -290,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
     __shared__ double red[4][10];
     __shared__ int64_t claim;
     const int q0 = (int)(blockIdx.x % (unsigned)n_queues);
-    if (!persistent) {
+    if constexpr (!PERS) {
         // one workgroup per tile; workgroup b runs on XCD b mod 8, so the
         // tiles of queue q (consecutive target views) stay on one XCD's L2
         const int64_t e = xcd_begin[q0] + blockIdx.x / (unsigned)n_queues;
@@ -355,11 +366,13 @@ void launch_cost_kernel(Plan& p, float* dz, hipStream_t s) {
         grid = (unsigned)(per_q * nq);
     }
     if (grid == 0) return;
-    edge_cost_kernel<FMT, P, EXT><<<grid, kBlock, 0, s>>>(
+    auto kernel = persistent ? edge_cost_kernel<FMT, P, EXT, true>
+                             : edge_cost_kernel<FMT, P, EXT, false>;
+    kernel<<<grid, kBlock, 0, s>>>(
         reinterpret_cast<const uint2*>(p.records.p), tex, p.tiles.p, p.pair_desc.p, p.pair_rel.p,
         p.partials.p, EXT ? p.ext_partials.p : nullptr, p.pair_res_base.p, dz, p.pair_scale.p,
         p.sample_budget > 0 ? p.qbegin_d.p : p.xcd_begin_d.p,
-        p.sample_budget > 0 ? p.tile_list.p : nullptr, nq, p.counters.p, persistent ? 1 : 0,
+        p.sample_budget > 0 ? p.tile_list.p : nullptr, nq, p.counters.p,
         std::max(1, 16384 / p.tile_size), p.params.huber_delta, p.params.z_min);
     EPO_CHECK_LAUNCH();
 }
@@ -396,7 +409,8 @@ void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss
         // the compacted list of its tiles
         launch_pair_selection(p, p.capture_step ? p.capture_step : p.sample_step, s);
         pair_setup_kernel<<<(unsigned)ceil_div(std::max(p.D, 16), 256), 256, 0, s>>>(
-            poses, p.K_d.p, p.wh_d.p, p.view_offset_d.p, p.pair_static.p, lambda,
+            poses, p.K_d.p, p.wh_d.p, p.view_offset_d.p,
+            p.opt.texture_format == 2 ? p.blk_off_d.p : nullptr, p.pair_static.p, lambda,
             p.params.lambda_max, p.pair_desc.p, p.pair_rel.p, p.D, p.counters.p, 8, p.status.p);
         EPO_CHECK_LAUNCH();
         const bool timed = p.timing;

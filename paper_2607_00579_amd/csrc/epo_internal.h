@@ -63,6 +63,16 @@ epo_status guarded(F&& f) {
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// pixel blocks of the u8 quad texture (8 x 4 texels of 4 bytes = 128 bytes)
+constexpr int kQuadBlockW = 8;
+constexpr int kQuadBlockH = 4;
+static_assert(kQuadBlockW * kQuadBlockH == 32, "a quad block is 32 texels (shift by 5)");
+
+// zero records allocated past the last edge record: the fused kernel's last
+// iteration over a tile reads up to two 256-record rows past the tile's end
+// (masked) instead of clamping every row index
+constexpr int64_t kRecordPad = 512;
+
 // device buffer owned by a plan
 template <class T>
 struct DevBuf {
@@ -156,7 +166,14 @@ struct Plan {
 
     // device, plan lifetime
     DevBuf<uint64_t> records;             // (u | v << 16) | (Z bits << 32)
-    DevBuf<uint32_t> tex;                 // texture (f32 bits or u8 quads), total_px
+    // u8 quad texture (format 2) in blocks of kQuadBlockW x kQuadBlockH
+    // pixels, one 128-byte cache line each, blocks row-major per view:
+    // a wave's projected edge points touch about a fifth fewer lines than
+    // with whole image rows
+    DevBuf<uint32_t> tex;                 // total_blk texels
+    std::vector<int64_t> blk_off;         // V: first texel of each view's blocks
+    DevBuf<int64_t> blk_off_d;
+    int64_t total_blk = 0;
     DevBuf<float> tex_f32;                // float32 sqrt(d2) per pixel
     DevBuf<float4> tex_q32;               // float32 taps of the cell at each pixel
     DevBuf<int32_t> scene_of_view_d;

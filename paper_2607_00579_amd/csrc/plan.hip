@@ -102,6 +102,7 @@ __global__ __launch_bounds__(256) void scatter_records_kernel(
 __global__ __launch_bounds__(256) void texture_kernel(const int32_t* __restrict__ d2,
                                                       const int64_t* __restrict__ view_off,
                                                       const int32_t* __restrict__ wh,
+                                                      const int64_t* __restrict__ blk_off,
                                                       uint32_t* __restrict__ q8,
                                                       float* __restrict__ f32,
                                                       float4* __restrict__ q32) {
@@ -127,7 +128,13 @@ __global__ __launch_bounds__(256) void texture_kernel(const int32_t* __restrict_
             const uint32_t t10 = rx ? (uint32_t)min(d2[base + i + 1], 255) : 255u;
             const uint32_t t01 = dy ? (uint32_t)min(d2[base + i + W], 255) : 255u;
             const uint32_t t11 = (rx && dy) ? (uint32_t)min(d2[base + i + W + 1], 255) : 255u;
-            q8[base + i] = t00 | (t10 << 8) | (t01 << 16) | (t11 << 24);
+            // blocked layout: block (x / 8, y / 4), row-major blocks, the
+            // block's 8 x 4 texels row-major inside it
+            const int64_t nbx = (W + kQuadBlockW - 1) / kQuadBlockW;
+            const int64_t o = blk_off[v] +
+                              (((int64_t)(y / kQuadBlockH) * nbx + x / kQuadBlockW) << 5) +
+                              ((y % kQuadBlockH) * kQuadBlockW) + (x % kQuadBlockW);
+            q8[o] = t00 | (t10 << 8) | (t01 << 16) | (t11 << 24);
         }
     }
 }
@@ -227,12 +234,12 @@ void build_texture(Plan& p, const int32_t* d2, hipStream_t s) {
     const bool q8 = p.params.lambda_max <= kQ8LambdaMax;
     p.tex_f32.alloc((size_t)p.total_px);
     p.tex_q32.alloc((size_t)p.total_px);
-    if (q8) p.tex.alloc((size_t)p.total_px);
+    if (q8) p.tex.alloc((size_t)p.total_blk);
     int64_t maxWH = 1;
     for (int v = 0; v < p.V; ++v) maxWH = std::max<int64_t>(maxWH, (int64_t)p.width[v] * p.height[v]);
     const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(maxWH, 256), 1024);
     texture_kernel<<<dim3(gx, p.V), 256, 0, s>>>(d2, p.view_offset_d.p, p.wh_d.p,
-                                                 q8 ? p.tex.p : nullptr, p.tex_f32.p,
+                                                 p.blk_off_d.p, q8 ? p.tex.p : nullptr, p.tex_f32.p,
                                                  p.tex_q32.p);
     EPO_CHECK_LAUNCH();
 }
@@ -347,6 +354,13 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         p->gamma_d.alloc(n_views);
         EPO_HIP(hipMemsetAsync(p->gamma_d.p, 0, sizeof(double) * n_views, s));
         upload(p->view_offset_d, p->view_offset, s);
+        p->blk_off.assign(n_views, 0);
+        for (int v = 0; v < n_views; ++v) {
+            p->blk_off[v] = p->total_blk;
+            p->total_blk += (int64_t)ceil_div(p->width[v], kQuadBlockW) *
+                            ceil_div(p->height[v], kQuadBlockH) * (kQuadBlockW * kQuadBlockH);
+        }
+        upload(p->blk_off_d, p->blk_off, s);
         upload(p->scene_of_view_d, p->scene_of_view, s);
 
         // ---- edge compaction: counts per 16x16 tile, host prefix, scatter
@@ -390,7 +404,8 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         }
         DevBuf<int64_t> tile_rec_d;
         upload(tile_rec_d, tile_rec, s);
-        p->records.alloc((size_t)std::max<int64_t>(acc, 1));
+        p->records.alloc((size_t)(acc + kRecordPad));
+        EPO_HIP(hipMemsetAsync(p->records.p + acc, 0, sizeof(uint64_t) * kRecordPad, s));
         DevBuf<int32_t> bad_d;
         bad_d.alloc(1);
         EPO_HIP(hipMemsetAsync(bad_d.p, 0, sizeof(int32_t), s));

@@ -30,9 +30,17 @@ __device__ __forceinline__ uint32_t texel32(const uint32_t* __restrict__ tex, ui
 template <int FMT>
 struct Taps;
 
+// texel of cell (x0, y0) in a row-major per-pixel texture of row stride W
+__device__ __forceinline__ uint32_t row_major_texel(int x0, int y0, int W) {
+    return (uint32_t)(__umul24(y0, W) + x0);
+}
+
 // float32 texture: four gathers
 template <>
 struct Taps<1> {
+    __device__ static inline uint32_t index(int x0, int y0, int W) {
+        return row_major_texel(x0, y0, W);
+    }
     __device__ static inline void load(const uint32_t* __restrict__ tex, uint32_t idx, int W,
                                        const float* /*lut*/, float& d00, float& d10, float& d01,
                                        float& d11) {
@@ -44,13 +52,22 @@ struct Taps<1> {
     }
 };
 
-// saturated u8 quads: one gather, four LDS look-ups of sqrt(k)
+// saturated u8 quads: one gather, four LDS look-ups of sqrt(k); texels in
+// 8 x 4 pixel blocks (one 128-byte line each), blocks row-major.  index()
+// returns the byte offset of the texel of cell (x0, y0):
+//   4 (32 (a nbx + x0 / 8) + 8 (y0 % 4) + x0 % 8),  a = y0 / 4,
+// written as a k + 32 y0 + 4 x0 + 12 (x0 & ~7) with k = 128 (nbx - 1) (the
+// descriptor's width field for this format), three multiply-adds and shifts
 template <>
 struct Taps<2> {
-    __device__ static inline void load(const uint32_t* __restrict__ tex, uint32_t idx, int /*W*/,
+    __device__ static inline uint32_t index(int x0, int y0, int k) {
+        const uint32_t x = (uint32_t)x0, y = (uint32_t)y0;
+        return __umul24(y >> 2, (uint32_t)k) + (y << 5) + (x << 2) + 12u * (x & ~7u);
+    }
+    __device__ static inline void load(const uint32_t* __restrict__ tex, uint32_t off, int /*W*/,
                                        const float* lut, float& d00, float& d10, float& d01,
                                        float& d11) {
-        const uint32_t q = texel32(tex, idx << 2);
+        const uint32_t q = texel32(tex, off);
         d00 = lut[q & 0xffu];
         d10 = lut[(q >> 8) & 0xffu];
         d01 = lut[(q >> 16) & 0xffu];
@@ -61,6 +78,9 @@ struct Taps<2> {
 // float32 quads: the four float32 taps of the cell in one 16-byte gather
 template <>
 struct Taps<3> {
+    __device__ static inline uint32_t index(int x0, int y0, int W) {
+        return row_major_texel(x0, y0, W);
+    }
     __device__ static inline void load(const uint32_t* __restrict__ tex, uint32_t idx, int /*W*/,
                                        const float* /*lut*/, float& d00, float& d10, float& d01,
                                        float& d11) {
@@ -124,25 +144,30 @@ __device__ __forceinline__ Residual eval_residual(const uint2 rec, bool active,
     // with that zero weight is zero
     const float al = (float)(upd - fx0);
     const float be = (float)(vpd - fy0);
-    // y0 < H and W are below 2^24 whenever the residual is valid
-    const uint32_t idx = valid ? (uint32_t)(__umul24(y0, pd.width) + x0) : 0u;
+    // y0 < H and W are below 2^24 whenever the residual is valid; idx is
+    // the format's texel index (byte offset for format 2)
+    const uint32_t idx = valid ? Taps<FMT>::index(x0, y0, pd.width) : 0u;
     r.xn = (float)xnd;
     r.yn = (float)ynd;
     r.rz = (float)rzd;
     float d00, d10, d01, d11;
     Taps<FMT>::load(texj, idx, pd.width, lut, d00, d10, d01, d11);
-    const float e0 = d10 - d00, e1 = d11 - d01;
-    const float f0 = d01 - d00, f1 = d11 - d10;
-    const float gu = fmaf(be, e1 - e0, e0);
-    const float gv = fmaf(al, f1 - f0, f0);
+    // bilinear sample and its gradient; the cell's cross term
+    // d11 - d10 - d01 + d00 is formed once and serves both directions
+    const float e0 = d10 - d00, f0 = d01 - d00;
+    const float c = (d11 - d01) - e0;
+    const float gu = fmaf(be, c, e0);
+    const float gv = fmaf(al, c, f0);
     const float D = fmaf(be, gv, fmaf(al, e0, d00));
+    // Huber of the clamped distance: with m = min(d, delta),
+    // m (d - m / 2) is d^2 / 2 below delta and delta (d - delta / 2) above
+    // (the same float32 roundings as either branch), and m is the derivative
     const bool unclamped = D < pd.lambda;
-    const float dh = unclamped ? D : pd.lambda;    // min(D, lambda); D is finite
-    const bool quad = dh <= delta;
-    float rho = quad ? 0.5f * dh * dh : delta * (dh - 0.5f * delta);
-    float drho = unclamped ? (quad ? dh : delta) : 0.0f;
+    const float dh = fminf(D, pd.lambda);          // D is finite
+    const float m = fminf(dh, delta);
+    const float rho = m * fmaf(-0.5f, m, dh);
     r.rho = valid ? rho : 0.0f;
-    drho = valid ? drho : 0.0f;
+    const float drho = (valid && unclamped) ? m : 0.0f;
     r.Au = drho * gu * pd.fx;
     r.Av = drho * gv * pd.fy;
     r.w = -fmaf(r.Au, r.xn, r.Av * r.yn);
