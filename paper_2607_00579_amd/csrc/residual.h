@@ -56,13 +56,13 @@ struct Taps<1> {
 // 8 x 4 pixel blocks (one 128-byte line each), blocks row-major.  index()
 // returns the byte offset of the texel of cell (x0, y0):
 //   4 (32 (a nbx + x0 / 8) + 8 (y0 % 4) + x0 % 8),  a = y0 / 4,
-// written as a k + 32 y0 + 4 x0 + 12 (x0 & ~7) with k = 128 (nbx - 1) (the
-// descriptor's width field for this format), three multiply-adds and shifts
+// written as a k + 32 y0 + 4 (x0 + 3 (x0 & ~7)) with k = 128 (nbx - 1) (the
+// descriptor's width field for this format): two 24-bit multiply-adds, shifts
 template <>
 struct Taps<2> {
     __device__ static inline uint32_t index(int x0, int y0, int k) {
         const uint32_t x = (uint32_t)x0, y = (uint32_t)y0;
-        return __umul24(y >> 2, (uint32_t)k) + (y << 5) + (x << 2) + 12u * (x & ~7u);
+        return __umul24(y >> 2, (uint32_t)k) + (y << 5) + ((__umul24(x & ~7u, 3u) + x) << 2);
     }
     __device__ static inline void load(const uint32_t* __restrict__ tex, uint32_t off, int /*W*/,
                                        const float* lut, float& d00, float& d10, float& d01,
@@ -146,7 +146,8 @@ __device__ __forceinline__ Residual eval_residual(const uint2 rec, bool active,
     const float be = (float)(vpd - fy0);
     // y0 < H and W are below 2^24 whenever the residual is valid; idx is
     // the format's texel index (byte offset for format 2)
-    const uint32_t idx = valid ? Taps<FMT>::index(x0, y0, pd.width) : 0u;
+    // (a mask rather than a select keeps the compiler from branching here)
+    const uint32_t idx = Taps<FMT>::index(x0, y0, pd.width) & (0u - (uint32_t)valid);
     r.xn = (float)xnd;
     r.yn = (float)ynd;
     r.rz = (float)rzd;
