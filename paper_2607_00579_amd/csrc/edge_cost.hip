@@ -200,7 +200,9 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
     // two residuals in flight per thread (about 50 VGPRs, so the SIMD keeps
     // eight waves to hide the record load and the dependent tap gather);
     // unrolling all P would multiply the float64 live ranges
-    constexpr int U = P < 2 ? P : 2;
+    // (the refinement variant keeps one: its focal sums and ray components
+    // would push two past 64 VGPRs, below eight waves per SIMD)
+    constexpr int U = (P < 2 || EXT) ? 1 : 2;
     // the trip count follows the tile's own size (uniform over the
     // workgroup), so a pair's short last tile costs only its residuals
     const int rows = (tl.count + kBlock - 1) / kBlock;
