@@ -184,7 +184,7 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
     // pair reduction reads none for it)
     if (pair_scale[tl.pair] == 0.0) return;
     const PairDesc pd = desc[tl.pair];
-    const uint32_t* texj = tex + pd.tex_off;
+    const uint32_t* texj = view_texture<FMT>(tex, pd.tex_off);
     const uint2* rec = records + tl.rec;
     double c3[3] = {0.0, 0.0, 0.0};
     float* dzt = nullptr;

@@ -89,7 +89,8 @@ __global__ __launch_bounds__(kBlock) void depth_grad_kernel(
         const double wd = pair_w[d];
         if (wd == 0.0) continue;                // no valid residual in pair d
         const PairDesc pd = desc[d];
-        const Residual r = eval_residual<FMT>(rec, active, pd, tex + pd.tex_off, lut, delta, zmin);
+        const Residual r = eval_residual<FMT>(rec, active, pd, view_texture<FMT>(tex, pd.tex_off),
+                                              lut, delta, zmin);
         acc = fma(wd, (double)depth_derivative(r), acc);
     }
     if (!active) return;

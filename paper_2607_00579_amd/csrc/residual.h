@@ -30,6 +30,17 @@ __device__ __forceinline__ uint32_t texel32(const uint32_t* __restrict__ tex, ui
 template <int FMT>
 struct Taps;
 
+// first texel of view j: the descriptor's tex_off counts texels of the
+// format (4 bytes for formats 1 and 2, 16 bytes for format 3)
+template <int FMT>
+__device__ __forceinline__ const uint32_t* view_texture(const uint32_t* __restrict__ tex,
+                                                        int64_t tex_off) {
+    if constexpr (FMT == 3)
+        return reinterpret_cast<const uint32_t*>(reinterpret_cast<const float4*>(tex) + tex_off);
+    else
+        return tex + tex_off;
+}
+
 // texel of cell (x0, y0) in a row-major per-pixel texture of row stride W
 __device__ __forceinline__ uint32_t row_major_texel(int x0, int y0, int W) {
     return (uint32_t)(__umul24(y0, W) + x0);

@@ -64,3 +64,26 @@ def shifted_pair(seed: int = 0, per_depth: int = 40):
     P1 = np.concatenate([np.eye(3), np.array([[-b], [0.0], [0.0]])], axis=1)
     return problem_from_maps([W, W], [H, H], [K, K], [e0, e1], [z0, z1], [P0, P1],
                              [[0, 1], [1, 0]], name="shifted_pair")
+
+
+def odd_size_views(seed: int = 0, density: float = 0.15):
+    """One scene of six views whose sizes are not multiples of the texture
+    blocks (8 x 4 pixels), down to a single 2 x 2 view: random edge pixels
+    with depths in [3, 5], cameras a few degrees and centimetres apart looking
+    the same way, every ordered pair."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(seed)
+    sizes = [(37, 23), (9, 5), (130, 67), (17, 41), (2, 2), (8, 4)]
+    Ws, Hs, Ks, E, Z, P = [], [], [], [], [], []
+    for W, H in sizes:
+        f = float(max(W, H))
+        Ws.append(W)
+        Hs.append(H)
+        Ks.append([f, f, (W - 1) / 2.0, (H - 1) / 2.0])
+        E.append((rng.random((H, W)) < density).astype(np.uint8))
+        Z.append(rng.uniform(3.0, 5.0, (H, W)).astype(np.float32))
+        R = Rotation.from_rotvec(np.radians(3.0) * rng.normal(size=3) / np.sqrt(3)).as_matrix()
+        P.append(np.concatenate([R, 0.05 * rng.normal(size=(3, 1))], axis=1))
+    n = len(sizes)
+    pairs = [(i, j) for i in range(n) for j in range(n) if i != j]
+    return problem_from_maps(Ws, Hs, Ks, E, Z, P, pairs, name="odd_sizes")

@@ -106,17 +106,22 @@ def test_ground_truth_poses(gpu):
     dict(texture_format=2, points_per_thread=16, tile_order=1, persistent=1),
     dict(texture_format=1, points_per_thread=8, tile_order=1, persistent=1),
     dict(texture_format=2, points_per_thread=2, tile_order=2, persistent=2),
+    dict(texture_format=3, points_per_thread=4, tile_order=1, persistent=2),
+    dict(texture_format=3, points_per_thread=16, tile_order=2, persistent=1),
 ])
 def test_schedules_agree_with_oracle(gpu, opts):
     p = problem("c2")
     check_against_oracle(p, p.poses_init, 10.0, options=opts)
 
 
-def test_texture_formats_bitwise_equal(gpu):
+@pytest.mark.parametrize("fmt", [2, 3])
+def test_texture_formats_bitwise_equal(gpu, fmt):
+    """The three textures hold the same float32 taps (format 2 through its
+    exact square-root table): every output bitwise equal to format 1's."""
     p = problem("c2")
     a = gpu_eval(plan_for(p, options=dict(texture_format=1, points_per_thread=4, tile_order=1,
                                           persistent=2)), p.poses_init, 10.0)
-    b = gpu_eval(plan_for(p, options=dict(texture_format=2, points_per_thread=4, tile_order=1,
+    b = gpu_eval(plan_for(p, options=dict(texture_format=fmt, points_per_thread=4, tile_order=1,
                                           persistent=2)), p.poses_init, 10.0)
     for k in a:
         assert np.array_equal(a[k], b[k]), k
@@ -211,3 +216,18 @@ def test_bwd_matches_fused_and_scales_upstream(gpu):
     a = plan.cost(P, 10.0, grad=True)["grad"]
     b = plan.cost_bwd(P, 10.0, upstream=torch.tensor([2.5], dtype=torch.float64, device="cuda"))
     assert torch.equal(b, 2.5 * a)
+
+
+@pytest.mark.parametrize("fmt", [1, 2, 3])
+def test_odd_view_sizes(gpu, fmt):
+    """Views whose sides are not multiples of the 8 x 4 texture blocks (down
+    to 2 x 2): every format against the oracle and bitwise equal to format 1
+    (format 3's per-view texture base counts 16-byte texels)."""
+    p = fixtures.odd_size_views()
+    opts = dict(texture_format=fmt, points_per_thread=2, tile_order=1, persistent=2)
+    plan, g, r = check_against_oracle(p, p.poses_init, 10.0, options=opts)
+    assert (r["n"] > 0).sum() >= 10
+    if fmt != 1:
+        ref = gpu_eval(plan_for(p, options=dict(opts, texture_format=1)), p.poses_init, 10.0)
+        for k in ("loss", "grad", "pair_cost", "pair_valid"):
+            assert np.array_equal(g[k], ref[k]), k

@@ -185,12 +185,14 @@ def test_refine_focal_vs_oracle_finite_differences(gpu):
     assert e < TOL
 
 
-def test_depth_pass_stored_and_recomputed_forms_agree_bitwise(gpu):
+@pytest.mark.parametrize("fmt", [2, 3])
+def test_depth_pass_stored_and_recomputed_forms_agree_bitwise(gpu, fmt):
     """Before the first refinement update the depth pass re-evaluates every
     residual; afterwards it gathers the derivatives stored by the fused
     refinement kernel.  Same terms in the same order: identical bits."""
     p = problem("c2")
-    plan = plan_for(p)
+    plan = plan_for(p, options=dict(texture_format=fmt, points_per_thread=4, tile_order=1,
+                                    persistent=2))
     P = torch.from_numpy(p.poses_init.copy()).cuda()
     up = torch.tensor([1.5], dtype=torch.float64, device="cuda")
     first = plan.refine(P, 7.0, upstream=up)
