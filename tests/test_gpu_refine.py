@@ -7,6 +7,7 @@ import pytest
 import torch
 
 from oracle import cost as ocost
+from oracle import sampling as osamp
 from tests.gpu_helpers import problem, rel_norm_err, say
 
 pytestmark = pytest.mark.gpu
@@ -56,8 +57,9 @@ def check_depth(got, want, name):
     assert bad <= max(2, err.size // 10000), bad
 
 
-def run_case(prob, poses, lam, gamma=None, alpha=None, beta=None):
-    plan = plan_for(prob)
+def run_case(prob, poses, lam, gamma=None, alpha=None, beta=None, sampling=None, options=None):
+    """sampling = (budget, seed, step): one sub-sampled step."""
+    plan = plan_for(prob, options=options)
     views, idx = oracle_index(prob, plan)
     n = views.size
     z0 = np.zeros(n)
@@ -84,8 +86,14 @@ def run_case(prob, poses, lam, gamma=None, alpha=None, beta=None):
                 zv[idx[sel]] = z[sel]
                 depth[v] = zv.astype(np.float64)
     P = torch.from_numpy(np.ascontiguousarray(poses)).cuda()
+    sel = None
+    if sampling is not None:
+        budget, seed, step = sampling
+        plan.set_pair_sampling(budget, seed,
+                               torch.full((1,), step, dtype=torch.int32, device="cuda"))
+        sel = osamp.selected_pairs(prob.pairs, prob.scene_of_pair, seed, step, budget)
     g = {k: t.cpu().numpy() for k, t in plan.refine(P, lam).items()}
-    r = ocost.OracleProblem(prob).evaluate(poses, lam, K=K, depth=depth)
+    r = ocost.OracleProblem(prob).evaluate(poses, lam, K=K, depth=depth, selected=sel)
     assert rel_norm_err(g["loss"], r["loss"]) < TOL
     e_t = rel_norm_err(g["grad"][:, :3], r["grad"][:, :3], axis=1)
     e_r = rel_norm_err(g["grad"][:, 3:], r["grad"][:, 3:], axis=1)
@@ -123,6 +131,21 @@ def test_refine_gradients_at_a_refined_state(gpu):
     alpha = (1.0 + rng.uniform(-0.02, 0.02, n)).astype(np.float32)
     beta = rng.uniform(-0.02, 0.02, n).astype(np.float32)
     run_case(p, p.poses_init, 6.0, gamma, alpha, beta)
+
+
+@pytest.mark.parametrize("options", [None, dict(texture_format=3, points_per_thread=4,
+                                                 tile_order=2, persistent=2)])
+def test_refine_with_pair_sub_sampling(gpu, options):
+    """A joint-phase call on a sub-sampled step: only the selected pairs'
+    tiles run (persistent launch), focal sums and stored depth derivatives
+    of the skipped pairs are neither read nor added."""
+    p = problem("c2")
+    rng = np.random.default_rng(12)
+    n = sum(int(np.count_nonzero(p.edge_map(v))) for v in range(p.n_views))
+    gamma = rng.uniform(-0.02, 0.02, p.n_views)
+    alpha = (1.0 + rng.uniform(-0.02, 0.02, n)).astype(np.float32)
+    beta = rng.uniform(-0.02, 0.02, n).astype(np.float32)
+    run_case(p, p.poses_init, 8.0, gamma, alpha, beta, sampling=(9, 5, 4), options=options)
 
 
 def test_refine_small_clamp_and_focal_only(gpu):
