@@ -165,7 +165,7 @@ __device__ inline double wave_sum(double x) {
 
 // per-tile sums: S, n, G[6] into partials[t]; the refinement variant adds
 // F_t, F_s into ext_partials[2 t ..] and, if dz is given, stores every
-// residual's depth derivative at dz[res_base[pair] + record]
+// residual's depth derivative in the source-major layout of dz_index
 template <int FMT, int P, bool EXT>
 __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ records,
                                         const uint32_t* __restrict__ tex,
@@ -174,7 +174,7 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
                                         const double* __restrict__ rel,
                                         Partial* __restrict__ partials,
                                         double* __restrict__ ext_partials,
-                                        const int64_t* __restrict__ res_base,
+                                        const int64_t* __restrict__ dz_index,
                                         float* __restrict__ dz,
                                         const double* __restrict__ pair_scale, const float* lut,
                                         double (*red)[10], float delta, double zmin) {
@@ -188,12 +188,18 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
     const uint2* rec = records + tl.rec;
     double c3[3] = {0.0, 0.0, 0.0};
     float* dzt = nullptr;
+    int64_t dzn = 0;
     if constexpr (EXT) {
         const double* R = rel + 12 * (int64_t)tl.pair;
         c3[0] = R[2];
         c3[1] = R[5];
         c3[2] = R[8];
-        if (dz) dzt = dz + res_base[tl.pair] + tl.rec;
+        if (dz) {
+            // source-major derivative layout: the tile starts a 256-record
+            // block of its source, and every further row is the next block
+            dzn = dz_index[2 * tl.pair + 1];
+            dzt = dz + dz_index[2 * tl.pair] + tl.rec * dzn;
+        }
     }
     Acc a{0, 0, 0, 0, 0, 0, 0, 0, 0};
     int n = 0;                                  // valid residuals of this thread
@@ -227,7 +233,7 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
             const int left = tl.count - (k0 + k) * kBlock;
             const bool in = tid < left;
             tt[k] = residual<FMT, EXT>(r[k], in, pd, texj, lut, delta, zmin, c3);
-            if (EXT && dzt && in) dzt[(k0 + k) * kBlock + tid] = tt[k].dz;
+            if (EXT && dzt && in) dzt[(int64_t)(k0 + k) * kBlock * dzn + tid] = tt[k].dz;
             n += tt[k].valid ? 1 : 0;
         }
 #pragma unroll
@@ -292,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
     const uint2* __restrict__ records, const uint32_t* __restrict__ tex,
     const Tile* __restrict__ tiles, const PairDesc* __restrict__ desc,
     const double* __restrict__ rel, Partial* __restrict__ partials,
-    double* __restrict__ ext_partials, const int64_t* __restrict__ res_base,
+    double* __restrict__ ext_partials, const int64_t* __restrict__ dz_index,
     float* __restrict__ dz, const double* __restrict__ pair_scale,
     const int64_t* __restrict__ xcd_begin, const int32_t* __restrict__ tile_list,
     int32_t n_queues, int32_t* __restrict__ counters, int32_t chunk, float delta, double zmin) {
@@ -311,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
         if (FMT == 2) lut[threadIdx.x] = sqrtf((float)threadIdx.x);
         __syncthreads();
         const int64_t t = tile_list ? (int64_t)tile_list[e] : e;
-        do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials, res_base,
+        do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials, dz_index,
                              dz, pair_scale, lut, red, delta, zmin);
         return;
     }
@@ -340,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
             for (int64_t e = e0; e < e1; ++e) {
                 const int64_t t = tile_list ? (int64_t)tile_list[e] : e;
                 do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials,
-                                     res_base, dz, pair_scale, lut, red, delta, zmin);
+                                     dz_index, dz, pair_scale, lut, red, delta, zmin);
                 __syncthreads();
             }
         }
@@ -372,7 +378,7 @@ void launch_cost_kernel(Plan& p, float* dz, hipStream_t s) {
                              : edge_cost_kernel<FMT, P, EXT, false>;
     kernel<<<grid, kBlock, 0, s>>>(
         reinterpret_cast<const uint2*>(p.records.p), tex, p.tiles.p, p.pair_desc.p, p.pair_rel.p,
-        p.partials.p, EXT ? p.ext_partials.p : nullptr, p.pair_res_base.p, dz, p.pair_scale.p,
+        p.partials.p, EXT ? p.ext_partials.p : nullptr, p.dz_index.p, dz, p.pair_scale.p,
         p.sample_budget > 0 ? p.qbegin_d.p : p.xcd_begin_d.p,
         p.sample_budget > 0 ? p.tile_list.p : nullptr, nq, p.counters.p,
         std::max(1, 16384 / p.tile_size), p.params.huber_delta, p.params.z_min);

@@ -231,8 +231,15 @@ struct Plan {
     DevBuf<float> K0_d;                   // V x 4 intrinsics as given (K_d holds the refined ones)
     DevBuf<double> gamma_d;               // V: current focal scales gamma
     DevBuf<float> z0;                     // n_records depths as given (allocated on first update)
-    DevBuf<int64_t> pair_res_base;        // D: residual (d, record k) at pair_res_base[d] + k
-    DevBuf<float> dz;                     // n_residuals dH/dZ per residual (allocated on first
+    // per-residual depth derivatives, source-major: source view i's records
+    // in blocks of 256 (counted from its first record), each block holding
+    // one 256-entry chunk per pair out of i, in CSR order, so the depth pass
+    // reads one contiguous run per block.  Residual (d, record r) sits at
+    // dz_index[2 d] + b n + (r - b), with b the first record of r's block and
+    // n = dz_index[2 d + 1] the number of pairs out of the source
+    DevBuf<int64_t> dz_index;             // D x 2
+    int64_t dz_size = 0;
+    DevBuf<float> dz;                     // dz_size dH/dZ per residual (allocated on first
                                           // update when it fits; else the depth pass recomputes)
     bool dz_declined = false;             // no room for dz: recompute form only
     DevBuf<Tile> vblocks;                 // 256-record blocks of each view (pair = view)

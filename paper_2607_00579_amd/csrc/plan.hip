@@ -424,11 +424,8 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         // ---- residual count, CSR lists
         p->n_residuals = 0;
         std::vector<std::vector<int32_t>> in(n_views), outl(n_views), sc(S);
-        std::vector<int64_t> res_base(std::max(n_pairs, 1), 0);
         for (int d = 0; d < n_pairs; ++d) {
             const int i = p->pairs[2 * d], j = p->pairs[2 * d + 1];
-            // residual (d, record k) sits at res_base[d] + k in per-residual buffers
-            res_base[d] = p->n_residuals - p->rec_off[i];
             p->n_residuals += p->rec_off[i + 1] - p->rec_off[i];
             in[j].push_back(d);
             outl[i].push_back(d);
@@ -445,8 +442,24 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
             upload(idx, hi, s);
             EPO_HIP(hipStreamSynchronize(s));
         };
-        upload(p->pair_res_base, res_base, s);
-        EPO_HIP(hipStreamSynchronize(s));
+        {
+            // source-major layout of the per-residual depth derivatives
+            std::vector<int64_t> dzi(2 * (size_t)std::max(n_pairs, 1), 0);
+            int64_t base = 0;
+            for (int i = 0; i < n_views; ++i) {
+                const int64_t r0 = p->rec_off[i], nrec = p->rec_off[i + 1] - r0;
+                const int64_t nout = (int64_t)outl[i].size();
+                for (int64_t slot = 0; slot < nout; ++slot) {
+                    const int d = outl[i][slot];
+                    dzi[2 * d] = base + slot * 256 - r0 * nout;
+                    dzi[2 * d + 1] = nout;
+                }
+                base += ceil_div(nrec, 256) * 256 * nout;
+            }
+            p->dz_size = base;
+            upload(p->dz_index, dzi, s);
+            EPO_HIP(hipStreamSynchronize(s));
+        }
         csr(in, p->view_in_ptr, p->view_in_idx);
         csr(outl, p->view_out_ptr, p->view_out_idx);
         csr(sc, p->scene_ptr, p->scene_pairs);

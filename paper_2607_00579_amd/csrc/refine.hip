@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void depth_grad_kernel(
 }
 
 __global__ __launch_bounds__(256) void depth_gather_kernel(
-    const float* __restrict__ dz, const int64_t* __restrict__ res_base,
+    const float* __restrict__ dz, const int64_t* __restrict__ dz_index,
     const Tile* __restrict__ vblocks, const double* __restrict__ pair_w,
     const int32_t* __restrict__ out_ptr, const int32_t* __restrict__ out_idx,
     const int32_t* __restrict__ scene_of_view, const double* __restrict__ upstream,
@@ -111,14 +111,32 @@ __global__ __launch_bounds__(256) void depth_gather_kernel(
     if ((int)threadIdx.x >= b.count) return;
     const int64_t k = b.rec + threadIdx.x;
     double acc = 0.0;
-    const int e1 = out_ptr[i + 1];
-    // same pairs, same order and same float32 terms as the recompute form
-#pragma unroll 4
-    for (int e = out_ptr[i]; e < e1; ++e) {
-        const int d = out_idx[e];
-        const double wd = pair_w[d];
-        const float g = dz[res_base[d] + k];
-        acc = wd != 0.0 ? fma(wd, (double)g, acc) : acc;
+    const int e0 = out_ptr[i], n = out_ptr[i + 1] - e0;
+    if (n > 0) {
+        // the block's derivative chunks are contiguous, one of 256 per pair
+        // out of i in CSR order, so the loads need no per-pair look-up and
+        // go out eight at a time ahead of the (ordered) sums.  Same pairs,
+        // same order and same float32 terms as the recompute form
+        const float* __restrict__ g = dz + dz_index[2 * out_idx[e0]] + b.rec * n + threadIdx.x;
+        constexpr int B = 8;
+        int q = 0;
+        for (; q + B <= n; q += B) {
+            float gq[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) gq[u] = g[(int64_t)(q + u) * 256];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const double wd = pair_w[out_idx[e0 + q + u]];
+                // a pair with zero weight (no valid residual, or skipped by
+                // this step's sub-sampling) holds no derivatives this step
+                acc = wd != 0.0 ? fma(wd, (double)gq[u], acc) : acc;
+            }
+        }
+        for (; q < n; ++q) {
+            const double wd = pair_w[out_idx[e0 + q]];
+            const float gq = g[(int64_t)q * 256];
+            acc = wd != 0.0 ? fma(wd, (double)gq, acc) : acc;
+        }
     }
     const double gr = (upstream ? upstream[scene_of_view[i]] : 1.0) * acc;
     if (grad_beta) grad_beta[k] = gr;
@@ -142,7 +160,7 @@ void launch_depth_grad(Plan& p, const double* upstream, double* grad_alpha, doub
     if (p.n_vblocks == 0) return;
     if (stored) {
         depth_gather_kernel<<<(unsigned)p.n_vblocks, kBlock, 0, s>>>(
-            p.dz.p, p.pair_res_base.p, p.vblocks.p, p.pair_w.p, p.view_out_ptr.p,
+            p.dz.p, p.dz_index.p, p.vblocks.p, p.pair_w.p, p.view_out_ptr.p,
             p.view_out_idx.p, p.scene_of_view_d.p, upstream, p.z0.p,
             reinterpret_cast<const uint2*>(p.records.p), grad_alpha, grad_beta);
         EPO_CHECK_LAUNCH();
@@ -172,13 +190,13 @@ extern "C" epo_status epo_plan_set_refinement(epo_plan plan, const double* gamma
         Plan& p = *reinterpret_cast<Plan*>(plan);
         EPO_HIP(hipSetDevice(p.device));
         hipStream_t s = as_stream(stream);
-        if (!p.dz.p && p.n_residuals > 0 && !p.dz_declined) {
+        if (!p.dz.p && p.dz_size > 0 && !p.dz_declined) {
             // room for the per-residual depth derivatives: use at most half
             // of the free device memory, else keep recomputing them
             size_t free_b = 0, total_b = 0;
             EPO_HIP(hipMemGetInfo(&free_b, &total_b));
-            if ((uint64_t)p.n_residuals * sizeof(float) <= free_b / 2)
-                p.dz.alloc((size_t)p.n_residuals);
+            if ((uint64_t)p.dz_size * sizeof(float) <= free_b / 2)
+                p.dz.alloc((size_t)p.dz_size);
             else
                 p.dz_declined = true;
         }
