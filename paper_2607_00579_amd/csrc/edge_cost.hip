@@ -5,18 +5,18 @@
 //
 // Fused kernel, per residual (source edge pixel p = (u, v) with depth Z of
 // view i, directed pair i -> j):
-//   lift + warp + project in one step: h = Z B (u, v, 1)^T + c with
-//     B = K_j R_ji K_i^-1 and c = K_j t_ji, so u' = h_x / h_z, v' = h_y / h_z
-//     and the target-camera depth is z = h_z (the paper lifts to the world once
-//     per image and projects per pair; folding the pose-free lift into one
-//     3x3 per pair gives the same point with fewer operations); this
-//     coordinate, the validity test and the cell split are float64, the rest
-//     of the residual and its adjoint float32;
+//   lift + warp in one step: X' = Z M (u, v, 1)^T + t_ji with M = R_ji K_i^-1
+//     (the paper lifts to the world once per image and projects per pair;
+//     folding the pose-free lift into one 3x3 per pair gives the same point
+//     with fewer operations), z = X'_z, x_n = X'_x / z, y_n = X'_y / z,
+//     u' = fx_j x_n + cx_j, v' = fy_j y_n + cy_j; this coordinate, the
+//     validity test and the cell split are float64, the rest of the residual
+//     and its adjoint float32;
 //   valid iff z > z_min and 0 <= u' < W_j - 1 and 0 <= v' < H_j - 1;
 //   bilinear D from the cell floor(u'), floor(v'); d^ = min(D, lambda);
 //   rho = Huber(d^); rho' = dHuber/dd^ if D < lambda else 0;
 //   adjoint: with A_u = rho' dD/du' fx_j, A_v = rho' dD/dv' fy_j, the
-//   normalised target coordinates x_n = (u' - cx_j)/fx_j, y_n likewise and
+//   normalised target coordinates x_n, y_n and
 //   w = -(A_u x_n + A_v y_n), the left-twist gradient of the target pose is
 //     (A_u, A_v, w) / z   and   (y_n w - A_v, A_u - x_n w, x_n A_v - y_n A_u)
 //   (the translation block is dH/dX', the rotation block X' x dH/dX', in
@@ -203,11 +203,11 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
     }
     Acc a{0, 0, 0, 0, 0, 0, 0, 0, 0};
     int n = 0;                                  // valid residuals of this thread
-    // two residuals in flight per thread (about 50 VGPRs, so the SIMD keeps
-    // eight waves to hide the record load and the dependent tap gather);
-    // unrolling all P would multiply the float64 live ranges
-    // (the refinement variant keeps one: its focal sums and ray components
-    // would push two past 64 VGPRs, below eight waves per SIMD)
+    // two residuals in flight per thread (59 VGPRs, so the SIMD keeps eight
+    // waves to hide the record load and the dependent tap gather); unrolling
+    // all P would multiply the float64 live ranges (the refinement variant
+    // keeps one: its focal sums and ray components would push two past 64
+    // VGPRs, below eight waves per SIMD)
     constexpr int U = (P < 2 || EXT) ? 1 : 2;
     // the trip count follows the tile's own size (uniform over the
     // workgroup), so a pair's short last tile costs only its residuals

@@ -9,16 +9,20 @@
 // tile, row-major inside a tile, so that the threads of a wave hold nearby
 // source pixels whose projections fall in nearby target pixels.
 //
-// Sampling textures (one 4-byte word per pixel, same packing as the maps):
-//   format 1  float32 sqrt(d2)
-//   format 2  the four taps of the bilinear cell whose top-left corner is the
-//             pixel, as bytes min(d2, 255).  The DTF is 1-Lipschitz, so when
+// Sampling textures:
+//   format 1  float32 sqrt(d2) per pixel, row-major like the maps
+//   format 2  per pixel the four taps of the bilinear cell whose top-left
+//             corner is the pixel, as bytes min(d2, 255), stored in blocks of
+//             8 x 4 pixels (one 128-byte line each), blocks row-major.  The
+//             DTF is 1-Lipschitz, so when
 //             any tap of a cell has d2 >= 255 every tap is at least
 //             sqrt(255) - sqrt(2) > 14.55; the sample then exceeds any clamp
 //             lambda <= 14.5 with both the true and the saturated taps, and is
 //             clamped with zero gradient either way.  Below saturation the
 //             taps are the same float32 sqrt(d2) as format 1, so both formats
 //             give bitwise identical residuals.
+//   format 3  per pixel the four float32 taps of the cell (16 bytes),
+//             row-major.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

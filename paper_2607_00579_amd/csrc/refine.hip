@@ -17,8 +17,9 @@
 // reproducible.  dL/dbeta_p = dL/dZ_p and dL/dalpha_p = Z0_p dL/dZ_p.
 // Two forms of that pass, with bitwise identical results:
 //   stored     the pair-major refinement kernel has written every residual's
-//              dH/dZ (float32, 4 bytes per residual); the pass only gathers
-//              them (coalesced: consecutive records of one pair are adjacent)
+//              dH/dZ (float32, 4 bytes per residual) source-major: each
+//              256-record block of a source holds one 1 KB chunk per pair out
+//              of it, so the pass reads one contiguous run per block
 //   recompute  no room for that buffer: the pass evaluates every residual
 //              again from the record, the pair descriptor and the texture.
 #include "residual.h"
