@@ -344,7 +344,9 @@ EPO_API epo_status epo_plan_sampled_pairs(epo_plan plan, uint8_t* selected, void
  *   param_grad  float32 [n_scenes][EPO_MLP_PARAMS] (written);
  *   delta_grad  float64 [V][3] (written)
  * epo_mlp_setup allocates the activation store (once per plan; about 1.6 KB
- * per view).  epo_mlp_backward uses the activations of the last forward.
+ * per view, plus 272 KB per scene of weights packed in bf16 for the matrix
+ * cores).  epo_mlp_backward uses the activations and the packed weights of
+ * the last forward (params must hold the same values).
  * epo_mlp_step: AdamW (x <- x (1 - lr wd), then Adam with bias correction at
  * step = *step + 1) on every parameter (wd_mlp) and delta (wd_delta), lr per
  * scene [n_scenes]; increments *step.  No allocation after set-up, no

@@ -68,6 +68,9 @@ constexpr int kQuadBlockW = 8;
 constexpr int kQuadBlockH = 4;
 static_assert(kQuadBlockW * kQuadBlockH == 32, "a quad block is 32 texels (shift by 5)");
 
+// bf16 weights of one scene's refiner MLP packed in MFMA operand order
+constexpr int kMlpPacked = 139264;
+
 // zero records allocated past the last edge record: the fused kernel's last
 // iteration over a tile reads up to two 256-record rows past the tile's end
 // (masked) instead of clamping every row index
@@ -227,6 +230,7 @@ struct Plan {
     DevBuf<int64_t> mlp_row_off;          // S + 1
     DevBuf<uint16_t> mlp_act;             // mlp_rows x (16 + 6 x 128) bf16
     DevBuf<float> mlp_out;                // mlp_rows x 12 MLP outputs
+    DevBuf<uint16_t> mlp_packed;          // S x kMlpPacked bf16 weights in MFMA operand order
     // focal and depth refinement: f = f0 (1 + gamma_v), Z = Z0 alpha + beta
     DevBuf<float> K0_d;                   // V x 4 intrinsics as given (K_d holds the refined ones)
     DevBuf<double> gamma_d;               // V: current focal scales gamma

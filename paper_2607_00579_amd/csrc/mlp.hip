@@ -32,6 +32,23 @@ constexpr int kRows = 64;         // rows per chunk
 constexpr int kLd = kH + 8;       // LDS row stride (bf16) of a forward activation
 constexpr int kLdB = kH;          // LDS row stride of a backward gradient (fits 64 KB)
 
+// Packed bf16 weights, per scene (written by mlp_pack_kernel from the float32
+// parameters before every forward): the B operand of each product, row j of
+// a block holding the eight-element fragments of output column j, so a lane
+// reads one fragment with one 16-byte load.
+//   forward, layer L:  Wf_L[j][k] = W_L[j][k], rows padded to 32 for the last
+//                      layer (12 outputs), columns to 16 for the first (12 inputs)
+//   backward, dh_L = dY_{L+1} W_{L+1}:  Wt_L[j][k] = W_{L+1}[k][j], columns
+//                      padded to 16 for the last layer (12 outputs)
+constexpr int kFwdOff[6] = {0, 2048, 18432, 34816, 51200, 67584};
+constexpr int kFwdLd[6] = {16, 128, 128, 128, 128, 128};
+constexpr int kBwdOff[6] = {0, 71680, 88064, 104448, 120832, 137216};   // index L = 1..5
+constexpr int kBwdLd[6] = {0, 128, 128, 128, 128, 16};
+constexpr int kPacked = 139264;
+static_assert(kFwdOff[5] + 32 * 128 == kBwdOff[1], "packed forward block");
+static_assert(kBwdOff[5] + 128 * 16 == kPacked, "packed backward block");
+static_assert(kPacked == kMlpPacked, "packed size");
+
 // parameter offsets (W1, b1, ..., W6, b6), one scene's flat float32 vector
 constexpr int kOffW[6] = {0, 1664, 18176, 34688, 51200, 67712};
 constexpr int kOffB[6] = {1536, 18048, 34560, 51072, 67584, 69248};
@@ -57,6 +74,29 @@ __device__ __forceinline__ f32x16 mfma_tile(FA A, FB B, int K) {
         }
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
     }
+    return c;
+}
+
+// the same tile with both operands read as 16-byte fragments: A(i, k) at
+// A[(i0 + i) lda + k] (LDS), B(k, j) at B[(j0 + j) ldb + k] (packed weights)
+template <int K>
+__device__ __forceinline__ f32x16 mfma_tile_vec(const __bf16* A, int lda, int i0,
+                                                const __bf16* __restrict__ B, int ldb, int j0) {
+    static_assert(K % 16 == 0, "K is a multiple of the MFMA k step");
+    constexpr int S = K / 16;
+    const int l = threadIdx.x & 63;
+    const __bf16* pa = A + (i0 + (l & 31)) * lda + 8 * (l >> 5);
+    const __bf16* pb = B + (j0 + (l & 31)) * ldb + 8 * (l >> 5);
+    bf16x8 a[S], b[S];
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+        a[st] = *reinterpret_cast<const bf16x8*>(pa + 16 * st);
+        b[st] = *reinterpret_cast<const bf16x8*>(pb + 16 * st);
+    }
+    f32x16 c = {};
+#pragma unroll
+    for (int st = 0; st < S; ++st)
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[st], b[st], c, 0, 0, 0);
     return c;
 }
 
@@ -133,16 +173,42 @@ struct Scratch {
     int64_t rows;    // total rows (the stride of h's layers)
 };
 
+// float32 parameters -> packed bf16 operands (one grid row per scene)
+__global__ __launch_bounds__(256) void mlp_pack_kernel(const float* __restrict__ params,
+                                                       __bf16* __restrict__ packed) {
+    const int s = blockIdx.y;
+    const float* __restrict__ W = params + (int64_t)s * EPO_MLP_PARAMS;
+    __bf16* __restrict__ P = packed + (int64_t)s * kPacked;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kPacked;
+         e += gridDim.x * blockDim.x) {
+        float v = 0.0f;
+        if (e < kBwdOff[1]) {
+            int L = 0;
+            while (L < 5 && e >= kFwdOff[L + 1]) ++L;
+            const int j = (e - kFwdOff[L]) / kFwdLd[L], k = (e - kFwdOff[L]) % kFwdLd[L];
+            if (j < kLayerOut[L] && k < kLayerIn[L]) v = W[kOffW[L] + j * kLayerIn[L] + k];
+        } else {
+            int L = 1;
+            while (L < 5 && e >= kBwdOff[L + 1]) ++L;
+            const int j = (e - kBwdOff[L]) / kBwdLd[L], k = (e - kBwdOff[L]) % kBwdLd[L];
+            if (k < kLayerOut[L]) v = W[kOffW[L] + k * kLayerIn[L] + j];
+        }
+        P[e] = to_bf16(v);
+    }
+}
+
 __global__ __launch_bounds__(256) void mlp_forward_kernel(
     const float* __restrict__ params, const double* __restrict__ poses0,
     const double* __restrict__ delta, const int32_t* __restrict__ view_ptr,
     const int32_t* __restrict__ view_idx, const int64_t* __restrict__ row_off, Scratch sc,
-    double* __restrict__ poses) {
-    __shared__ __bf16 hA[kRows * kLd], hB[kRows * kLd], h1s[kRows * kLd];
+    const __bf16* __restrict__ packed, double* __restrict__ poses) {
+    // 16-byte aligned: the MFMA operands are read as 16-byte fragments
+    __shared__ __attribute__((aligned(16))) __bf16 hA[kRows * kLd], hB[kRows * kLd], h1s[kRows * kLd];
     __shared__ float os[kRows * kIn];
     const int s = blockIdx.x;
     const int v0 = view_ptr[s], n = view_ptr[s + 1] - v0;
     const float* __restrict__ W = params + (int64_t)s * EPO_MLP_PARAMS;
+    const __bf16* __restrict__ Pk = packed + (int64_t)s * kPacked;
     const int wave = threadIdx.x >> 6;
     for (int c0 = 0; c0 < n; c0 += kRows) {
         const int64_t g0 = row_off[s] + c0;               // first global row of the chunk
@@ -160,16 +226,13 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(
         __bf16* in = hA;
         __bf16* out = hB;
         for (int L = 0; L < 5; ++L) {
-            const float* __restrict__ Wl = W + kOffW[L];
             const float* __restrict__ bl = W + kOffB[L];
-            const int K = L == 0 ? kInPad : kH, Kreal = kLayerIn[L];
             __bf16* dst = L == 0 ? h1s : out;
             for (int t = wave; t < (kRows / 32) * (kH / 32); t += 4) {
                 const int i0 = 32 * (t / (kH / 32)), j0 = 32 * (t % (kH / 32));
-                const f32x16 acc = mfma_tile(
-                    [&](int i, int k) { return in[(i0 + i) * kLd + k]; },
-                    [&](int k, int j) { return k < Kreal ? to_bf16(Wl[(j0 + j) * Kreal + k]) : to_bf16(0.0f); },
-                    K);
+                const f32x16 acc =
+                    L == 0 ? mfma_tile_vec<kInPad>(in, kLd, i0, Pk + kFwdOff[0], kFwdLd[0], j0)
+                           : mfma_tile_vec<kH>(in, kLd, i0, Pk + kFwdOff[L], kFwdLd[L], j0);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int i = i0 + tile_row(r), j = j0 + tile_col();
@@ -196,14 +259,10 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(
         }
         // layer 6: o = h5 W6^T + b6 (float32, 12 outputs)
         {
-            const float* __restrict__ Wl = W + kOffW[5];
             const float* __restrict__ bl = W + kOffB[5];
             for (int t = wave; t < kRows / 32; t += 4) {
                 const int i0 = 32 * t;
-                const f32x16 acc = mfma_tile(
-                    [&](int i, int k) { return in[(i0 + i) * kLd + k]; },
-                    [&](int k, int j) { return j < kIn ? to_bf16(Wl[j * kH + k]) : to_bf16(0.0f); },
-                    kH);
+                const f32x16 acc = mfma_tile_vec<kH>(in, kLd, i0, Pk + kFwdOff[5], kFwdLd[5], 0);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int i = i0 + tile_row(r), j = tile_col();
@@ -263,13 +322,14 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(
     const float* __restrict__ params, const double* __restrict__ poses0,
     const double* __restrict__ poses, const double* __restrict__ grad,
     const int32_t* __restrict__ view_ptr, const int32_t* __restrict__ view_idx,
-    const int64_t* __restrict__ row_off, Scratch sc, float* __restrict__ param_grad,
-    double* __restrict__ delta_grad) {
-    __shared__ __bf16 dA_[kRows * kLdB], dB_[kRows * kLdB];
+    const int64_t* __restrict__ row_off, Scratch sc, const __bf16* __restrict__ packed,
+    float* __restrict__ param_grad, double* __restrict__ delta_grad) {
+    __shared__ __attribute__((aligned(16))) __bf16 dA_[kRows * kLdB], dB_[kRows * kLdB];
     __shared__ float dh3[kRows * kH];
     const int s = blockIdx.x;
     const int v0 = view_ptr[s], n = view_ptr[s + 1] - v0;
-    const float* __restrict__ W = params + (int64_t)s * EPO_MLP_PARAMS;
+    // the weights as the last forward packed them (params holds the same values)
+    const __bf16* __restrict__ Pk = packed + (int64_t)s * kPacked;
     float* __restrict__ G = param_grad + (int64_t)s * EPO_MLP_PARAMS;
     const int wave = threadIdx.x >> 6;
     if (n == 0) {
@@ -326,14 +386,11 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(
         __bf16* dYn = dB_;                                   // next (lower) layer's dY
         for (int L = 5; L >= 1; --L) {
             // dh_L = dY_{L+1} W_{L+1}  (rows x 128), K = out of layer L+1
-            const float* __restrict__ Wn = W + kOffW[L];
-            const int Kn = kLayerOut[L], Kpad = L == 5 ? kInPad : kH;
+            const __bf16* __restrict__ Wt = Pk + kBwdOff[L];
             for (int t = wave; t < (kRows / 32) * (kH / 32); t += 4) {
                 const int i0 = 32 * (t / (kH / 32)), j0 = 32 * (t % (kH / 32));
-                const f32x16 acc = mfma_tile(
-                    [&](int i, int k) { return dYc[(i0 + i) * kLdB + k]; },
-                    [&](int k, int j) { return k < Kn ? to_bf16(Wn[k * kH + j0 + j]) : to_bf16(0.0f); },
-                    Kpad);
+                const f32x16 acc = L == 5 ? mfma_tile_vec<kInPad>(dYc, kLdB, i0, Wt, kBwdLd[5], j0)
+                                          : mfma_tile_vec<kH>(dYc, kLdB, i0, Wt, kBwdLd[L], j0);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int i = i0 + tile_row(r), j = j0 + tile_col();
@@ -441,14 +498,18 @@ void mlp_setup(Plan& p, hipStream_t s) {
                            hipMemcpyHostToDevice, s));
     p.mlp_act.alloc((size_t)p.mlp_rows * (kInPad + 6 * kH));
     p.mlp_out.alloc((size_t)p.mlp_rows * kIn);
+    p.mlp_packed.alloc((size_t)p.S * kPacked);
     EPO_HIP(hipStreamSynchronize(s));
 }
 
 void launch_mlp_forward(Plan& p, const float* params, const double* poses0, const double* delta,
                         double* poses, hipStream_t s) {
+    __bf16* packed = reinterpret_cast<__bf16*>(p.mlp_packed.p);
+    mlp_pack_kernel<<<dim3(64, (unsigned)p.S), 256, 0, s>>>(params, packed);
+    EPO_CHECK_LAUNCH();
     mlp_forward_kernel<<<(unsigned)p.S, 256, 0, s>>>(params, poses0, delta, p.scene_view_ptr.p,
                                                      p.scene_view_idx.p, p.mlp_row_off.p,
-                                                     scratch_of(p), poses);
+                                                     scratch_of(p), packed, poses);
     EPO_CHECK_LAUNCH();
 }
 
@@ -457,8 +518,9 @@ void launch_mlp_backward(Plan& p, const float* params, const double* poses0, con
                          hipStream_t s) {
     mlp_backward_kernel<<<(unsigned)p.S, 256, 0, s>>>(params, poses0, poses, grad,
                                                       p.scene_view_ptr.p, p.scene_view_idx.p,
-                                                      p.mlp_row_off.p, scratch_of(p), param_grad,
-                                                      delta_grad);
+                                                      p.mlp_row_off.p, scratch_of(p),
+                                                      reinterpret_cast<const __bf16*>(p.mlp_packed.p),
+                                                      param_grad, delta_grad);
     EPO_CHECK_LAUNCH();
 }
 
