@@ -53,9 +53,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, options: dict, n_residuals: int):
-    """HBM bytes per launch from the committed PMC summary, if it was taken
-    on the current kernel source with the same workload and schedule."""
+def measured_counters(workload: str, options: dict, n_residuals: int):
+    """The committed PMC summary of the fused kernel, if it was taken on the
+    current kernel source with the same workload and schedule."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -64,7 +64,7 @@ def measured_traffic(workload: str, options: dict, n_residuals: int):
     if (rec.get("kernel_hash") != kernel_source_hash() or rec.get("workload") != workload
             or rec.get("options") != options or rec.get("n_residuals") != n_residuals):
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec
 
 
 def cpu_baseline(prob, budget_s: float = 15.0):
@@ -441,12 +441,21 @@ def main():
         f"{value / 1e9:.1f} G residual+grad/s")
 
     achieved = BYTES_PER_RESIDUAL * R_expected / (kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, options, R_expected)
+    counters = measured_counters(args.workload, options, R_expected)
+    traffic = counters.get("hbm_bytes_per_launch") if counters else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": "edge_cost_kernel",
                 "kernel_ms": round(kernel_ms, 4),
                 "bytes_per_launch": BYTES_PER_RESIDUAL * R_expected}
+    if counters and counters.get("l2_read_requests_per_launch"):
+        # what bounds the kernel: its L1 -> L2 read requests (128-byte lines)
+        l2_bytes = 128.0 * counters["l2_read_requests_per_launch"]
+        roofline["l2"] = {"read_requests_per_launch": counters["l2_read_requests_per_launch"],
+                          "read_bytes_per_launch": l2_bytes,
+                          "achieved_TBps": round(l2_bytes / (kernel_ms * 1e-3) / 1e12, 2),
+                          "hit_rate": round(counters["l2_hit_rate"], 4),
+                          "channel_busy": round(counters["l2_channel_busy"], 3)}
 
     out = {"metric": METRIC, "value": value, "unit": "residual+grad evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
