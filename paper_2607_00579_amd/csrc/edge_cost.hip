@@ -359,14 +359,17 @@ void launch_cost_kernel(Plan& p, float* dz, hipStream_t s) {
                           : FMT == 3 ? reinterpret_cast<const uint32_t*>(p.tex_q32.p)
                                      : reinterpret_cast<const uint32_t*>(p.tex_f32.p);
     const int nq = p.n_xcd_queues;
-    // with pair sub-sampling the step's tile count is known only on the
-    // device: workgroups claim tiles from the compacted queues (persistent)
-    const bool persistent = p.opt.persistent == 1 || p.sample_budget > 0;
+    const bool persistent = p.opt.persistent == 1;
     unsigned grid;
     if (persistent) {
         int64_t want = (int64_t)p.n_cu * 8;
         want = std::min<int64_t>(want, ceil_div(p.n_tiles, 1) + nq);
         grid = (unsigned)(ceil_div(want, nq) * nq);
+    } else if (p.sample_budget > 0) {
+        // with pair sub-sampling the step's tile count is known only on the
+        // device: enough workgroups for every tile, split as the compacted
+        // list is (nq equal queues); those past a queue's end exit at once
+        grid = (unsigned)(ceil_div(p.n_tiles, nq) * nq);
     } else {
         int64_t per_q = 0;
         for (int q = 0; q < nq; ++q)
