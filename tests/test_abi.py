@@ -135,3 +135,21 @@ def test_plan_create_rejects_z_min_out_of_range(lib, z_min):
     with pytest.raises(lib.EpoError) as e:
         lib.plan_create(**_plan_args(params=lib.CostParams(1.0, z_min, 0, 10.0)))
     assert e.value.status == lib.ERR_INVALID_ARG and "z_min" in str(e.value)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No fallback path: without libepo.so the binding raises."""
+    from paper_2607_00579_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libepo.so"))
+    with pytest.raises(RuntimeError, match="no fallback"):
+        _lib.load()
+
+
+def test_cpu_device_is_refused():
+    """The package has no CPU path: a plan on a CPU device is refused."""
+    from paper_2607_00579_amd.api import EdgePlan
+    from synth import fixtures
+    p = fixtures.odd_size_views()
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        EdgePlan.from_problem(p, device="cpu")
