@@ -29,18 +29,18 @@ __device__ inline void exp_coeffs(double th, double& a, double& b, double& c) {
     }
 }
 
-// single workgroup: the step counter is read by every thread before the one
-// increment at the end
-__global__ __launch_bounds__(256) void pose_step_kernel(
+// one thread per view; every thread reads the step counter, which
+// advance_step_kernel increments afterwards
+__global__ __launch_bounds__(64) void pose_step_kernel(
     double* __restrict__ poses, double* __restrict__ m, double* __restrict__ w2,
     const double* __restrict__ grad, int32_t V, const int32_t* __restrict__ scene_of_view,
     const uint8_t* __restrict__ fixed, const double* __restrict__ lr, double b1, double b2,
-    double eps, int32_t* __restrict__ step) {
+    double eps, const int32_t* __restrict__ step) {
     const int s = step[0] + 1;
     const double bc1 = 1.0 - pow(b1, (double)s);
     const double bc2 = 1.0 - pow(b2, (double)s);
-    for (int v = threadIdx.x; v < V; v += blockDim.x) {
-        if (fixed && fixed[v]) continue;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < V && !(fixed && fixed[v])) {
         const double lr_v = lr[scene_of_view ? scene_of_view[v] : 0];
         double xi[6];
         for (int k = 0; k < 6; ++k) {
@@ -82,9 +82,10 @@ __global__ __launch_bounds__(256) void pose_step_kernel(
             }
         }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) step[0] = s;
 }
+
+// the step counter advances after every view has read it (its own launch)
+__global__ void advance_step_kernel(int32_t* step) { step[0] += 1; }
 
 __global__ __launch_bounds__(256) void schedule_kernel(const int32_t* __restrict__ step,
                                                        int32_t S, float l0, float l1,
@@ -113,8 +114,14 @@ __global__ __launch_bounds__(256) void schedule_kernel(const int32_t* __restrict
 void launch_pose_step(double* poses, double* m, double* v, const double* grad, int32_t n_views,
                       const int32_t* scene_of_view, const uint8_t* fixed, const double* lr,
                       double b1, double b2, double eps, int32_t* step, hipStream_t s) {
-    pose_step_kernel<<<1, 256, 0, s>>>(poses, m, v, grad, n_views, scene_of_view, fixed, lr, b1,
-                                       b2, eps, step);
+    // one view per thread over the whole chip (the float64 exponential map is
+    // a long dependent chain, so views are spread rather than looped over)
+    if (n_views > 0) {
+        pose_step_kernel<<<(unsigned)ceil_div(n_views, 64), 64, 0, s>>>(
+            poses, m, v, grad, n_views, scene_of_view, fixed, lr, b1, b2, eps, step);
+        EPO_CHECK_LAUNCH();
+    }
+    advance_step_kernel<<<1, 1, 0, s>>>(step);
     EPO_CHECK_LAUNCH();
 }
 
