@@ -231,3 +231,36 @@ def test_odd_view_sizes(gpu, fmt):
         ref = gpu_eval(plan_for(p, options=dict(opts, texture_format=1)), p.poses_init, 10.0)
         for k in ("loss", "grad", "pair_cost", "pair_valid"):
             assert np.array_equal(g[k], ref[k]), k
+
+
+def _one_view_scene():
+    p = fixtures.odd_size_views()
+    return fixtures.problem_from_maps([p.width[0]], [p.height[0]], [p.K[0]], [p.edge_map(0)],
+                                      [p.depth_map(0)], [p.poses_init[0]], np.zeros((0, 2)),
+                                      name="one_view")
+
+
+def test_scenes_without_pairs(gpu):
+    """A scene with one view has no pairs: its loss and gradient are exactly
+    zero, alone (a plan with no pairs at all) and batched beside a scene
+    that has pairs, whose results are unchanged; the pose step leaves its
+    pose where it is."""
+    from synth.scenes import config_c1, pack
+    one = _one_view_scene()
+    g = gpu_eval(plan_for(one), one.poses_init, 10.0)
+    assert np.array_equal(g["loss"], np.zeros(1)) and not np.any(g["grad"])
+    c1 = pack(list(config_c1().scenes), "c1")
+    mix = pack(list(config_c1().scenes) + list(one.scenes), "mix")
+    plan, gm, r = check_against_oracle(mix, mix.poses_init, 10.0)
+    assert gm["loss"][1] == 0.0 and not np.any(gm["grad"][2])
+    alone = gpu_eval(plan_for(c1), c1.poses_init, 10.0)
+    assert np.array_equal(gm["loss"][:1], alone["loss"])
+    assert np.array_equal(gm["grad"][:2], alone["grad"])
+    P = torch.from_numpy(mix.poses_init.copy()).cuda()
+    out = plan.cost(P, 10.0, grad=True)
+    m = torch.zeros(mix.n_views, 6, dtype=torch.float64, device="cuda")
+    v = torch.zeros_like(m)
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    plan.pose_step(P, m, v, out["grad"], 3e-3, step)
+    assert torch.equal(P[2], torch.from_numpy(mix.poses_init[2]).cuda())
+    assert int(step.item()) == 1
