@@ -295,6 +295,64 @@ def refiner_timing(plan, prob, steps, warmup, R):
                     "translation offsets, AdamW; lambda/lr schedule as the twist loop"}
 
 
+def relative_rotation_errors(P, Pgt):
+    """Angles (deg) between estimated and true relative rotations R_i R_j^T
+    over all view pairs (invariant to the global gauge the loss leaves free)."""
+    import numpy as np
+    R, Rg = P[:, :, :3], Pgt[:, :, :3]
+    errs = []
+    for i in range(len(P)):
+        for j in range(i + 1, len(P)):
+            D = (R[i] @ R[j].T) @ (Rg[i] @ Rg[j].T).T
+            c = np.clip((np.trace(D) - 1.0) / 2.0, -1.0, 1.0)
+            errs.append(np.degrees(np.arccos(c)))
+    return np.array(errs)
+
+
+def parameterization_ablation(name="c3", n=1000):
+    """The two pose parameterizations on the same synthetic workload and
+    schedule (lambda 10 -> 6, lr warm-up then cosine over n steps): left-twist
+    Adam on the poses against the paper's refiner MLP + 6D rotation +
+    translation offset with AdamW.  Reports the relative rotation error
+    against the generator's ground truth before and after, and the step time."""
+    import numpy as np
+    import torch
+    from paper_2607_00579_amd.api import EdgePlan, PoseRefiner
+    from synth import make
+    p = make(name)
+    dev = torch.device("cuda:0")
+    e0 = relative_rotation_errors(p.poses_init, p.poses_gt)
+    out = {"workload": f"{name}: {WORKLOADS[name]}", "steps": n,
+           "initial_rre_deg": {"mean": float(e0.mean()), "median": float(np.median(e0))}}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for form in ("twist", "refiner"):
+        plan = EdgePlan.from_problem(p, device=dev)
+        step = torch.zeros(1, dtype=torch.int32, device=dev)
+        loss = torch.zeros(plan.n_scenes, dtype=torch.float64, device=dev)
+        if form == "twist":
+            poses = torch.from_numpy(p.poses_init.copy()).to(dev)
+            m = torch.zeros(p.n_views, 6, dtype=torch.float64, device=dev)
+            v = torch.zeros_like(m)
+            plan.capture_iteration(poses, m, v, step, loss, total=n)
+        else:
+            ref = PoseRefiner(plan, torch.from_numpy(p.poses_init.copy()).to(dev), seed=0)
+            ref.capture_iteration(step, loss, total=n)
+            poses = ref.poses
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(n):
+            plan.launch_iteration()
+        ev[1].record()
+        torch.cuda.synchronize()
+        e = relative_rotation_errors(poses.cpu().numpy(), p.poses_gt)
+        out[form] = {"final_rre_deg": {"mean": float(e.mean()), "median": float(np.median(e))},
+                     "final_loss": float(loss.sum().item()),
+                     "ms_per_step": round(ev[0].elapsed_time(ev[1]) / n, 4)}
+        log(f"ablation {name} {form}: relative rotation error {e0.mean():.3f} -> {e.mean():.3f} deg "
+            f"(median {np.median(e):.3f}), {out[form]['ms_per_step']:.3f} ms/step")
+    return out
+
+
 def viewgraph_timing(name="c3", stride=4):
     """Viewgraph construction (cycle-consistent reprojection of a stride-4
     pixel grid of every view into every other view of its scene and back) on
@@ -340,6 +398,9 @@ def main():
                     help="skip the sub-sampled step and viewgraph timings")
     ap.add_argument("--refine-only", action="store_true",
                     help="only eager joint-phase calls with depth gradients (for profilers)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also run both pose parameterizations for 1000 steps on c3 and "
+                         "report their relative rotation errors")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -473,6 +534,8 @@ def main():
         out["refiner_loop"] = refiner_timing(plan, prob, args.steps, args.warmup, R_expected)
         out["sub_sampled"] = sampled_timing(plan, prob, args.steps, args.warmup)
         out["viewgraph"] = viewgraph_timing()
+    if args.ablation:
+        out["parameterization_ablation"] = parameterization_ablation()
 
     # free what the baselines do not need
     dtf_flat = plan.dtf
