@@ -173,27 +173,49 @@ struct Scratch {
     int64_t rows;    // total rows (the stride of h's layers)
 };
 
-// float32 parameters -> packed bf16 operands (one grid row per scene)
+// float32 parameters -> packed bf16 operands, one grid row per scene: the
+// first kPackFwdBlocks workgroups copy the forward blocks (rows padded,
+// coalesced), the others transpose one 32 x 32 tile of a weight matrix each
+// through LDS (both the read and the write coalesced)
+constexpr int kPackFwdBlocks = 35;                 // x 2048 >= forward block size
+constexpr int kPackTiles[6] = {0, 16, 16, 16, 16, 4};   // 32 x 32 tiles of W_1 .. W_5
+constexpr int kPackBlocks = kPackFwdBlocks + 68;
+static_assert(kPackFwdBlocks * 2048 >= kBwdOff[1], "forward pack coverage");
+
 __global__ __launch_bounds__(256) void mlp_pack_kernel(const float* __restrict__ params,
                                                        __bf16* __restrict__ packed) {
+    __shared__ float tile[32][33];
     const int s = blockIdx.y;
     const float* __restrict__ W = params + (int64_t)s * EPO_MLP_PARAMS;
     __bf16* __restrict__ P = packed + (int64_t)s * kPacked;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kPacked;
-         e += gridDim.x * blockDim.x) {
-        float v = 0.0f;
-        if (e < kBwdOff[1]) {
+    if ((int)blockIdx.x < kPackFwdBlocks) {
+        for (int u = 0; u < 8; ++u) {
+            const int e = (int)blockIdx.x * 2048 + u * 256 + (int)threadIdx.x;
+            if (e >= kBwdOff[1]) break;
             int L = 0;
             while (L < 5 && e >= kFwdOff[L + 1]) ++L;
             const int j = (e - kFwdOff[L]) / kFwdLd[L], k = (e - kFwdOff[L]) % kFwdLd[L];
-            if (j < kLayerOut[L] && k < kLayerIn[L]) v = W[kOffW[L] + j * kLayerIn[L] + k];
-        } else {
-            int L = 1;
-            while (L < 5 && e >= kBwdOff[L + 1]) ++L;
-            const int j = (e - kBwdOff[L]) / kBwdLd[L], k = (e - kBwdOff[L]) % kBwdLd[L];
-            if (k < kLayerOut[L]) v = W[kOffW[L] + k * kLayerIn[L] + j];
+            const float v =
+                (j < kLayerOut[L] && k < kLayerIn[L]) ? W[kOffW[L] + j * kLayerIn[L] + k] : 0.0f;
+            P[e] = to_bf16(v);
         }
-        P[e] = to_bf16(v);
+        return;
+    }
+    // transposed blocks: Wt_L[j][k] = W_L[k][j] (k < out of layer L, else 0)
+    int t = (int)blockIdx.x - kPackFwdBlocks, L = 1;
+    while (L < 5 && t >= kPackTiles[L]) t -= kPackTiles[L++];
+    const int out = kLayerOut[L], in = kLayerIn[L], ld = kBwdLd[L];
+    const int nkb = (ld + 31) / 32;                 // tiles along k (the out index)
+    const int kb = t % nkb, jb = t / nkb;
+    const int c = (int)threadIdx.x & 31, r0 = (int)threadIdx.x >> 5;
+    for (int r = r0; r < 32; r += 8) {              // read rows k = kb * 32 + r of W_L
+        const int k = kb * 32 + r, j = jb * 32 + c;
+        tile[r][c] = (k < out) ? W[kOffW[L] + k * in + j] : 0.0f;
+    }
+    __syncthreads();
+    for (int r = r0; r < 32; r += 8) {              // write rows j = jb * 32 + r of Wt_L
+        const int j = jb * 32 + r, k = kb * 32 + c;
+        if (k < ld) P[kBwdOff[L] + j * ld + k] = to_bf16(tile[c][r]);
     }
 }
 
@@ -505,7 +527,7 @@ void mlp_setup(Plan& p, hipStream_t s) {
 void launch_mlp_forward(Plan& p, const float* params, const double* poses0, const double* delta,
                         double* poses, hipStream_t s) {
     __bf16* packed = reinterpret_cast<__bf16*>(p.mlp_packed.p);
-    mlp_pack_kernel<<<dim3(64, (unsigned)p.S), 256, 0, s>>>(params, packed);
+    mlp_pack_kernel<<<dim3(kPackBlocks, (unsigned)p.S), 256, 0, s>>>(params, packed);
     EPO_CHECK_LAUNCH();
     mlp_forward_kernel<<<(unsigned)p.S, 256, 0, s>>>(params, poses0, delta, p.scene_view_ptr.p,
                                                      p.scene_view_idx.p, p.mlp_row_off.p,
