@@ -167,7 +167,9 @@ __device__ inline void gram_schmidt_backward(const double* A, const double* G, d
 
 struct Scratch {
     __bf16* h0;      // [rows][16]
-    __bf16* h;       // [5][rows][128]: h1 .. h5
+    __bf16* h;       // [5][rows / 64][128][64]: h1 .. h5, each 64-row chunk
+                     // column-major (a column's rows contiguous for the
+                     // weight-gradient fragments)
     __bf16* r3;      // [rows][128]: relu of the third layer (its mask)
     float* o;        // [rows][12]: MLP outputs
     int64_t rows;    // total rows (the stride of h's layers)
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(
                         hv = to_bf16(y);
                     }
                     dst[i * kLd + j] = hv;
-                    sc.h[(int64_t)L * sc.rows * kH + (g0 + i) * kH + j] = hv;
+                    sc.h[(int64_t)L * sc.rows * kH + g0 * kH + j * kRows + i] = hv;
                 }
             }
             __syncthreads();
@@ -340,6 +342,56 @@ __device__ inline void weight_grad(FD dY, FH h, int out, int in, float* __restri
     }
 }
 
+// A read element-wise through FA, B as 16-byte fragments: B(k, j) at
+// B[(j0 + j) ldb + k]
+template <int K, class FA>
+__device__ __forceinline__ f32x16 mfma_tile_bvec(FA A, const __bf16* __restrict__ B, int ldb,
+                                                 int j0) {
+    constexpr int S = K / 16;
+    const int l = threadIdx.x & 63;
+    const __bf16* pb = B + (j0 + (l & 31)) * ldb + 8 * (l >> 5);
+    bf16x8 a[S], b[S];
+#pragma unroll
+    for (int st = 0; st < S; ++st) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[st][q] = A(l & 31, 16 * st + 8 * (l >> 5) + q);
+        b[st] = *reinterpret_cast<const bf16x8*>(pb + 16 * st);
+    }
+    f32x16 c = {};
+#pragma unroll
+    for (int st = 0; st < S; ++st)
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[st], b[st], c, 0, 0, 0);
+    return c;
+}
+
+// weight_grad for a 128-wide input whose stored activations are transposed
+// per chunk (hT[j kRows + k]: column j of the chunk contiguous over its rows)
+template <class FD>
+__device__ inline void weight_grad_t(FD dY, const __bf16* __restrict__ hT, int out,
+                                     float* __restrict__ gW, float* __restrict__ gb, bool first) {
+    const int wave = threadIdx.x >> 6;
+    const int tm = (out + 31) / 32, tn = kH / 32;
+    for (int t = wave; t < tm * tn; t += 4) {
+        const int i0 = 32 * (t / tn), j0 = 32 * (t % tn);
+        const f32x16 acc = mfma_tile_bvec<kRows>(
+            [&](int i, int k) { return i0 + i < out ? dY(k, i0 + i) : to_bf16(0.0f); }, hT, kRows,
+            j0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = i0 + tile_row(r), j = j0 + tile_col();
+            if (i < out) {
+                float* p = gW + i * kH + j;
+                *p = first ? acc[r] : *p + acc[r];
+            }
+        }
+    }
+    for (int j = threadIdx.x; j < out; j += 256) {
+        float sum = 0.0f;
+        for (int k = 0; k < kRows; ++k) sum += to_f32(dY(k, j));
+        gb[j] = first ? sum : gb[j] + sum;
+    }
+}
+
 __global__ __launch_bounds__(256) void mlp_backward_kernel(
     const float* __restrict__ params, const double* __restrict__ poses0,
     const double* __restrict__ poses, const double* __restrict__ grad,
@@ -361,9 +413,10 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(
     for (int c0 = 0; c0 < n; c0 += kRows) {
         const bool first = c0 == 0;
         const int64_t g0 = row_off[s] + c0;
-        auto H = [&](int L, int k, int j) {                // stored h_L (L = 1..5)
-            return sc.h[(int64_t)(L - 1) * sc.rows * kH + (g0 + k) * kH + j];
+        auto hT = [&](int L) {                             // stored h_L (L = 1..5)
+            return sc.h + (int64_t)(L - 1) * sc.rows * kH + g0 * kH;
         };
+        auto H = [&](int L, int k, int j) { return hT(L)[j * kRows + k]; };
         // dL/do per row from the pose chain (float64), as bf16 operand dY6
         for (int k = threadIdx.x; k < kRows * kInPad; k += 256)
             dA_[(k / kInPad) * kLdB + k % kInPad] = to_bf16(0.0f);
@@ -401,9 +454,8 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(
         }
         __syncthreads();
         // layer 6: dW6 = dY6^T h5, db6; dh5 = dY6 W6 -> dY5 = bf16(dh5 [h5 > 0])
-        weight_grad([&](int k, int i) { return dA_[k * kLdB + i]; },
-                    [&](int k, int j) { return H(5, k, j); }, kIn, kH, G + kOffW[5], G + kOffB[5],
-                    first);
+        weight_grad_t([&](int k, int i) { return dA_[k * kLdB + i]; }, hT(5), kIn,
+                      G + kOffW[5], G + kOffB[5], first);
         __bf16* dYc = dA_;                                   // current layer's dY
         __bf16* dYn = dB_;                                   // next (lower) layer's dY
         for (int L = 5; L >= 1; --L) {
@@ -431,9 +483,8 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(
             __syncthreads();
             // dW_L = dY_L^T h_{L-1}, db_L
             if (L >= 2) {
-                weight_grad([&](int k, int i) { return dYn[k * kLdB + i]; },
-                            [&](int k, int j) { return H(L - 1, k, j); }, kH, kH,
-                            G + kOffW[L - 1], G + kOffB[L - 1], first);
+                weight_grad_t([&](int k, int i) { return dYn[k * kLdB + i]; }, hT(L - 1), kH,
+                              G + kOffW[L - 1], G + kOffB[L - 1], first);
             } else {
                 weight_grad([&](int k, int i) { return dYn[k * kLdB + i]; },
                             [&](int k, int j) { return sc.h0[(g0 + k) * kInPad + j]; }, kH, kIn,
