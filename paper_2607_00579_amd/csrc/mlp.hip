@@ -269,10 +269,17 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(
                         hv = to_bf16(y);
                     }
                     dst[i * kLd + j] = hv;
-                    sc.h[(int64_t)L * sc.rows * kH + g0 * kH + j * kRows + i] = hv;
                 }
             }
             __syncthreads();
+            {
+                // the layer's activations to the store, column-major per chunk
+                // (coalesced: consecutive threads take consecutive rows); the
+                // next layer only reads dst, so no barrier is needed after
+                __bf16* __restrict__ gh = sc.h + (int64_t)L * sc.rows * kH + g0 * kH;
+                for (int e = threadIdx.x; e < kRows * kH; e += 256)
+                    gh[e] = dst[(e % kRows) * kLd + e / kRows];
+            }
             if (L == 0) {
                 in = h1s;                                  // layer 2 reads h1
             } else {
