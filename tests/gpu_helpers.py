@@ -25,6 +25,19 @@ def rel_norm_err(got, want, axis=None):
                  / max(np.linalg.norm(want, axis=axis).max(), 1e-300))
 
 
+def check_depth(got, want, name, tol=1e-4):
+    """Per-record depth derivatives, element-wise relative to the largest
+    magnitude; a residual whose clamp or Huber branch sits within float32
+    rounding of its threshold may flip, so a handful of records (at most 1 in
+    10^4) may miss the bar."""
+    scale = np.abs(want).max()
+    err = np.abs(got - want) / scale
+    bad = int((err > tol).sum())
+    say(f"{name}: max err {err.max():.2e}, 99.99% {np.quantile(err, 0.9999):.2e}, "
+        f"{bad} of {err.size} above {tol}")
+    assert bad <= max(2, err.size // 10000), bad
+
+
 def rotation_angle_deg(Ra, Rb):
     c = np.clip((np.trace(Ra @ Rb.T) - 1.0) / 2.0, -1.0, 1.0)
     return float(np.degrees(np.arccos(c)))

@@ -9,7 +9,7 @@ import torch
 
 from oracle import cost as ocost
 from oracle import edt as oedt
-from tests.gpu_helpers import problem, say
+from tests.gpu_helpers import check_depth, problem, rel_norm_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -132,3 +132,84 @@ def test_full_size_edt_sampled(gpu, name, n_views):
         got = d2[a + qy.astype(np.int64) * W + qx]
         assert np.array_equal(got, want), v
     say(f"{name}: EDT bit-exact on {len(views)} whole views and 2 x 4000 sampled pixels")
+
+
+def test_full_size_joint_phase_whole_scenes_c4(gpu):
+    """The joint phase on the whole 64-scene batch (autotuned schedule, seeded
+    non-identity focal and depth refinement), checked scene by scene: scenes
+    are independent, so each sampled scene's loss, pose and focal gradients
+    and every one of its records' depth derivatives are the oracle's on that
+    scene alone.  Sampled: the scene with the fewest residuals, the one with
+    the most image pairs among scenes of at most 2 M residuals and the one
+    with the fewest views among scenes of 768 x 576 images or larger."""
+    from paper_2607_00579_amd.api import EdgePlan
+    prob = problem("c4")
+    plan = EdgePlan.from_problem(prob)
+    P = torch.from_numpy(prob.poses_init.copy()).cuda()
+    chosen = plan.autotune(P, 10.0, iters=1)
+    lam = 8.0
+    ne = np.array([np.count_nonzero(prob.edge_map(v)) for v in range(prob.n_views)], np.int64)
+    off = np.concatenate([[0], np.cumsum(ne)])
+    assert plan.n_records == off[-1]
+    rng = np.random.default_rng(23)
+    gamma = rng.uniform(-0.02, 0.02, prob.n_views)
+    alpha = (1.0 + rng.uniform(-0.02, 0.02, off[-1])).astype(np.float32)
+    beta = rng.uniform(-0.02, 0.02, off[-1]).astype(np.float32)
+    plan.set_refinement(torch.from_numpy(gamma), torch.from_numpy(alpha), torch.from_numpy(beta))
+    g = {k: t.cpu().numpy() for k, t in plan.refine(P, lam).items()}
+    assert plan.device_status() == 0
+    # the library's refined values: float32(f0 (1 + gamma)) with the product
+    # in float64, float32(Z0 alpha + beta) (Z0 alpha exact)
+    K = prob.K.astype(np.float64).reshape(-1, 4).copy()
+    K[:, :2] = (prob.K.reshape(-1, 4)[:, :2].astype(np.float64)
+                * (1.0 + gamma)[:, None]).astype(np.float32)
+
+    S = int(prob.scene_of_view.max()) + 1
+    R = np.bincount(prob.scene_of_pair, weights=ne[prob.pairs[:, 0]], minlength=S)
+    npairs = np.bincount(prob.scene_of_pair, minlength=S)
+    px = np.zeros(S, np.int64)
+    np.maximum.at(px, prob.scene_of_view, prob.width.astype(np.int64) * prob.height)
+    small = np.flatnonzero(R <= 2e6)
+    big = np.flatnonzero(px >= 768 * 576)
+    nv = np.bincount(prob.scene_of_view, minlength=S)
+    scenes = sorted({int(np.argmin(R)), int(small[np.argmax(npairs[small])]),
+                     int(big[np.argmin(nv[big])])})
+    for s in scenes:
+        views = np.flatnonzero(prob.scene_of_view == s)
+        pair_ids = np.flatnonzero(prob.scene_of_pair == s)
+        depth, z0, rec, order = {}, [], [], []
+        for v in views:
+            # plan records of view v in plan order -> the oracle's row-major
+            # edge-pixel order
+            r = plan.view_records(int(v))
+            x = (r & 0xFFFF).astype(np.int64)
+            y = ((r >> np.uint64(16)) & np.uint64(0xFFFF)).astype(np.int64)
+            ys, xs = np.nonzero(prob.edge_map(int(v)))
+            keys = ys.astype(np.int64) * int(prob.width[v]) + xs
+            pos = np.searchsorted(keys, y * int(prob.width[v]) + x)
+            assert np.array_equal(keys[pos], y * int(prob.width[v]) + x)
+            idx = np.arange(off[v], off[v + 1])
+            zv = prob.depth_map(int(v))[ys, xs].astype(np.float64)[pos]
+            zr = np.zeros(ne[v])
+            zr[pos] = (zv * alpha[idx].astype(np.float64)
+                       + beta[idx].astype(np.float64)).astype(np.float32)
+            depth[int(v)] = zr
+            z0.append(zv)
+            rec.append(idx)
+            order.append((int(v), pos))
+        op = ocost.OracleProblem(prob, views=views.tolist())
+        r = op.evaluate(prob.poses_init, lam, pair_ids=pair_ids.tolist(), K=K, depth=depth)
+        e_l = abs(g["loss"][s] - r["loss"][s]) / abs(r["loss"][s])
+        e_p = rel_norm_err(g["grad"][views], r["grad"][views], axis=1)
+        want_gamma = r["grad_focal"][views] / (1.0 + gamma[views])
+        e_g = rel_norm_err(g["grad_gamma"][views], want_gamma)
+        say(f"c4 scene {s} ({views.size} views, {pair_ids.size} pairs, {int(R[s])} residuals, "
+            f"schedule {chosen}): loss err {e_l:.2e}, pose grad err {e_p:.2e}, "
+            f"focal err {e_g:.2e}")
+        assert e_l < 1e-4 and e_p < 1e-4 and e_g < 1e-4
+        want_beta = np.concatenate([r["grad_depth"][v][pos] for v, pos in order])
+        rec = np.concatenate(rec)
+        check_depth(g["grad_beta"][rec], want_beta, f"c4 scene {s} dL/dbeta")
+        check_depth(g["grad_alpha"][rec], np.concatenate(z0) * want_beta, f"c4 scene {s} dL/dalpha")
+    # the other scenes' outputs are finite
+    assert np.isfinite(g["loss"]).all() and np.isfinite(g["grad_beta"]).all()
