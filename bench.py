@@ -242,6 +242,42 @@ def sampled_timing(plan, prob, steps, warmup, budgets=(1024, 256, 64)):
     return res
 
 
+def early_exit_timing(plan, prob, steps, warmup):
+    """Captured iteration with the convergence test, once with stopped
+    scenes still evaluated (learning rate 0) and once with their tiles left
+    out of the launch (device-side early exit).  Thresholds that every scene
+    passes at once stop the whole batch after two replays, so the timed
+    replays show the floor of a replay whose scenes have all stopped."""
+    import torch
+    dev = plan.device
+    res = {}
+    for mode in (False, True):
+        poses = torch.from_numpy(prob.poses_init.copy()).to(dev)
+        m = torch.zeros(prob.n_views, 6, dtype=torch.float64, device=dev)
+        v = torch.zeros_like(m)
+        step = torch.zeros(1, dtype=torch.int32, device=dev)
+        loss = torch.zeros(plan.n_scenes, dtype=torch.float64, device=dev)
+        plan.convergence_reset(poses, 1, 1e30, 1, 1e30)
+        plan.capture_iteration(poses, m, v, step, loss, convergence=True, early_exit=mode)
+        for _ in range(max(warmup, 3)):
+            plan.launch_iteration()
+        torch.cuda.synchronize()
+        stopped = int((plan.convergence_query()["phase"] == 2).sum())
+        if stopped != plan.n_scenes:
+            log(f"early exit: only {stopped} of {plan.n_scenes} scenes stopped; not timed")
+            return {"error": f"{stopped} of {plan.n_scenes} scenes stopped"}
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.launch_iteration()
+        e1.record()
+        torch.cuda.synchronize()
+        res["skip_stopped" if mode else "evaluate_stopped"] = round(e0.elapsed_time(e1) / steps, 4)
+    log(f"every scene stopped: {res['evaluate_stopped']:.3f} ms/replay evaluating them, "
+        f"{res['skip_stopped']:.3f} ms/replay with early exit")
+    return {"ms_per_replay_all_stopped": res}
+
+
 def refiner_timing(plan, prob, steps, warmup, R):
     """The loop with the pose refiner parameterization (per-scene MLP, 6D
     rotation, translation offsets, AdamW), captured as one graph and
@@ -533,6 +569,7 @@ def main():
     if not args.no_extras:
         out["refiner_loop"] = refiner_timing(plan, prob, args.steps, args.warmup, R_expected)
         out["sub_sampled"] = sampled_timing(plan, prob, args.steps, args.warmup)
+        out["early_exit"] = early_exit_timing(plan, prob, args.steps, args.warmup)
         out["viewgraph"] = viewgraph_timing()
     if args.ablation:
         out["parameterization_ablation"] = parameterization_ablation()

@@ -364,7 +364,9 @@ EPO_API epo_status epo_mlp_backward(epo_plan plan, const float* params, const do
  * lr 0 for a scene stopped by the convergence test) -> fused cost + adjoint
  * at `poses` -> epo_mlp_backward -> epo_mlp_step (advances *step) ->
  * epo_mlp_forward of the new parameters into `poses` -> [pose-change test,
- * with_convergence != 0].  Before the first replay `poses` must hold
+ * with_convergence 1 or 2, as in epo_iteration_capture: with 2 a stopped
+ * scene's tiles are skipped, its parameter gradients read 0 and its
+ * parameters stay].  Before the first replay `poses` must hold
  * epo_mlp_forward of the current parameters (the backward reads that
  * forward's activations), and, with the test, epo_convergence_reset must
  * have been called on them.  Replaces a previously captured iteration; grad
@@ -468,6 +470,18 @@ EPO_API epo_status epo_convergence_query(epo_plan plan, int32_t* phase, double* 
  *   grad                          float64 [V][6] scratch/result of each replay
  *   fixed_mask                    uint8 [V] or NULL
  *   schedule constants            as in epo_schedule
+ *   with_convergence              0: no test; 1: the test, a stopped scene
+ *                                 gets learning rate 0 (its cost is still
+ *                                 evaluated); 2: as 1, and from the replay
+ *                                 after a scene stops its tiles are left out
+ *                                 of the fused launch (device-side early exit:
+ *                                 the launch's tile list is compacted on the
+ *                                 device, as with pair sub-sampling); its
+ *                                 loss entry keeps the value of its last
+ *                                 evaluated step, its gradient rows read 0.
+ *                                 Poses, phases and the other scenes' results
+ *                                 are bitwise those of mode 1.  Other values:
+ *                                 EPO_ERR_INVALID_ARG.
  * epo_iteration_launch replays it on `stream` (any stream of the device).
  * ------------------------------------------------------------------------- */
 EPO_API epo_status epo_iteration_capture(epo_plan plan, double* poses, double* adam_m, double* adam_v,

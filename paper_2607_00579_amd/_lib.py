@@ -217,7 +217,7 @@ def mlp_iteration_capture(plan, params, m, v, param_grad, delta, dm, dv, delta_g
         plan, _ptr(params), _ptr(m), _ptr(v), _ptr(param_grad), _ptr(delta), _ptr(dm), _ptr(dv),
         _ptr(delta_grad), _ptr(poses0), _ptr(poses), _ptr(step), _ptr(loss), _ptr(grad), lambda0,
         lambda1, anneal_steps, peak_lr, warmup, total, beta1, beta2, eps, wd_mlp, wd_delta,
-        1 if with_convergence else 0, stream))
+        int(with_convergence), stream))
 
 
 def plan_set_pair_sampling(plan, budget, seed, step, stream):
@@ -254,7 +254,7 @@ def iteration_capture(plan, poses, m, v, step, loss, grad, fixed_mask, lambda0, 
     _check(load().epo_iteration_capture(plan, _ptr(poses), _ptr(m), _ptr(v), _ptr(step),
                                         _ptr(loss), _ptr(grad), _ptr(fixed_mask), lambda0,
                                         lambda1, anneal_steps, peak_lr, warmup, total, beta1,
-                                        beta2, eps, 1 if with_convergence else 0, stream))
+                                        beta2, eps, int(with_convergence), stream))
 
 
 class ConvergenceParams(C.Structure):

@@ -256,11 +256,17 @@ class EdgePlan:
 
     def capture_iteration(self, poses, m, v, step, loss, grad=None, fixed_mask=None,
                           lambda0=10.0, lambda1=6.0, anneal_steps=1000, peak_lr=3e-3, warmup=25,
-                          total=2000, beta1=0.9, beta2=0.999, eps=1e-8, convergence=False):
+                          total=2000, beta1=0.9, beta2=0.999, eps=1e-8, convergence=False,
+                          early_exit=False):
+        """Capture one iteration (schedule -> cost + adjoint -> reductions ->
+        pose step [-> convergence test]); replay with launch_iteration().
+        With the test, early_exit=True leaves a stopped scene's tiles out of
+        the following replays (its loss keeps its last value)."""
         self._graph_refs = (poses, m, v, step, loss, grad, fixed_mask)   # keep buffers alive
+        mode = (2 if early_exit else 1) if convergence else 0
         _lib.iteration_capture(self.handle, poses, m, v, step, loss, grad, fixed_mask, lambda0,
                                lambda1, anneal_steps, peak_lr, warmup, total, beta1, beta2, eps,
-                               convergence, _stream(self.device))
+                               mode, _stream(self.device))
 
     def convergence_reset(self, poses, w1=25, eps1=0.5, w2=50, eps2=0.1):
         _lib.convergence_reset(self.handle, poses, _lib.ConvergenceParams(w1, eps1, w2, eps2),
@@ -392,12 +398,13 @@ class PoseRefiner:
     def capture_iteration(self, step: torch.Tensor, loss: torch.Tensor, grad=None,
                           lambda0=10.0, lambda1=6.0, anneal_steps=1000, peak_lr=3e-3, warmup=25,
                           total=2000, beta1=0.9, beta2=0.999, eps=1e-8, wd_mlp=0.01,
-                          wd_delta=0.1, convergence=False):
+                          wd_delta=0.1, convergence=False, early_exit=False):
         """Capture one iteration of the loop with this parameterization;
         replay it with plan.launch_iteration().  Runs the forward once so
         that `poses` and the stored activations belong to the current
         parameters (and, with the convergence test, resets it there;
-        `convergence` is True or (w1, eps1, w2, eps2))."""
+        `convergence` is True or (w1, eps1, w2, eps2); early_exit=True
+        leaves a stopped scene's tiles out of the following replays)."""
         self.forward()
         if convergence:
             cp = tuple(convergence) if isinstance(convergence, (tuple, list)) else ()
@@ -407,7 +414,8 @@ class PoseRefiner:
                                    self.delta, self.dm, self.dv, self.delta_grad, self.poses0,
                                    self.poses, step, loss, grad, lambda0, lambda1, anneal_steps,
                                    peak_lr, warmup, total, beta1, beta2, eps, wd_mlp, wd_delta,
-                                   bool(convergence), _stream(self.plan.device))
+                                   (2 if early_exit else 1) if convergence else 0,
+                                   _stream(self.plan.device))
 
     def step(self, lr, step: torch.Tensor, beta1=0.9, beta2=0.999, eps=1e-8, wd_mlp=0.01,
              wd_delta=0.1):

@@ -180,8 +180,8 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
                                         double (*red)[10], float delta, double zmin) {
     const int tid = threadIdx.x;
     const Tile tl = tiles[t];
-    // a pair skipped by this step's sub-sampling: no work, no partials (the
-    // pair reduction reads none for it)
+    // a pair skipped by this step's sub-sampling (or of a stopped scene): no
+    // work, no partials (the pair reduction reads none for it)
     if (pair_scale[tl.pair] == 0.0) return;
     const PairDesc pd = desc[tl.pair];
     const uint32_t* texj = view_texture<FMT>(tex, pd.tex_off);
@@ -365,10 +365,11 @@ void launch_cost_kernel(Plan& p, float* dz, hipStream_t s) {
         int64_t want = (int64_t)p.n_cu * 8;
         want = std::min<int64_t>(want, ceil_div(p.n_tiles, 1) + nq);
         grid = (unsigned)(ceil_div(want, nq) * nq);
-    } else if (p.sample_budget > 0) {
-        // with pair sub-sampling the step's tile count is known only on the
-        // device: enough workgroups for every tile, split as the compacted
-        // list is (nq equal queues); those past a queue's end exit at once
+    } else if (compacted_launch(p)) {
+        // with pair sub-sampling (or stopped scenes skipped) the step's tile
+        // count is known only on the device: enough workgroups for every
+        // tile, split as the compacted list is (nq equal queues); those past
+        // a queue's end exit at once
         grid = (unsigned)(ceil_div(p.n_tiles, nq) * nq);
     } else {
         int64_t per_q = 0;
@@ -382,8 +383,8 @@ void launch_cost_kernel(Plan& p, float* dz, hipStream_t s) {
     kernel<<<grid, kBlock, 0, s>>>(
         reinterpret_cast<const uint2*>(p.records.p), tex, p.tiles.p, p.pair_desc.p, p.pair_rel.p,
         p.partials.p, EXT ? p.ext_partials.p : nullptr, p.dz_index.p, dz, p.pair_scale.p,
-        p.sample_budget > 0 ? p.qbegin_d.p : p.xcd_begin_d.p,
-        p.sample_budget > 0 ? p.tile_list.p : nullptr, nq, p.counters.p,
+        compacted_launch(p) ? p.qbegin_d.p : p.xcd_begin_d.p,
+        compacted_launch(p) ? p.tile_list.p : nullptr, nq, p.counters.p,
         std::max(1, 16384 / p.tile_size), p.params.huber_delta, p.params.z_min);
     EPO_CHECK_LAUNCH();
 }
@@ -416,8 +417,8 @@ void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss
                  double* pair_cost, int32_t* pair_valid, double* pair_grad, double* grad,
                  const double* upstream, hipStream_t s, const RefineOut* ext) {
     if (p.D > 0) {
-        // this step's pair subset (stochastic sub-sampling), if enabled, and
-        // the compacted list of its tiles
+        // this step's pair subset (stochastic sub-sampling, stopped scenes
+        // skipped), if enabled, and the compacted list of its tiles
         launch_pair_selection(p, p.capture_step ? p.capture_step : p.sample_step, s);
         pair_setup_kernel<<<(unsigned)ceil_div(std::max(p.D, 16), 256), 256, 0, s>>>(
             poses, p.K_d.p, p.wh_d.p, p.view_offset_d.p,

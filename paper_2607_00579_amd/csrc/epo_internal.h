@@ -218,6 +218,12 @@ struct Plan {
     uint64_t sample_seed = 0;
     const int32_t* sample_step = nullptr;   // device step counter read by the selection
     const int32_t* capture_step = nullptr;  // the captured iteration's counter (during capture)
+    // early exit of stopped scenes (during the capture of an iteration that
+    // skips them): the convergence phases the launches read; pair_scale then
+    // holds 0 for every pair of a stopped scene, so an eager call without
+    // sub-sampling first restores it from pair_scale_all
+    const int32_t* gate_phase = nullptr;
+    bool scale_gated = false;
     int32_t max_views_per_scene = 0;
     DevBuf<double> conv_prev;             // V x 12 poses of the previous step
     DevBuf<ConvState> conv_state;         // S
@@ -278,6 +284,10 @@ struct RefineOut {
     double* grad_alpha;     // n_records: dL/dalpha = Z0 dL/dZ
     double* grad_beta;      // n_records: dL/dbeta = dL/dZ
 };
+
+// the fused kernel runs over a compacted list of this step's tiles (pair
+// sub-sampling, or stopped scenes skipped) instead of every tile
+inline bool compacted_launch(const Plan& p) { return p.sample_budget > 0 || p.gate_phase; }
 
 // launches of the per-iteration pipeline (no allocation, no sync)
 void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss,

@@ -686,6 +686,8 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
         EPO_HIP(hipSetDevice(p.device));
         EPO_REQUIRE(lambda0 <= p.params.lambda_max && lambda1 <= p.params.lambda_max,
                     "schedule clamp above the plan's lambda_max");
+        EPO_REQUIRE(with_convergence >= 0 && with_convergence <= 2,
+                    "with_convergence must be 0, 1 or 2");
         EPO_REQUIRE(!with_convergence || p.max_views_per_scene <= kConvMaxViews,
                     "a scene has more views than the convergence kernel supports");
         hipStream_t user = as_stream(stream);
@@ -704,6 +706,8 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
                                            hipGetErrorString(cap)};
         }
         p.capture_step = step;               // the selection reads the iteration's counter
+        // with_convergence 2: stopped scenes' tiles are left out of the launch
+        p.gate_phase = with_convergence == 2 ? p.conv_phase.p : nullptr;
         try {
             launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
                             p.lambda_buf.p, p.lr_buf.p,
@@ -719,10 +723,13 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
             (void)hipStreamDestroy(cs);
             p.timing = timing;
             p.capture_step = nullptr;
+            p.gate_phase = nullptr;
             throw;
         }
         p.timing = timing;
         p.capture_step = nullptr;
+        if (p.gate_phase) p.scale_gated = true;
+        p.gate_phase = nullptr;
         hipError_t e = hipStreamEndCapture(cs, &p.graph);
         (void)hipStreamDestroy(cs);
         if (e != hipSuccess)
@@ -748,6 +755,8 @@ extern "C" epo_status epo_mlp_iteration_capture(
         EPO_REQUIRE(p.mlp_act.p, "call epo_mlp_setup first");
         EPO_REQUIRE(lambda0 <= p.params.lambda_max && lambda1 <= p.params.lambda_max,
                     "schedule clamp above the plan's lambda_max");
+        EPO_REQUIRE(with_convergence >= 0 && with_convergence <= 2,
+                    "with_convergence must be 0, 1 or 2");
         EPO_REQUIRE(!with_convergence || p.max_views_per_scene <= kConvMaxViews,
                     "a scene has more views than the convergence kernel supports");
         hipStream_t user = as_stream(stream);
@@ -766,6 +775,8 @@ extern "C" epo_status epo_mlp_iteration_capture(
                                            hipGetErrorString(cap)};
         }
         p.capture_step = step;
+        // with_convergence 2: stopped scenes' tiles are left out of the launch
+        p.gate_phase = with_convergence == 2 ? p.conv_phase.p : nullptr;
         try {
             // schedule -> cost and adjoint at the current poses -> refiner
             // backward (activations of the forward that made them) -> AdamW
@@ -787,10 +798,13 @@ extern "C" epo_status epo_mlp_iteration_capture(
             (void)hipStreamDestroy(cs);
             p.timing = timing;
             p.capture_step = nullptr;
+            p.gate_phase = nullptr;
             throw;
         }
         p.timing = timing;
         p.capture_step = nullptr;
+        if (p.gate_phase) p.scale_gated = true;
+        p.gate_phase = nullptr;
         hipError_t e = hipStreamEndCapture(cs, &p.graph);
         (void)hipStreamDestroy(cs);
         if (e != hipSuccess)

@@ -9,7 +9,8 @@
 //                  - sum over pairs out of v of w_d Ad(T_ji)^T G_d
 //              (the source pose sees the target's left perturbation moved
 //              through the relative pose: T_ji Exp(-xi_i) = Exp(-Ad(T_ji) xi_i) T_ji)
-//   per scene  loss = sum over its pairs of (2 / |D_scene|) L_d (Eqs. L, L_ij)
+//   per scene  loss = sum over its pairs of (2 / |D_scene|) L_d (Eqs. L, L_ij);
+//              in an iteration that skips stopped scenes, theirs is kept
 //   refinement (Sec. 3 Camera Refinement): with the per-pair focal sums F_t
 //              (target) and F_s (source), each f dH/df,
 //              dL/dgamma_v = (sum over pairs into v of w_d F_t
@@ -128,13 +129,16 @@ __global__ __launch_bounds__(256) void reduce_views_kernel(
     }
 }
 
-// one workgroup per scene
+// one workgroup per scene; a scene the convergence test has stopped (phase
+// 2, when phases are given) evaluated nothing and keeps its last loss
 __global__ __launch_bounds__(256) void reduce_scenes_kernel(
     const double* __restrict__ pair_sum, const PairStatic* __restrict__ ps,
     const double* __restrict__ pair_scale, const int32_t* __restrict__ scene_ptr,
-    const int32_t* __restrict__ scene_pairs, int32_t norm_mode, double* __restrict__ loss) {
+    const int32_t* __restrict__ scene_pairs, int32_t norm_mode, const int32_t* __restrict__ phase,
+    double* __restrict__ loss) {
     __shared__ double part[4];
     const int s = blockIdx.x;
+    if (phase && phase[s] == 2) return;
     double L = 0.0;
     for (int k = scene_ptr[s] + threadIdx.x; k < scene_ptr[s + 1]; k += blockDim.x) {
         const int d = scene_pairs[k];
@@ -171,7 +175,7 @@ void launch_reductions(Plan& p, double* loss, double* pair_cost, int32_t* pair_v
         reduce_scenes_kernel<<<(unsigned)p.S, 256, 0, s>>>(p.pair_sum.p, p.pair_static.p,
                                                             p.pair_scale.p, p.scene_ptr.p,
                                                             p.scene_pairs.p, p.params.norm_mode,
-                                                            loss);
+                                                            p.gate_phase, loss);
         EPO_CHECK_LAUNCH();
     }
 }

@@ -32,7 +32,8 @@ __global__ __launch_bounds__(256) void select_pairs_kernel(
     const int32_t* __restrict__ group_npairs, const int32_t* __restrict__ scene_ptr,
     const int32_t* __restrict__ scene_pairs, const int32_t* __restrict__ group_of_pair,
     const int32_t* __restrict__ step, uint64_t seed, int32_t budget,
-    uint8_t* __restrict__ group_sel, double* __restrict__ pair_scale) {
+    const int32_t* __restrict__ phase, uint8_t* __restrict__ group_sel,
+    double* __restrict__ pair_scale) {
     __shared__ uint32_t hist[256];
     __shared__ uint64_t prefix_s;
     __shared__ int rank_s, equal_s;
@@ -40,6 +41,12 @@ __global__ __launch_bounds__(256) void select_pairs_kernel(
     __shared__ int wave_tot[4];
     const int s = blockIdx.x;
     const int tid = threadIdx.x;
+    if (phase && phase[s] == 2) {
+        // a stopped scene evaluates nothing (the whole workgroup leaves here)
+        for (int k = scene_ptr[s] + tid; k < scene_ptr[s + 1]; k += 256)
+            pair_scale[scene_pairs[k]] = 0.0;
+        return;
+    }
     const int a = scene_group_ptr[s], n = scene_group_ptr[s + 1] - a;
     const uint64_t base = splitmix64(seed + (uint64_t)(uint32_t)step[0]);
     uint64_t T = ~0ull;             // key of rank budget - 1 (all selected if n <= budget)
@@ -113,6 +120,21 @@ __global__ __launch_bounds__(256) void select_pairs_kernel(
     for (int k = scene_ptr[s] + tid; k < scene_ptr[s + 1]; k += 256) {
         const int d = scene_pairs[k];
         pair_scale[d] = group_sel[group_of_pair[d]] ? scale : 0.0;
+    }
+}
+
+// Without sub-sampling: every pair at its full scale, or 0 for the pairs of
+// a scene the convergence test has stopped (phase 2), when phase is given.
+__global__ __launch_bounds__(256) void gate_pairs_kernel(const int32_t* __restrict__ scene_ptr,
+                                                         const int32_t* __restrict__ scene_pairs,
+                                                         const int32_t* __restrict__ phase,
+                                                         const double* __restrict__ scale_all,
+                                                         double* __restrict__ pair_scale) {
+    const int s = blockIdx.x;
+    const bool stopped = phase && phase[s] == 2;
+    for (int k = scene_ptr[s] + threadIdx.x; k < scene_ptr[s + 1]; k += 256) {
+        const int d = scene_pairs[k];
+        pair_scale[d] = stopped ? 0.0 : scale_all[d];
     }
 }
 
@@ -210,12 +232,22 @@ __global__ __launch_bounds__(256) void sampled_pairs_kernel(const double* __rest
 }  // namespace
 
 void launch_pair_selection(Plan& p, const int32_t* step, hipStream_t s) {
-    if (p.sample_budget <= 0 || p.D == 0) return;
-    select_pairs_kernel<<<(unsigned)p.S, 256, 0, s>>>(
-        p.scene_group_ptr.p, p.group_id_sorted.p, p.group_npairs.p, p.scene_ptr.p,
-        p.scene_pairs.p, p.group_of_pair.p, step, p.sample_seed, p.sample_budget, p.group_sel.p,
-        p.pair_scale.p);
-    EPO_CHECK_LAUNCH();
+    if (p.D == 0) return;
+    if (p.sample_budget > 0) {
+        select_pairs_kernel<<<(unsigned)p.S, 256, 0, s>>>(
+            p.scene_group_ptr.p, p.group_id_sorted.p, p.group_npairs.p, p.scene_ptr.p,
+            p.scene_pairs.p, p.group_of_pair.p, step, p.sample_seed, p.sample_budget,
+            p.gate_phase, p.group_sel.p, p.pair_scale.p);
+        EPO_CHECK_LAUNCH();
+    } else if (p.gate_phase || p.scale_gated) {
+        // stopped scenes skipped (captured iteration), or the full scales
+        // restored after such an iteration ran
+        gate_pairs_kernel<<<(unsigned)p.S, 256, 0, s>>>(p.scene_ptr.p, p.scene_pairs.p,
+                                                         p.gate_phase, p.pair_scale_all.p,
+                                                         p.pair_scale.p);
+        EPO_CHECK_LAUNCH();
+    }
+    if (!compacted_launch(p)) return;
     const int64_t T = p.n_tiles;
     const int32_t B = (int32_t)std::max<int64_t>(ceil_div(T, kCompact), 1);
     tile_count_kernel<<<(unsigned)B, 256, 0, s>>>(p.tiles.p, p.pair_scale.p, T, p.tile_blk.p);
