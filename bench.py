@@ -242,6 +242,36 @@ def sampled_timing(plan, prob, steps, warmup, budgets=(1024, 256, 64)):
     return res
 
 
+def edt_timing(prob, steps=3):
+    """Exact distance transform of every view of the workload (setup work,
+    run once per problem): HIP-event mean over `steps` calls after one
+    warm-up.  Algorithmic bytes per pixel: the edge byte read, d2 (int32) and
+    the DTF (float32) written, 9 B."""
+    import numpy as np
+    import torch
+    from paper_2607_00579_amd.api import build_distance_fields
+    dev = torch.device("cuda:0")
+    e = torch.from_numpy(np.asarray(prob.edge_flat)).to(dev, torch.uint8)
+    px = int((prob.width.astype(np.int64) * prob.height).sum())
+    build_distance_fields(e, prob.view_offset, prob.width, prob.height)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        d2, dtf = build_distance_fields(e, prob.view_offset, prob.width, prob.height)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    gbs = 9.0 * px / (ms * 1e-3) / 1e9
+    log(f"EDT: {ms:.2f} ms for {px} pixels of {prob.n_views} views "
+        f"({px / (ms * 1e-3) / 1e9:.1f} Gpx/s, {gbs:.0f} GB/s algorithmic)")
+    del e, d2, dtf
+    return {"ms": round(ms, 3), "pixels": px, "views": int(prob.n_views),
+            "algorithmic_bytes_per_pixel": 9,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}}
+
+
 def early_exit_timing(plan, prob, steps, warmup):
     """Captured iteration with the convergence test, once with stopped
     scenes still evaluated (learning rate 0) and once with their tiles left
@@ -564,6 +594,7 @@ def main():
                       "residuals_per_step": R_expected, "plan_options": options},
            "roofline": roofline}
 
+    out["edt"] = edt_timing(prob)
     if not args.no_refine:
         out["refine"] = refine_timing(plan, poses, lam, args.steps, args.warmup, R_expected)
     if not args.no_extras:
