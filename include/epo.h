@@ -118,6 +118,8 @@ typedef struct epo_plan_s* epo_plan;
  *   view_offset  (host) int64 [n_views] element offsets (views must not overlap)
  *   width/height (host) int32 [n_views], each in [1, EPO_MAX_SIDE]
  *   d2_out       int32, same packing as edge_maps: exact squared distances
+ *                (it holds the column pass's per-segment edge rows during
+ *                the call)
  *   dtf_out      float32, same packing: sqrt(d2).  Required: it also serves as
  *                the scratch of the column pass during the call.
  * Errors: EPO_ERR_INVALID_ARG for null pointers, n_views < 0, sides out of

@@ -5,20 +5,23 @@
 //
 //   column pass  f(x, y) = squared distance to the nearest edge pixel of
 //                column x (EPO_D2_EMPTY if the column has none).  One thread
-//                per (column, 64-row segment): it looks up and down from its
-//                segment for the nearest edge outside it, then sweeps the
+//                per (column, 64-row segment), in two kernels: the first
+//                records each segment's first and last edge row (in d2, not
+//                yet written); the second takes the nearest edge above and
+//                below its segment from those records, then sweeps the
 //                segment down and up.  The 64 threads of a wave take 64
 //                adjacent columns, so every step is one coalesced access, and
 //                the segments give every view H/64 times the waves of a
 //                thread-per-column pass.
 //   row pass     d2(x, y) = min over q of f(q, y) + (x - q)^2.  One workgroup
-//                per row stages f of the row in LDS; for each x the search
-//                widens r = 1, 2, ... on both sides while r^2 is below the
-//                best value found so far (every q at distance r adds at
-//                least r^2), so a pixel costs about twice its distance to
-//                the nearest edge instead of a sequential envelope per row.
-//                Integer arithmetic throughout: the exact minimum.  The same
-//                kernel writes DTF = sqrt(d2) in float32.
+//                per row stages f of the row and its minimum per 8-pixel
+//                block in LDS; each x searches outward block by block,
+//                scanning only blocks whose minimum plus the squared
+//                distance could beat its best value, and stops when the
+//                distance alone cannot (a parallel bounded search instead of
+//                a sequential envelope per row).  Integer arithmetic
+//                throughout: the exact minimum.  The same kernel writes
+//                DTF = sqrt(d2) in float32.
 //
 // Views are processed in batches whose descriptors travel as a kernel
 // argument, so the call needs no device allocation.
@@ -41,8 +44,11 @@ struct EdtBatch {
 };
 static_assert(sizeof(EdtBatch) <= 4000, "EDT batch descriptors exceed the kernel-argument space");
 
-__global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ edge,
-                                                  int32_t* __restrict__ colsq, EdtBatch b) {
+// First pass over each (column, segment): the rows of its first and last
+// edge pixel (-1 if none), packed as (first + 1) | (last + 1) << 16 into the
+// segment's first row of d2, which is free until the row pass.
+__global__ __launch_bounds__(64) void edt_segments(const uint8_t* __restrict__ edge,
+                                                   int32_t* __restrict__ seg, EdtBatch b) {
     const int k = blockIdx.z;
     const int W = b.w[k], H = b.h[k];
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -50,11 +56,38 @@ __global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ ed
     if (x >= W || y0 >= H) return;
     const int y1 = min(y0 + kSeg, H);
     const uint8_t* e = edge + b.off[k] + x;
+    int first = -1, last = -1;
+#pragma unroll 8
+    for (int y = y0; y < y1; ++y) {
+        if (e[(int64_t)y * W]) {
+            if (first < 0) first = y;
+            last = y;
+        }
+    }
+    seg[b.off[k] + (int64_t)y0 * W + x] = (first + 1) | ((last + 1) << 16);
+}
+
+// The nearest edge above and below a segment comes from the other segments'
+// summaries (at most H/64 coalesced reads, however far the edge is), then
+// the segment is swept down and up.
+__global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ edge,
+                                                  const int32_t* __restrict__ seg,
+                                                  int32_t* __restrict__ colsq, EdtBatch b) {
+    const int k = blockIdx.z;
+    const int W = b.w[k], H = b.h[k];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s0 = blockIdx.y, y0 = s0 * kSeg;
+    if (x >= W || y0 >= H) return;
+    const int y1 = min(y0 + kSeg, H);
+    const int n_seg = (H + kSeg - 1) / kSeg;
+    const uint8_t* e = edge + b.off[k] + x;
+    const int32_t* sm = seg + b.off[k] + x;
     int32_t* out = colsq + b.off[k] + x;
     int last = -1;                       // row of the nearest edge at or above
-    for (int y = y0 - 1; y >= 0; --y) {
-        if (e[(int64_t)y * W]) {
-            last = y;
+    for (int q = s0 - 1; q >= 0; --q) {
+        const int32_t v = sm[(int64_t)q * kSeg * W];
+        if (v >> 16) {
+            last = (v >> 16) - 1;
             break;
         }
     }
@@ -65,9 +98,10 @@ __global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ ed
         out[o] = last >= 0 ? (y - last) : -1;
     }
     int next = -1;                       // row of the nearest edge at or below
-    for (int y = y1; y < H; ++y) {
-        if (e[(int64_t)y * W]) {
-            next = y;
+    for (int q = s0 + 1; q < n_seg; ++q) {
+        const int32_t v = sm[(int64_t)q * kSeg * W];
+        if (v & 0xFFFF) {
+            next = (v & 0xFFFF) - 1;
             break;
         }
     }
@@ -84,23 +118,64 @@ __global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ ed
 // One workgroup per row.  The row's column-pass values live in dtf (the
 // call's scratch); the workgroup reads all of them into LDS before any of its
 // threads writes the row's DTF, and no other workgroup touches the row.
+// The row is split into blocks of 8 pixels with their minimum f in LDS; a
+// pixel scans its own block, then the blocks at block distance R = 1, 2, ...
+// on both sides: a block is scanned only if its minimum plus the squared
+// distance to its nearest pixel is below the best value so far, and the
+// search ends once the nearer of the two blocks is at least sqrt(best) away
+// (every farther pixel adds more).  Every pixel that can attain the minimum
+// is scanned, so the result is the exact minimum, at about D/8 block tests
+// per pixel (D its distance to the nearest edge).
+constexpr int kRowBlk = 8;
+
 __global__ __launch_bounds__(256) void edt_rows(const int32_t* __restrict__ colsq,
                                                int32_t* __restrict__ d2, float* __restrict__ dtf,
                                                EdtBatch b) {
-    extern __shared__ int32_t row[];
+    extern __shared__ int32_t lds[];
     const int k = blockIdx.y;
     const int W = b.w[k], H = b.h[k];
     const int y = blockIdx.x;
     if (y >= H) return;                  // whole workgroup
+    const int nb = (W + kRowBlk - 1) / kRowBlk;
+    int32_t* row = lds;
+    int32_t* bmin = lds + W;
     const int64_t base = b.off[k] + (int64_t)y * W;
     for (int x = threadIdx.x; x < W; x += blockDim.x) row[x] = colsq[base + x];
     __syncthreads();
+    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+        int32_t m = row[kRowBlk * j];
+        for (int q = kRowBlk * j + 1; q < min(kRowBlk * j + kRowBlk, W); ++q) m = min(m, row[q]);
+        bmin[j] = m;
+    }
+    __syncthreads();
+    // f <= (H - 1)^2 < 2^28 or kInf = 2^30, distances < 2^14: no int32 overflow
     for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        // f <= (H - 1)^2 < 2^28 or kInf = 2^30, r^2 < 2^28: no int32 overflow
+        const int bx = x / kRowBlk;
         int32_t best = row[x];
-        for (int r = 1; r * r < best && (x - r >= 0 || x + r < W); ++r) {
-            if (x - r >= 0) best = min(best, row[x - r] + r * r);
-            if (x + r < W) best = min(best, row[x + r] + r * r);
+        for (int q = kRowBlk * bx; q < min(kRowBlk * bx + kRowBlk, W); ++q)
+            best = min(best, row[q] + (x - q) * (x - q));
+        for (int R = 1;; ++R) {
+            const int bl = bx - R, br = bx + R;
+            const bool lin = bl >= 0, rin = kRowBlk * br < W;
+            if (!lin && !rin) break;
+            const int dl = x - (kRowBlk * bl + kRowBlk - 1);     // >= 1 when lin
+            const int dr = kRowBlk * br - x;                    // >= 1 when rin
+            const int dn = min(lin ? dl : 0x7fff, rin ? dr : 0x7fff);
+            if (dn * dn >= best) break;
+            if (lin && bmin[bl] + dl * dl < best) {
+#pragma unroll
+                for (int u = 0; u < kRowBlk; ++u) {
+                    const int q = kRowBlk * bl + u;
+                    best = min(best, row[q] + (x - q) * (x - q));
+                }
+            }
+            if (rin && bmin[br] + dr * dr < best) {
+#pragma unroll
+                for (int u = 0; u < kRowBlk; ++u) {
+                    const int q = kRowBlk * br + u;
+                    if (q < W) best = min(best, row[q] + (x - q) * (x - q));
+                }
+            }
         }
         d2[base + x] = best;
         dtf[base + x] = sqrtf((float)best);
@@ -139,11 +214,27 @@ extern "C" epo_status epo_build_distance_fields(const uint8_t* edge_maps, const 
                 maxW = std::max(maxW, b.w[k]);
                 maxH = std::max(maxH, b.h[k]);
             }
-            edt_columns<<<dim3((unsigned)ceil_div(maxW, 64), (unsigned)ceil_div(maxH, kSeg), b.n),
-                          64, 0, s>>>(edge_maps, colsq, b);
+            const dim3 cgrid((unsigned)ceil_div(maxW, 64), (unsigned)ceil_div(maxH, kSeg), b.n);
+            edt_segments<<<cgrid, 64, 0, s>>>(edge_maps, d2_out, b);
             EPO_CHECK_LAUNCH();
-            edt_rows<<<dim3((unsigned)maxH, b.n), 256, (size_t)maxW * sizeof(int32_t), s>>>(
-                colsq, d2_out, dtf_out, b);
+            edt_columns<<<cgrid, 64, 0, s>>>(edge_maps, d2_out, colsq, b);
+            EPO_CHECK_LAUNCH();
+            const size_t lds = (size_t)(maxW + ceil_div(maxW, kRowBlk)) * sizeof(int32_t);
+            if (lds > 65536) {
+                // rows wider than 14563 pixels: more than the default 64 KB of
+                // dynamic LDS (gfx950 has 160 KB per workgroup); an error, never
+                // a short allocation, if the device cannot give it
+                int dev = 0, max_lds = 0;
+                EPO_HIP(hipGetDevice(&dev));
+                EPO_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                              dev));
+                EPO_REQUIRE(lds <= (size_t)max_lds,
+                            "rows too wide for the device's LDS per workgroup");
+                EPO_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(edt_rows),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            (int)lds));
+            }
+            edt_rows<<<dim3((unsigned)maxH, b.n), 256, lds, s>>>(colsq, d2_out, dtf_out, b);
             EPO_CHECK_LAUNCH();
         }
     });

@@ -52,16 +52,23 @@ def test_random_maps_bit_exact(gpu, shape, density):
 
 
 def test_wide_and_single_pixel(gpu):
+    """Maps with one or two edge pixels: d2 is the closed-form minimum over
+    them.  Rows of 14600 and 16384 pixels need more than 64 KB of LDS in the
+    row pass."""
+    cases = [(3, 4000, [(1, 3999)]), (2000, 2, [(0, 0)]), (64, 2048, [(63, 1000)]),
+             (2, 16384, [(1, 5)]), (3, 14600, [(0, 14599)]),
+             (4, 16384, [(0, 9000), (3, 9100)])]
     maps = []
-    for (H, W, y0, x0) in [(3, 4000, 1, 3999), (2000, 2, 0, 0), (64, 2048, 63, 1000)]:
+    for H, W, pts in cases:
         e = np.zeros((H, W), np.uint8)
-        e[y0, x0] = 1
+        for y0, x0 in pts:
+            e[y0, x0] = 1
         maps.append(e)
     got, _ = gpu_edt(maps)
-    for g, m in zip(got, maps):
-        (y0,), (x0,) = np.nonzero(m)
-        yy, xx = np.mgrid[0:m.shape[0], 0:m.shape[1]]
-        assert np.array_equal(g, (xx - x0) ** 2 + (yy - y0) ** 2)
+    for g, m, (H, W, pts) in zip(got, maps, cases):
+        yy, xx = np.mgrid[0:H, 0:W]
+        want = np.min([(xx - x0) ** 2 + (yy - y0) ** 2 for y0, x0 in pts], axis=0)
+        assert np.array_equal(g, want), (H, W)
 
 
 @pytest.mark.parametrize("name", ["c1", "c2"])
