@@ -462,6 +462,8 @@ def main():
                     help="only eager fused-kernel launches (for profilers)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the sub-sampled step and viewgraph timings")
+    ap.add_argument("--edt-only", action="store_true",
+                    help="only the exact distance transform of the workload's views (for profilers)")
     ap.add_argument("--refine-only", action="store_true",
                     help="only eager joint-phase calls with depth gradients (for profilers)")
     ap.add_argument("--ablation", action="store_true",
@@ -489,6 +491,10 @@ def main():
     R_expected = prob.residual_count()
     log(f"workload {args.workload}: {prob.n_views} views, {prob.n_pairs} pairs, "
         f"{R_expected} residuals/iter (generated in {time.time() - t0:.1f} s)")
+
+    if args.edt_only:
+        edt_timing(prob, steps=args.steps)
+        return
 
     t0 = time.time()
     plan = EdgePlan.from_problem(prob, device=dev, keep_fields=True)
