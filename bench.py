@@ -195,6 +195,34 @@ def refine_timing(plan, poses, lam, steps, warmup, R):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         res[key] = {"ms_per_call": round(ms, 4), "fused_kernel_ms": round(float(np.mean(ks)), 4)}
+    # joint-phase AdamW step of gamma, alpha, beta (then the refined focal
+    # lengths and depths are written into the plan): 96 B per record for the
+    # step (alpha, beta and four float64 moments read and written, two
+    # float64 gradients read), 28 B for the depth rewrite (Z0, alpha, beta,
+    # the 8-byte record read and written)
+    grads = plan.refine(poses, lam, loss=False, grad=False)
+    state = plan.joint_state()
+    state["gamma"].fill_(0.01)
+    state["alpha"].fill_(1.01)
+    state["beta"].fill_(0.01)
+    lr = torch.full((plan.n_scenes,), 3e-3, dtype=torch.float64, device=plan.device)
+    step = torch.zeros(1, dtype=torch.int32, device=plan.device)
+    for _ in range(max(warmup, 1)):
+        plan.joint_step(state, grads, lr, step)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        plan.joint_step(state, grads, lr, step)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    gbs = 124.0 * plan.n_records / (ms * 1e-3) / 1e9
+    res["joint_step"] = {"ms_per_call": round(ms, 4), "records": int(plan.n_records),
+                         "algorithmic_bytes_per_record": 124, "GBps": round(gbs, 1)}
+    log(f"joint step (AdamW on gamma, alpha, beta + refinement update): {ms:.3f} ms for "
+        f"{plan.n_records} records ({gbs:.0f} GB/s algorithmic)")
+    del grads, state
     assert plan.device_status() == 0
     plan.set_refinement()
     full = res["focal_and_depth"]["ms_per_call"]
@@ -465,7 +493,7 @@ def main():
     ap.add_argument("--edt-only", action="store_true",
                     help="only the exact distance transform of the workload's views (for profilers)")
     ap.add_argument("--refine-only", action="store_true",
-                    help="only eager joint-phase calls with depth gradients (for profilers)")
+                    help="only eager joint-phase calls with depth gradients, each followed by a joint step (for profilers)")
     ap.add_argument("--ablation", action="store_true",
                     help="also run both pose parameterizations for 1000 steps on c3 and "
                          "report their relative rotation errors")
@@ -521,8 +549,11 @@ def main():
         plan.set_refinement(torch.full((plan.n_views,), 0.01, dtype=torch.float64),
                             torch.full((plan.n_records,), 1.01),
                             torch.full((plan.n_records,), 0.01))
+        state = plan.joint_state()
+        lr = torch.full((plan.n_scenes,), 3e-3, dtype=torch.float64, device=dev)
+        jstep = torch.zeros(1, dtype=torch.int32, device=dev)
         for _ in range(args.warmup + args.steps):
-            plan.refine(poses, lam)
+            plan.joint_step(state, plan.refine(poses, lam), lr, jstep)
         torch.cuda.synchronize()
         log("refine-only run done")
         return

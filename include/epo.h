@@ -262,6 +262,52 @@ EPO_API epo_status epo_edge_cost_refine(epo_plan plan, const double* poses, cons
                                 void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Joint-phase optimizer step (paper Sec. 3 "Camera Refinement", "Depth
+ * Refinement"; Sec. 4 "Implementation Details": every parameter is trained
+ * with AdamW, beta = (0.9, 0.999), weight decay 0.01; Alg. EPO.Forward: the
+ * depth optimizer steps only once the pose-phase criterion holds).
+ *
+ * epo_joint_step applies one AdamW step to the focal scales gamma and the
+ * per-record depth scale alpha and shift beta, then makes the new values the
+ * plan's refinement exactly as epo_plan_set_refinement does.  For each
+ * parameter x with gradient g, learning rate a = lr[scene] and t = *step + 1:
+ *   x <- x (1 - a wd),  m <- b1 m + (1 - b1) g,  w <- b2 w + (1 - b2) g^2,
+ *   x <- x - a (m / (1 - b1^t)) / (sqrt(w / (1 - b2^t)) + eps)
+ * in float64 (alpha, beta are read as float32, rounded once when stored).
+ * The step counter is read, not advanced: call this before epo_pose_step of
+ * the same iteration, which advances it, so both use the same t.
+ *
+ *   gamma               float64 [V], updated in place
+ *   alpha, beta         float32 [n_records] (plan record order), in place
+ *   m_gamma, v_gamma    float64 [V] moments, in place (start at 0)
+ *   m_depth, v_depth    float64 [2][n_records] moments: alpha's, then beta's
+ *   grad_*              float64, as written by epo_edge_cost_refine
+ *   lr                  float64 [n_scenes]
+ *   phase               int32 [n_scenes] or NULL: with phases (as written by
+ *                       epo_convergence_update: 0 pose phase, 1 joint phase,
+ *                       2 stopped), gamma steps unless the scene has stopped
+ *                       and alpha, beta step only in phase 1; a parameter that
+ *                       does not step keeps its value and moments (no decay).
+ *                       NULL: every parameter steps.
+ *   wd_focal, wd_depth  weight decay of gamma and of alpha, beta (the paper:
+ *                       0.01 for both)
+ *   step                int32 [1] device step counter (read only)
+ * All arrays are device memory.  Errors: EPO_ERR_INVALID_ARG for a null
+ * pointer other than phase or betas outside [0, 1) or eps <= 0.  The first
+ * call allocates a copy of the plan's record offsets (8 bytes per view) and,
+ * through the refinement update, what epo_plan_set_refinement allocates on
+ * its first call with depths; later calls allocate nothing and do not
+ * synchronise.
+ * ------------------------------------------------------------------------- */
+EPO_API epo_status epo_joint_step(epo_plan plan, double* gamma, float* alpha, float* beta,
+                                  double* m_gamma, double* v_gamma, double* m_depth,
+                                  double* v_depth, const double* grad_gamma,
+                                  const double* grad_alpha, const double* grad_beta,
+                                  const double* lr, const int32_t* phase, double beta1,
+                                  double beta2, double eps, double wd_focal, double wd_depth,
+                                  const int32_t* step, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Viewgraph estimation (paper Sec. 3 "Viewgraph Estimation", Sec. 4
  * "Implementation Details"; construction kernels of the supplementary
  * material).  For every candidate pair (i, j), each pixel p = (a s, b s) of

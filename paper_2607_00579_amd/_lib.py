@@ -63,6 +63,7 @@ _SIGS = {
     "epo_plan_sampled_pairs": [P, P, P],
     "epo_edge_cost_refine": [P, P, P, P, P, P, P, P, P, P],
     "epo_pose_step": [P, P, P, P, I32, P, P, P, F64, F64, F64, P, P],
+    "epo_joint_step": [P, P, P, P, P, P, P, P, P, P, P, P, P, F64, F64, F64, F64, F64, P, P],
     "epo_schedule": [P, I32, F32, F32, I32, F64, I32, I32, P, P, P],
     "epo_iteration_capture": [P, P, P, P, P, P, P, P, F32, F32, I32, F64, I32, I32, F64, F64,
                               F64, I32, P],
@@ -233,6 +234,15 @@ def edge_cost_refine(plan, poses, lam, upstream, loss, grad, grad_gamma, grad_al
     _check(load().epo_edge_cost_refine(plan, _ptr(poses), _ptr(lam), _ptr(upstream), _ptr(loss),
                                        _ptr(grad), _ptr(grad_gamma), _ptr(grad_alpha),
                                        _ptr(grad_beta), stream))
+
+
+def joint_step(plan, gamma, alpha, beta, m_gamma, v_gamma, m_depth, v_depth, grad_gamma,
+               grad_alpha, grad_beta, lr, phase, beta1, beta2, eps, wd_focal, wd_depth, step,
+               stream):
+    _check(load().epo_joint_step(plan, _ptr(gamma), _ptr(alpha), _ptr(beta), _ptr(m_gamma),
+                                 _ptr(v_gamma), _ptr(m_depth), _ptr(v_depth), _ptr(grad_gamma),
+                                 _ptr(grad_alpha), _ptr(grad_beta), _ptr(lr), _ptr(phase), beta1,
+                                 beta2, eps, wd_focal, wd_depth, _ptr(step), stream))
 
 
 def pose_step(poses, m, v, grad, n_views, scene_of_view, fixed_mask, lr, beta1, beta2, eps, step,

@@ -240,6 +240,55 @@ class EdgePlan:
         _lib.plan_sampled_pairs(self.handle, out, _stream(self.device))
         return out[: self.n_pairs].bool()
 
+    def joint_state(self):
+        """Parameters of the joint phase at their identity values (gamma 0,
+        alpha 1, beta 0) and zero AdamW moments, on the plan's device."""
+        d, n, V = self.device, self.n_records, self.n_views
+        return {"gamma": torch.zeros(V, dtype=torch.float64, device=d),
+                "alpha": torch.ones(max(n, 1), dtype=torch.float32, device=d)[:n],
+                "beta": torch.zeros(max(n, 1), dtype=torch.float32, device=d)[:n],
+                "m_gamma": torch.zeros(V, dtype=torch.float64, device=d),
+                "v_gamma": torch.zeros(V, dtype=torch.float64, device=d),
+                "m_depth": torch.zeros(max(2 * n, 1), dtype=torch.float64, device=d),
+                "v_depth": torch.zeros(max(2 * n, 1), dtype=torch.float64, device=d)}
+
+    def joint_step(self, state, grads, lr, step, phase=None, beta1=0.9, beta2=0.999, eps=1e-8,
+                   wd_focal=0.01, wd_depth=0.01):
+        """One AdamW step of gamma, alpha, beta (state from joint_state,
+        updated in place; grads from refine()), then the plan's refinement is
+        set to the new values.  phase: int32 [n_scenes] device tensor of
+        convergence phases (depth steps only in phase 1, nothing in phase 2)
+        or None (every parameter steps).  `step` is read, not advanced."""
+        if not torch.is_tensor(lr):
+            lr = torch.full((self.n_scenes,), float(lr), dtype=torch.float64, device=self.device)
+        for k in ("grad_gamma", "grad_alpha", "grad_beta"):
+            if k not in grads:
+                raise ValueError(f"joint_step needs {k} (refine(..., focal=True, depth=True))")
+        V, n = self.n_views, self.n_records
+        want = {"gamma": (torch.float64, V), "alpha": (torch.float32, n),
+                "beta": (torch.float32, n), "m_gamma": (torch.float64, V),
+                "v_gamma": (torch.float64, V), "m_depth": (torch.float64, 2 * n),
+                "v_depth": (torch.float64, 2 * n)}
+        checks = [(f"state[{k!r}]", state.get(k), dt, size) for k, (dt, size) in want.items()]
+        checks += [("grad_gamma", grads["grad_gamma"], torch.float64, V),
+                   ("grad_alpha", grads["grad_alpha"], torch.float64, n),
+                   ("grad_beta", grads["grad_beta"], torch.float64, n),
+                   ("lr", lr, torch.float64, self.n_scenes),
+                   ("step", step, torch.int32, 1)]
+        if phase is not None:
+            checks.append(("phase", phase, torch.int32, self.n_scenes))
+        for name, t, dt, size in checks:
+            if (not torch.is_tensor(t) or not t.is_cuda
+                    or t.device.index != (self.device.index or 0) or t.dtype != dt
+                    or t.numel() < size or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous {dt} tensor of at least {size} "
+                                 f"values on {self.device}")
+        _lib.joint_step(self.handle, state["gamma"], state["alpha"], state["beta"],
+                        state["m_gamma"], state["v_gamma"], state["m_depth"], state["v_depth"],
+                        grads["grad_gamma"], grads["grad_alpha"], grads["grad_beta"],
+                        lr, phase, beta1, beta2,
+                        eps, wd_focal, wd_depth, step, _stream(self.device))
+
     def pose_step(self, poses, m, v, grad, lr, step, fixed_mask=None, beta1=0.9, beta2=0.999,
                   eps=1e-8):
         if not torch.is_tensor(lr):

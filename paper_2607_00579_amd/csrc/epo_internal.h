@@ -241,6 +241,7 @@ struct Plan {
     DevBuf<float> K0_d;                   // V x 4 intrinsics as given (K_d holds the refined ones)
     DevBuf<double> gamma_d;               // V: current focal scales gamma
     DevBuf<float> z0;                     // n_records depths as given (allocated on first update)
+    DevBuf<int64_t> rec_off_d;            // V + 1 record offsets (allocated by the first joint step)
     // per-residual depth derivatives, source-major: source view i's records
     // in blocks of 256 (counted from its first record), each block holding
     // one 256-entry chunk per pair out of i, in CSR order, so the depth pass

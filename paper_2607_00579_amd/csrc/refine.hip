@@ -154,6 +154,66 @@ void launch_depth_fmt(Plan& p, const uint32_t* tex, const double* upstream, doub
     EPO_CHECK_LAUNCH();
 }
 
+// AdamW step of the joint phase's parameters (decoupled weight decay, then
+// Adam with bias correction at t = step + 1), one thread per parameter:
+// [0, V) focal scales gamma (float64), then alpha, then beta of every record
+// (float32 parameters; the update is formed in float64 from the stored value
+// and rounded once).  Moments are float64: m_depth / v_depth hold alpha's at
+// [0, n) and beta's at [n, 2n).  With a phase array, the scene's phase gates
+// the step: gamma moves unless the scene has stopped (phase 2), alpha and
+// beta only in the joint phase (phase 1); a gated parameter and its moments
+// are left as they are.
+__global__ __launch_bounds__(256) void joint_step_kernel(
+    double* __restrict__ gamma, float* __restrict__ alpha, float* __restrict__ beta,
+    double* __restrict__ m_gamma, double* __restrict__ v_gamma, double* __restrict__ m_depth,
+    double* __restrict__ v_depth, const double* __restrict__ g_gamma,
+    const double* __restrict__ g_alpha, const double* __restrict__ g_beta,
+    const int64_t* __restrict__ rec_off, const int32_t* __restrict__ scene_of_view, int32_t V,
+    int64_t n, const double* __restrict__ lr, const int32_t* __restrict__ phase, double b1,
+    double b2, double eps, double wd_focal, double wd_depth, const int32_t* __restrict__ step) {
+    const double t = (double)(step[0] + 1);
+    const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+    const int64_t total = (int64_t)V + 2 * n;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int view;
+        int64_t q = 0;
+        if (k < V) {
+            view = (int)k;
+        } else {
+            q = k - V;
+            const int64_t r = q < n ? q : q - n;
+            int lo = 0, hi = V - 1;          // last view whose first record is <= r
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (rec_off[mid] <= r) lo = mid; else hi = mid - 1;
+            }
+            view = lo;
+        }
+        const int sc = scene_of_view[view];
+        const int ph = phase ? phase[sc] : 1;
+        const double a = lr[sc];
+        if (k < V) {
+            if (ph == 2) continue;
+            const double g = g_gamma[k];
+            const double mk = b1 * m_gamma[k] + (1.0 - b1) * g;
+            const double vk = b2 * v_gamma[k] + (1.0 - b2) * g * g;
+            m_gamma[k] = mk;
+            v_gamma[k] = vk;
+            gamma[k] = gamma[k] * (1.0 - a * wd_focal) - a * (mk / c1) / (sqrt(vk / c2) + eps);
+        } else {
+            if (ph != 1) continue;
+            float* x = q < n ? alpha + q : beta + (q - n);
+            const double g = q < n ? g_alpha[q] : g_beta[q - n];
+            const double mk = b1 * m_depth[q] + (1.0 - b1) * g;
+            const double vk = b2 * v_depth[q] + (1.0 - b2) * g * g;
+            m_depth[q] = mk;
+            v_depth[q] = vk;
+            *x = (float)((double)*x * (1.0 - a * wd_depth) - a * (mk / c1) / (sqrt(vk / c2) + eps));
+        }
+    }
+}
+
 }  // namespace
 
 void launch_depth_grad(Plan& p, const double* upstream, double* grad_alpha, double* grad_beta,
@@ -233,4 +293,41 @@ extern "C" epo_status epo_edge_cost_refine(epo_plan plan, const double* poses,
         launch_cost(p, poses, lambda, loss, nullptr, nullptr, nullptr, grad, upstream,
                     as_stream(stream), &out);
     });
+}
+
+extern "C" epo_status epo_joint_step(epo_plan plan, double* gamma, float* alpha, float* beta,
+                                     double* m_gamma, double* v_gamma, double* m_depth,
+                                     double* v_depth, const double* grad_gamma,
+                                     const double* grad_alpha, const double* grad_beta,
+                                     const double* lr, const int32_t* phase, double beta1,
+                                     double beta2, double eps, double wd_focal, double wd_depth,
+                                     const int32_t* step, void* stream) {
+    const epo_status st = guarded([&] {
+        EPO_REQUIRE(plan, "null plan");
+        EPO_REQUIRE(gamma && alpha && beta && m_gamma && v_gamma && m_depth && v_depth &&
+                        grad_gamma && grad_alpha && grad_beta && lr && step,
+                    "null pointer argument (only phase may be null)");
+        EPO_REQUIRE(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0,
+                    "beta1, beta2 must be in [0, 1) and eps > 0");
+        Plan& p = *reinterpret_cast<Plan*>(plan);
+        EPO_HIP(hipSetDevice(p.device));
+        hipStream_t s = as_stream(stream);
+        const int64_t n = p.rec_off.back();
+        if (!p.rec_off_d.p) {
+            p.rec_off_d.alloc(p.rec_off.size());
+            EPO_HIP(hipMemcpyAsync(p.rec_off_d.p, p.rec_off.data(),
+                                   p.rec_off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        }
+        const int64_t total = (int64_t)p.V + 2 * n;
+        const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
+        joint_step_kernel<<<grid, 256, 0, s>>>(gamma, alpha, beta, m_gamma, v_gamma, m_depth,
+                                               v_depth, grad_gamma, grad_alpha, grad_beta,
+                                               p.rec_off_d.p, p.scene_of_view_d.p, p.V, n, lr,
+                                               phase, beta1, beta2, eps, wd_focal, wd_depth,
+                                               step);
+        EPO_CHECK_LAUNCH();
+    });
+    if (st != EPO_OK) return st;
+    // the refined focal lengths and depths of the new parameters
+    return epo_plan_set_refinement(plan, gamma, alpha, beta, stream);
 }

@@ -1,0 +1,139 @@
+"""GPU: the joint-phase optimizer step (AdamW on focal scales gamma and the
+per-record depth scale alpha and shift beta, with the convergence-phase gate)
+through the C-ABI, against the FP64 oracle on the same seeded state and
+gradients, on a two-scene batch with one learning rate per scene; and the
+refinement it leaves in the plan against an explicit set_refinement."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import joint as oj
+from tests.gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+def two_scene_problem():
+    from synth.scenes import config_c1, config_c2, pack
+    return pack(list(config_c2().scenes) + list(config_c1().scenes), "c2+c1")
+
+
+def setup(seed=0):
+    from paper_2607_00579_amd.api import EdgePlan
+    prob = two_scene_problem()
+    plan = EdgePlan.from_problem(prob, device="cuda:0")
+    V, n = plan.n_views, plan.n_records
+    vor = plan.record_pixels()[:, 0]
+    sv = np.asarray(plan.scene_of_view, np.int64)
+    rng = np.random.default_rng(seed)
+    host = {"gamma": rng.normal(0, 0.02, V), "alpha": (1 + rng.normal(0, 0.05, n)).astype(np.float32),
+            "beta": rng.normal(0, 0.05, n).astype(np.float32),
+            "m_gamma": np.zeros(V), "v_gamma": np.zeros(V)}
+    for k in ("alpha", "beta"):
+        host["m_" + k] = np.zeros(n)
+        host["v_" + k] = np.zeros(n)
+    dev = plan.joint_state()
+    dev["gamma"].copy_(torch.from_numpy(host["gamma"]))
+    dev["alpha"].copy_(torch.from_numpy(host["alpha"]))
+    dev["beta"].copy_(torch.from_numpy(host["beta"]))
+    return prob, plan, sv, vor, rng, host, dev
+
+
+def grads_of(rng, V, n):
+    return {"grad_gamma": rng.normal(0, 1e-2, V), "grad_alpha": rng.normal(0, 1e-3, n),
+            "grad_beta": rng.normal(0, 1e-3, n)}
+
+
+def check_first_moment(got, want, prev_m, g, tag):
+    """m = b1 m_prev + (1 - b1) g can cancel; one side fusing the product
+    into the sum changes the result by about 2^-53 of the terms' size, not of
+    the result's, and later steps carry that difference on scaled by b1: the
+    bound is 1e-14 of the terms' size."""
+    scale = 0.9 * np.abs(prev_m) + 0.1 * np.abs(g)
+    err = np.abs(got - want)
+    assert np.all(err <= 1e-14 * scale + 1e-13 * np.abs(want)), \
+        f"{tag}: worst {np.max(err / (scale + 1e-300)):.2e} of the terms' size"
+
+
+def compare(dev, want, prev, g, n, tag):
+    got = {k: t.cpu().numpy() for k, t in dev.items()}
+    for k in ("gamma", "v_gamma"):
+        np.testing.assert_allclose(got[k], want[k], rtol=1e-13, atol=1e-300, err_msg=f"{tag} {k}")
+    check_first_moment(got["m_gamma"], want["m_gamma"], prev["m_gamma"], g["grad_gamma"],
+                       f"{tag} m_gamma")
+    for i, k in enumerate(("alpha", "beta")):
+        # float64 step rounded once to float32: at most one float32 ulp apart
+        # (the two sides may contract multiply-adds differently)
+        w = want[k].astype(np.float32)
+        ulp = np.spacing(np.abs(w)).astype(np.float64)
+        err = np.abs(got[k].astype(np.float64) - w.astype(np.float64))
+        assert np.all(err <= ulp), f"{tag} {k}: {int((err > ulp).sum())} beyond one ulp"
+        np.testing.assert_allclose(got["v_depth"][i * n:(i + 1) * n], want["v_" + k],
+                                   rtol=1e-13, atol=1e-300, err_msg=f"{tag} v_{k}")
+        check_first_moment(got["m_depth"][i * n:(i + 1) * n], want["m_" + k], prev["m_" + k],
+                           g["grad_" + k], f"{tag} m_{k}")
+
+
+def test_joint_step_matches_oracle(gpu):
+    """Four steps (two ungated, then phases (0, 1) and (1, 2)) with learning
+    rates 3e-3 and 1e-3 by scene and the paper's weight decay."""
+    prob, plan, sv, vor, rng, host, dev = setup()
+    V, n = plan.n_views, plan.n_records
+    say(f"joint step: {V} views, {n} records, {plan.n_scenes} scenes")
+    lr = np.array([3e-3, 1e-3])
+    lr_t = torch.from_numpy(lr).cuda()
+    phases = [None, None, [0, 1], [1, 2]]
+    want = host
+    for s, ph in enumerate(phases):
+        g = grads_of(rng, V, n)
+        gt = {k: torch.from_numpy(v).cuda() for k, v in g.items()}
+        step = torch.tensor([s], dtype=torch.int32, device="cuda")
+        ph_t = None if ph is None else torch.tensor(ph, dtype=torch.int32, device="cuda")
+        plan.joint_step(dev, gt, lr_t, step, phase=ph_t)
+        torch.cuda.synchronize()
+        prev, want = want, oj.joint_step(want, g, lr, sv, vor, s, phase=ph)
+        compare(dev, want, prev, g, n, f"step {s}")
+        assert int(step.item()) == s                 # read, not advanced
+
+
+def test_joint_step_sets_refinement(gpu):
+    """After a step the plan's refinement is that of the new parameters:
+    the loss and gradients equal those after an explicit set_refinement of
+    the same arrays (bitwise), and differ from the unrefined ones."""
+    prob, plan, sv, vor, rng, host, dev = setup(seed=1)
+    V, n = plan.n_views, plan.n_records
+    P = torch.from_numpy(prob.poses_init.copy()).cuda()
+    g = {k: torch.from_numpy(v).cuda() for k, v in grads_of(rng, V, n).items()}
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    plan.joint_step(dev, g, 1e-2, step)
+    after = {k: t.cpu().numpy() for k, t in plan.refine(P, 10.0).items()}
+    plan.set_refinement(dev["gamma"], dev["alpha"], dev["beta"])
+    explicit = {k: t.cpu().numpy() for k, t in plan.refine(P, 10.0).items()}
+    for k in after:
+        assert np.array_equal(after[k], explicit[k]), k
+    plan.set_refinement()
+    base = plan.refine(P, 10.0)["loss"].cpu().numpy()
+    assert not np.array_equal(base, after["loss"])
+
+
+def test_joint_step_rejects_bad_arguments(gpu):
+    from paper_2607_00579_amd import _lib
+    prob, plan, sv, vor, rng, host, dev = setup()
+    g = {k: torch.from_numpy(v).cuda() for k, v in grads_of(rng, plan.n_views, plan.n_records).items()}
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(RuntimeError):
+        plan.joint_step(dev, g, 1e-3, step, beta1=1.0)
+    with pytest.raises(ValueError):
+        plan.joint_step(dev, {"grad_gamma": g["grad_gamma"]}, 1e-3, step)
+    with pytest.raises(ValueError):             # fewer phases than scenes
+        plan.joint_step(dev, g, 1e-3, step, phase=torch.zeros(1, dtype=torch.int32, device="cuda"))
+    with pytest.raises(ValueError):             # host memory
+        plan.joint_step(dev, dict(g, grad_beta=g["grad_beta"].cpu()), 1e-3, step)
+    with pytest.raises(ValueError):             # wrong dtype
+        plan.joint_step(dev, dict(g, grad_alpha=g["grad_alpha"].float()), 1e-3, step)
+    with pytest.raises(_lib.EpoError):          # null step counter, seen by the C side
+        _lib.joint_step(plan.handle, dev["gamma"], dev["alpha"], dev["beta"], dev["m_gamma"],
+                        dev["v_gamma"], dev["m_depth"], dev["v_depth"], g["grad_gamma"],
+                        g["grad_alpha"], g["grad_beta"],
+                        torch.ones(plan.n_scenes, dtype=torch.float64, device="cuda"), None,
+                        0.9, 0.999, 1e-8, 0.01, 0.01, None, None)
