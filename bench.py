@@ -198,8 +198,8 @@ def refine_timing(plan, poses, lam, steps, warmup, R):
     # joint-phase AdamW step of gamma, alpha, beta (then the refined focal
     # lengths and depths are written into the plan): 96 B per record for the
     # step (alpha, beta and four float64 moments read and written, two
-    # float64 gradients read), 28 B for the depth rewrite (Z0, alpha, beta,
-    # the 8-byte record read and written)
+    # float64 gradients read), 8 B for the depth rewrite (Z0 read, the
+    # record's depth written)
     grads = plan.refine(poses, lam, loss=False, grad=False)
     state = plan.joint_state()
     state["gamma"].fill_(0.01)
@@ -217,9 +217,9 @@ def refine_timing(plan, poses, lam, steps, warmup, R):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    gbs = 124.0 * plan.n_records / (ms * 1e-3) / 1e9
+    gbs = 104.0 * plan.n_records / (ms * 1e-3) / 1e9
     res["joint_step"] = {"ms_per_call": round(ms, 4), "records": int(plan.n_records),
-                         "algorithmic_bytes_per_record": 124, "GBps": round(gbs, 1)}
+                         "algorithmic_bytes_per_record": 104, "GBps": round(gbs, 1)}
     log(f"joint step (AdamW on gamma, alpha, beta + refinement update): {ms:.3f} ms for "
         f"{plan.n_records} records ({gbs:.0f} GB/s algorithmic)")
     del grads, state

@@ -53,6 +53,12 @@ __global__ __launch_bounds__(256) void snapshot_depth_kernel(const uint2* __rest
     if (k < n) z0[k] = __uint_as_float(records[k].y);
 }
 
+// Z0 alpha is exact in float64 (two float32 factors), so this is one
+// rounding to float64 followed by one to float32
+__device__ inline float refined_depth(float z0, float alpha, float beta) {
+    return (float)fma((double)z0, (double)alpha, (double)beta);
+}
+
 __global__ __launch_bounds__(256) void refine_depth_kernel(const float* __restrict__ z0,
                                                            const float* __restrict__ alpha,
                                                            const float* __restrict__ beta,
@@ -60,9 +66,7 @@ __global__ __launch_bounds__(256) void refine_depth_kernel(const float* __restri
                                                            int32_t* __restrict__ status) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    // Z0 alpha is exact in float64 (two float32 factors), so this is one
-    // rounding to float64 followed by one to float32
-    const float z = alpha ? (float)fma((double)z0[k], (double)alpha[k], (double)beta[k]) : z0[k];
+    const float z = alpha ? refined_depth(z0[k], alpha[k], beta[k]) : z0[k];
     if (!isfinite(z)) atomicOr(status, 4);
     records[k].y = __float_as_uint(z);
 }
@@ -155,14 +159,15 @@ void launch_depth_fmt(Plan& p, const uint32_t* tex, const double* upstream, doub
 }
 
 // AdamW step of the joint phase's parameters (decoupled weight decay, then
-// Adam with bias correction at t = step + 1), one thread per parameter:
-// [0, V) focal scales gamma (float64), then alpha, then beta of every record
-// (float32 parameters; the update is formed in float64 from the stored value
-// and rounded once).  Moments are float64: m_depth / v_depth hold alpha's at
+// Adam with bias correction at t = step + 1), one thread per view (its focal
+// scale gamma, float64) and one per edge record (its alpha and beta, float32
+// parameters: the update is formed in float64 from the stored value and
+// rounded once).  Moments are float64: m_depth / v_depth hold alpha's at
 // [0, n) and beta's at [n, 2n).  With a phase array, the scene's phase gates
 // the step: gamma moves unless the scene has stopped (phase 2), alpha and
 // beta only in the joint phase (phase 1); a gated parameter and its moments
-// are left as they are.
+// are left as they are.  With z0 and records, each record's depth is then
+// rewritten from the current alpha and beta, as the refinement update does.
 __global__ __launch_bounds__(256) void joint_step_kernel(
     double* __restrict__ gamma, float* __restrict__ alpha, float* __restrict__ beta,
     double* __restrict__ m_gamma, double* __restrict__ v_gamma, double* __restrict__ m_depth,
@@ -170,47 +175,62 @@ __global__ __launch_bounds__(256) void joint_step_kernel(
     const double* __restrict__ g_alpha, const double* __restrict__ g_beta,
     const int64_t* __restrict__ rec_off, const int32_t* __restrict__ scene_of_view, int32_t V,
     int64_t n, const double* __restrict__ lr, const int32_t* __restrict__ phase, double b1,
-    double b2, double eps, double wd_focal, double wd_depth, const int32_t* __restrict__ step) {
+    double b2, double eps, double wd_focal, double wd_depth, const int32_t* __restrict__ step,
+    const float* __restrict__ z0, uint2* __restrict__ records, int32_t* __restrict__ status) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the view of the workgroup's first record, found once (records are in
+    // view order, so each thread then advances a few views at most)
+    __shared__ int view0;
+    if (threadIdx.x == 0) {
+        const int64_t r0 = std::max<int64_t>((int64_t)blockIdx.x * blockDim.x - V, 0);
+        int lo = 0, hi = V - 1;              // last view whose first record is <= r0
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rec_off[mid] <= r0) lo = mid; else hi = mid - 1;
+        }
+        view0 = lo;
+    }
+    __syncthreads();
+    if (k >= (int64_t)V + n) return;
     const double t = (double)(step[0] + 1);
     const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
-    const int64_t total = (int64_t)V + 2 * n;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        int view;
-        int64_t q = 0;
-        if (k < V) {
-            view = (int)k;
-        } else {
-            q = k - V;
-            const int64_t r = q < n ? q : q - n;
-            int lo = 0, hi = V - 1;          // last view whose first record is <= r
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (rec_off[mid] <= r) lo = mid; else hi = mid - 1;
-            }
-            view = lo;
-        }
-        const int sc = scene_of_view[view];
-        const int ph = phase ? phase[sc] : 1;
+    if (k < V) {
+        const int sc = scene_of_view[k];
+        if (phase && phase[sc] == 2) return;
         const double a = lr[sc];
-        if (k < V) {
-            if (ph == 2) continue;
-            const double g = g_gamma[k];
-            const double mk = b1 * m_gamma[k] + (1.0 - b1) * g;
-            const double vk = b2 * v_gamma[k] + (1.0 - b2) * g * g;
-            m_gamma[k] = mk;
-            v_gamma[k] = vk;
-            gamma[k] = gamma[k] * (1.0 - a * wd_focal) - a * (mk / c1) / (sqrt(vk / c2) + eps);
-        } else {
-            if (ph != 1) continue;
-            float* x = q < n ? alpha + q : beta + (q - n);
-            const double g = q < n ? g_alpha[q] : g_beta[q - n];
-            const double mk = b1 * m_depth[q] + (1.0 - b1) * g;
-            const double vk = b2 * v_depth[q] + (1.0 - b2) * g * g;
-            m_depth[q] = mk;
-            v_depth[q] = vk;
-            *x = (float)((double)*x * (1.0 - a * wd_depth) - a * (mk / c1) / (sqrt(vk / c2) + eps));
-        }
+        const double g = g_gamma[k];
+        const double mk = b1 * m_gamma[k] + (1.0 - b1) * g;
+        const double vk = b2 * v_gamma[k] + (1.0 - b2) * g * g;
+        m_gamma[k] = mk;
+        v_gamma[k] = vk;
+        gamma[k] = gamma[k] * (1.0 - a * wd_focal) - a * (mk / c1) / (sqrt(vk / c2) + eps);
+        return;
+    }
+    const int64_t r = k - V;
+    int view = view0;                        // rec_off[view] <= r0 <= r < n = rec_off[V]
+    while (rec_off[view + 1] <= r) ++view;
+    const int sc = scene_of_view[view];
+    float xa = alpha[r], xb = beta[r];
+    if (!phase || phase[sc] == 1) {
+        const double a = lr[sc];
+        const double ga = g_alpha[r], gb = g_beta[r];
+        const double ma = b1 * m_depth[r] + (1.0 - b1) * ga;
+        const double va = b2 * v_depth[r] + (1.0 - b2) * ga * ga;
+        const double mb = b1 * m_depth[n + r] + (1.0 - b1) * gb;
+        const double vb = b2 * v_depth[n + r] + (1.0 - b2) * gb * gb;
+        m_depth[r] = ma;
+        v_depth[r] = va;
+        m_depth[n + r] = mb;
+        v_depth[n + r] = vb;
+        xa = (float)((double)xa * (1.0 - a * wd_depth) - a * (ma / c1) / (sqrt(va / c2) + eps));
+        xb = (float)((double)xb * (1.0 - a * wd_depth) - a * (mb / c1) / (sqrt(vb / c2) + eps));
+        alpha[r] = xa;
+        beta[r] = xb;
+    }
+    if (records) {
+        const float z = refined_depth(z0[r], xa, xb);
+        if (!isfinite(z)) atomicOr(status, 4);
+        records[r].y = __float_as_uint(z);
     }
 }
 
@@ -302,6 +322,7 @@ extern "C" epo_status epo_joint_step(epo_plan plan, double* gamma, float* alpha,
                                      const double* lr, const int32_t* phase, double beta1,
                                      double beta2, double eps, double wd_focal, double wd_depth,
                                      const int32_t* step, void* stream) {
+    bool installed = false;
     const epo_status st = guarded([&] {
         EPO_REQUIRE(plan, "null plan");
         EPO_REQUIRE(gamma && alpha && beta && m_gamma && v_gamma && m_depth && v_depth &&
@@ -318,16 +339,23 @@ extern "C" epo_status epo_joint_step(epo_plan plan, double* gamma, float* alpha,
             EPO_HIP(hipMemcpyAsync(p.rec_off_d.p, p.rec_off.data(),
                                    p.rec_off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
         }
-        const int64_t total = (int64_t)p.V + 2 * n;
-        const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(total, 256), 8192);
-        joint_step_kernel<<<grid, 256, 0, s>>>(gamma, alpha, beta, m_gamma, v_gamma, m_depth,
-                                               v_depth, grad_gamma, grad_alpha, grad_beta,
-                                               p.rec_off_d.p, p.scene_of_view_d.p, p.V, n, lr,
-                                               phase, beta1, beta2, eps, wd_focal, wd_depth,
-                                               step);
+        // once the plan holds its original depths (after the first depth
+        // update), the step kernel rewrites the records' depths itself
+        installed = p.z0.p != nullptr;
+        const int64_t total = (int64_t)p.V + n;
+        joint_step_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(
+            gamma, alpha, beta, m_gamma, v_gamma, m_depth, v_depth, grad_gamma, grad_alpha,
+            grad_beta, p.rec_off_d.p, p.scene_of_view_d.p, p.V, n, lr, phase, beta1, beta2, eps,
+            wd_focal, wd_depth, step, installed ? p.z0.p : nullptr,
+            installed ? reinterpret_cast<uint2*>(p.records.p) : nullptr, p.status.p);
         EPO_CHECK_LAUNCH();
+        if (installed) {
+            refine_intrinsics_kernel<<<(unsigned)ceil_div(p.V, 256), 256, 0, s>>>(
+                p.K0_d.p, gamma, p.K_d.p, p.gamma_d.p, p.V, p.status.p);
+            EPO_CHECK_LAUNCH();
+        }
     });
-    if (st != EPO_OK) return st;
-    // the refined focal lengths and depths of the new parameters
+    if (st != EPO_OK || installed) return st;
+    // first depth update of the plan: the refinement update keeps its depths
     return epo_plan_set_refinement(plan, gamma, alpha, beta, stream);
 }

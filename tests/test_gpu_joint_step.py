@@ -97,20 +97,26 @@ def test_joint_step_matches_oracle(gpu):
 
 
 def test_joint_step_sets_refinement(gpu):
-    """After a step the plan's refinement is that of the new parameters:
+    """After each step the plan's refinement is that of the new parameters:
     the loss and gradients equal those after an explicit set_refinement of
-    the same arrays (bitwise), and differ from the unrefined ones."""
+    the same arrays (bitwise), and differ from the unrefined ones.  The first
+    step of a plan installs the depths through the refinement update, later
+    ones rewrite them in the step kernel (phases (1, 0) on the third step:
+    one scene's depths stay, the other's move)."""
     prob, plan, sv, vor, rng, host, dev = setup(seed=1)
     V, n = plan.n_views, plan.n_records
     P = torch.from_numpy(prob.poses_init.copy()).cuda()
-    g = {k: torch.from_numpy(v).cuda() for k, v in grads_of(rng, V, n).items()}
-    step = torch.zeros(1, dtype=torch.int32, device="cuda")
-    plan.joint_step(dev, g, 1e-2, step)
-    after = {k: t.cpu().numpy() for k, t in plan.refine(P, 10.0).items()}
-    plan.set_refinement(dev["gamma"], dev["alpha"], dev["beta"])
-    explicit = {k: t.cpu().numpy() for k, t in plan.refine(P, 10.0).items()}
-    for k in after:
-        assert np.array_equal(after[k], explicit[k]), k
+    for s, ph in enumerate((None, None, [1, 0])):
+        g = {k: torch.from_numpy(v).cuda() for k, v in grads_of(rng, V, n).items()}
+        step = torch.tensor([s], dtype=torch.int32, device="cuda")
+        ph_t = None if ph is None else torch.tensor(ph, dtype=torch.int32, device="cuda")
+        plan.joint_step(dev, g, 1e-2, step, phase=ph_t)
+        after = {k: t.cpu().numpy() for k, t in plan.refine(P, 10.0).items()}
+        plan.set_refinement(dev["gamma"], dev["alpha"], dev["beta"])
+        explicit = {k: t.cpu().numpy() for k, t in plan.refine(P, 10.0).items()}
+        for k in after:
+            assert np.array_equal(after[k], explicit[k]), (s, k)
+        assert plan.device_status() == 0
     plan.set_refinement()
     base = plan.refine(P, 10.0)["loss"].cpu().numpy()
     assert not np.array_equal(base, after["loss"])
