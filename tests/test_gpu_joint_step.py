@@ -143,3 +143,56 @@ def test_joint_step_rejects_bad_arguments(gpu):
                         g["grad_alpha"], g["grad_beta"],
                         torch.ones(plan.n_scenes, dtype=torch.float64, device="cuda"), None,
                         0.9, 0.999, 1e-8, 0.01, 0.01, None, None)
+
+
+def test_joint_step_views_without_edges(gpu):
+    """Six views of 40x30 with 300, 0, 7, 0, 500, 0 edge pixels (813
+    parameters over four workgroups whose boundaries fall inside views, empty
+    views in the middle and at the end): two steps (the first installs the
+    depths through the refinement update, the second rewrites them itself)
+    against the oracle, and the installed refinement against an explicit
+    set_refinement."""
+    from paper_2607_00579_amd.api import EdgePlan
+    from synth import fixtures
+    W, H = 40, 30
+    K = [32.0, 32.0, 19.5, 14.5]
+    rng = np.random.default_rng(11)
+    edges, depths = [], []
+    for cnt in (300, 0, 7, 0, 500, 0):
+        e = np.zeros(W * H, np.uint8)
+        e[rng.choice(W * H, cnt, replace=False)] = 255
+        edges.append(e.reshape(H, W))
+        depths.append(rng.uniform(2.0, 6.0, (H, W)).astype(np.float32))
+    P = [np.concatenate([np.eye(3), np.array([[0.05 * v], [0.0], [0.0]])], axis=1)
+         for v in range(6)]
+    pairs = [[i, j] for i in range(6) for j in range(6) if i != j]
+    q = fixtures.problem_from_maps([W] * 6, [H] * 6, [K] * 6, edges, depths, P, pairs)
+    plan = EdgePlan.from_problem(q, device="cuda:0")
+    V, n = plan.n_views, plan.n_records
+    assert (V, n) == (6, 807)
+    vor = plan.record_pixels()[:, 0]
+    sv = np.asarray(plan.scene_of_view, np.int64)
+    host = {"gamma": rng.normal(0, 0.02, V), "alpha": (1 + rng.normal(0, 0.05, n)).astype(np.float32),
+            "beta": rng.normal(0, 0.05, n).astype(np.float32),
+            "m_gamma": np.zeros(V), "v_gamma": np.zeros(V)}
+    for k in ("alpha", "beta"):
+        host["m_" + k] = np.zeros(n)
+        host["v_" + k] = np.zeros(n)
+    dev = plan.joint_state()
+    for k in ("gamma", "alpha", "beta"):
+        dev[k].copy_(torch.from_numpy(host[k]))
+    poses = torch.from_numpy(q.poses_init.copy()).cuda()
+    lr = np.array([2e-3])
+    want = host
+    for s in range(2):
+        g = grads_of(rng, V, n)
+        step = torch.tensor([s], dtype=torch.int32, device="cuda")
+        plan.joint_step(dev, {k: torch.from_numpy(v).cuda() for k, v in g.items()},
+                        torch.from_numpy(lr).cuda(), step)
+        after = {k: t.cpu().numpy() for k, t in plan.refine(poses, 10.0).items()}
+        prev, want = want, oj.joint_step(want, g, lr, sv, vor, s)
+        compare(dev, want, prev, g, n, f"empty views, step {s}")
+        plan.set_refinement(dev["gamma"], dev["alpha"], dev["beta"])
+        explicit = {k: t.cpu().numpy() for k, t in plan.refine(poses, 10.0).items()}
+        for k in after:
+            assert np.array_equal(after[k], explicit[k]), (s, k)
