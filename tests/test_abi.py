@@ -68,6 +68,10 @@ def test_version_and_error_paths(lib):
     with pytest.raises(lib.EpoError) as e:
         lib.edge_cost_refine(None, None, None, None, None, None, None, None, None, None)
     assert e.value.status == lib.ERR_INVALID_ARG
+    with pytest.raises(lib.EpoError) as e:
+        lib.joint_step(None, None, None, None, None, None, None, None, None, None, None, None,
+                       None, 0.9, 0.999, 1e-8, 0.01, 0.01, None, None)
+    assert e.value.status == lib.ERR_INVALID_ARG and "null plan" in str(e.value)
     # zero views is a valid no-op for the distance transform
     lib.build_distance_fields(None, None, None, None, 0, None, None, None)
 
