@@ -9,7 +9,7 @@
 //                records each segment's first and last edge row (in d2, not
 //                yet written); the second takes the nearest edge above and
 //                below its segment from those records, then sweeps the
-//                segment down and up.  The 64 threads of a wave take 64
+//                segment down and up, holding it in registers in between.  The 64 threads of a wave take 64
 //                adjacent columns, so every step is one coalesced access, and
 //                the segments give every view H/64 times the waves of a
 //                thread-per-column pass.
@@ -91,11 +91,20 @@ __global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ ed
             break;
         }
     }
-#pragma unroll 8
-    for (int y = y0; y < y1; ++y) {
-        const int64_t o = (int64_t)y * W;
-        if (e[o]) last = y;
-        out[o] = last >= 0 ? (y - last) : -1;
+    // the segment stays in registers between the two sweeps: the distance
+    // to the edge above (-1: none) per row, and the rows' edge flags as bits
+    int up[kSeg];
+    uint64_t emask = 0;
+#pragma unroll
+    for (int i = 0; i < kSeg; ++i) {
+        const int y = y0 + i;
+        if (y < y1) {
+            if (e[(int64_t)y * W]) {
+                last = y;
+                emask |= 1ull << i;
+            }
+            up[i] = last >= 0 ? (y - last) : -1;
+        }
     }
     int next = -1;                       // row of the nearest edge at or below
     for (int q = s0 + 1; q < n_seg; ++q) {
@@ -105,13 +114,15 @@ __global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ ed
             break;
         }
     }
-#pragma unroll 8
-    for (int y = y1 - 1; y >= y0; --y) {
-        const int64_t o = (int64_t)y * W;
-        if (e[o]) next = y;
-        int best = out[o];
-        if (next >= 0 && (best < 0 || next - y < best)) best = next - y;
-        out[o] = best >= 0 ? best * best : kInf;
+#pragma unroll
+    for (int i = kSeg - 1; i >= 0; --i) {
+        const int y = y0 + i;
+        if (y < y1) {
+            if ((emask >> i) & 1ull) next = y;
+            int best = up[i];
+            if (next >= 0 && (best < 0 || next - y < best)) best = next - y;
+            out[(int64_t)y * W] = best >= 0 ? best * best : kInf;
+        }
     }
 }
 
