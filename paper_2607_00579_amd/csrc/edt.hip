@@ -14,7 +14,7 @@
 //                the segments give every view H/64 times the waves of a
 //                thread-per-column pass.
 //   row pass     d2(x, y) = min over q of f(q, y) + (x - q)^2.  One workgroup
-//                per row stages f of the row and its minimum per 8-pixel
+//                per row stages f of the row and its minimum per 16-pixel
 //                block in LDS; each x searches outward block by block,
 //                scanning only blocks whose minimum plus the squared
 //                distance could beat its best value, and stops when the
@@ -129,15 +129,15 @@ __global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ ed
 // One workgroup per row.  The row's column-pass values live in dtf (the
 // call's scratch); the workgroup reads all of them into LDS before any of its
 // threads writes the row's DTF, and no other workgroup touches the row.
-// The row is split into blocks of 8 pixels with their minimum f in LDS; a
+// The row is split into blocks of 16 pixels with their minimum f in LDS; a
 // pixel scans its own block, then the blocks at block distance R = 1, 2, ...
 // on both sides: a block is scanned only if its minimum plus the squared
 // distance to its nearest pixel is below the best value so far, and the
 // search ends once the nearer of the two blocks is at least sqrt(best) away
 // (every farther pixel adds more).  Every pixel that can attain the minimum
-// is scanned, so the result is the exact minimum, at about D/8 block tests
+// is scanned, so the result is the exact minimum, at about D/16 block tests
 // per pixel (D its distance to the nearest edge).
-constexpr int kRowBlk = 8;
+constexpr int kRowBlk = 16;
 
 __global__ __launch_bounds__(256) void edt_rows(const int32_t* __restrict__ colsq,
                                                int32_t* __restrict__ d2, float* __restrict__ dtf,
@@ -232,7 +232,7 @@ extern "C" epo_status epo_build_distance_fields(const uint8_t* edge_maps, const 
             EPO_CHECK_LAUNCH();
             const size_t lds = (size_t)(maxW + ceil_div(maxW, kRowBlk)) * sizeof(int32_t);
             if (lds > 65536) {
-                // rows wider than 14563 pixels: more than the default 64 KB of
+                // rows wider than 15420 pixels: more than the default 64 KB of
                 // dynamic LDS (gfx950 has 160 KB per workgroup); an error, never
                 // a short allocation, if the device cannot give it
                 int dev = 0, max_lds = 0;

@@ -53,10 +53,12 @@ def test_random_maps_bit_exact(gpu, shape, density):
 
 def test_wide_and_single_pixel(gpu):
     """Maps with one or two edge pixels: d2 is the closed-form minimum over
-    them.  Rows of 14600 and 16384 pixels need more than 64 KB of LDS in the
-    row pass."""
+    them.  The row pass stages a row and its 16-pixel block minima in LDS:
+    rows of up to 15420 pixels fit in 64 KB, wider ones (15421, 15500,
+    16384) need more."""
     cases = [(3, 4000, [(1, 3999)]), (2000, 2, [(0, 0)]), (64, 2048, [(63, 1000)]),
-             (2, 16384, [(1, 5)]), (3, 14600, [(0, 14599)]),
+             (2, 16384, [(1, 5)]), (3, 15500, [(0, 15499)]),
+             (2, 15420, [(1, 15419)]), (2, 15421, [(0, 7000)]),
              (4, 16384, [(0, 9000), (3, 9100)])]
     maps = []
     for H, W, pts in cases:
