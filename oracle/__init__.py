@@ -20,6 +20,14 @@ integers), written from the paper's definitions:
   loop.py      clamp annealing, learning-rate warm-up + cosine (Sec. 4
                implementation details, Alg. 3), Adam on se(3) twists, the
                iteration loop
+  convergence.py  pose-change signal theta_95 and the dual-phase windowed
+               convergence test (Sec. 3 optimization schedule, Alg. 2)
+  joint.py     the joint phase's AdamW step of focal scales and per-pixel
+               depth scale and shift, gated by the convergence phase
+  mlp.py       the paper's pose refiner: MLP, 6D rotation and Gram-Schmidt,
+               translation offset, AdamW, with BF16 operand rounding
+  sampling.py  per-step stochastic image-pair sub-sampling (SplitMix64 draws)
+  viewgraph.py cycle-consistent reprojection test for candidate image pairs
 
 Parity status of each function is stated in its module header.
 """
