@@ -206,14 +206,13 @@ def refine_timing(plan, poses, lam, steps, warmup, R):
     state["alpha"].fill_(1.01)
     state["beta"].fill_(0.01)
     lr = torch.full((plan.n_scenes,), 3e-3, dtype=torch.float64, device=plan.device)
-    step = torch.zeros(1, dtype=torch.int32, device=plan.device)
     for _ in range(max(warmup, 1)):
-        plan.joint_step(state, grads, lr, step)
+        plan.joint_step(state, grads, lr)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        plan.joint_step(state, grads, lr, step)
+        plan.joint_step(state, grads, lr)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
@@ -551,9 +550,8 @@ def main():
                             torch.full((plan.n_records,), 0.01))
         state = plan.joint_state()
         lr = torch.full((plan.n_scenes,), 3e-3, dtype=torch.float64, device=dev)
-        jstep = torch.zeros(1, dtype=torch.int32, device=dev)
         for _ in range(args.warmup + args.steps):
-            plan.joint_step(state, plan.refine(poses, lam), lr, jstep)
+            plan.joint_step(state, plan.refine(poses, lam), lr)
         torch.cuda.synchronize()
         log("refine-only run done")
         return

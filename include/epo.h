@@ -270,12 +270,12 @@ EPO_API epo_status epo_edge_cost_refine(epo_plan plan, const double* poses, cons
  * epo_joint_step applies one AdamW step to the focal scales gamma and the
  * per-record depth scale alpha and shift beta, then makes the new values the
  * plan's refinement exactly as epo_plan_set_refinement does.  For each
- * parameter x with gradient g, learning rate a = lr[scene] and t = *step + 1:
+ * parameter x with gradient g, learning rate a = lr[scene] and t = 1 + the
+ * steps its optimizer has taken (per scene, focal scales and depth
+ * parameters counted apart, as separate optimizers; see `steps`):
  *   x <- x (1 - a wd),  m <- b1 m + (1 - b1) g,  w <- b2 w + (1 - b2) g^2,
  *   x <- x - a (m / (1 - b1^t)) / (sqrt(w / (1 - b2^t)) + eps)
  * in float64 (alpha, beta are read as float32, rounded once when stored).
- * The step counter is read, not advanced: call this before epo_pose_step of
- * the same iteration, which advances it, so both use the same t.
  *
  *   gamma               float64 [V], updated in place
  *   alpha, beta         float32 [n_records] (plan record order), in place
@@ -291,7 +291,13 @@ EPO_API epo_status epo_edge_cost_refine(epo_plan plan, const double* poses, cons
  *                       NULL: every parameter steps.
  *   wd_focal, wd_depth  weight decay of gamma and of alpha, beta (the paper:
  *                       0.01 for both)
- *   step                int32 [1] device step counter (read only)
+ *   steps               int32 [2][n_scenes] step counts, start at 0:
+ *                       steps[s] the AdamW steps scene s's focal scales have
+ *                       taken, steps[n_scenes + s] those of its depth
+ *                       parameters (so the depth optimizer's first step after
+ *                       the switch to the joint phase is its step 1); the call
+ *                       advances the count of every parameter kind that
+ *                       stepped
  * All arrays are device memory.  Errors: EPO_ERR_INVALID_ARG for a null
  * pointer other than phase or betas outside [0, 1) or eps <= 0.  The first
  * call allocates a copy of the plan's record offsets (8 bytes per view) and,
@@ -305,7 +311,7 @@ EPO_API epo_status epo_joint_step(epo_plan plan, double* gamma, float* alpha, fl
                                   const double* grad_alpha, const double* grad_beta,
                                   const double* lr, const int32_t* phase, double beta1,
                                   double beta2, double eps, double wd_focal, double wd_depth,
-                                  const int32_t* step, void* stream);
+                                  int32_t* steps, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Viewgraph estimation (paper Sec. 3 "Viewgraph Estimation", Sec. 4

@@ -237,12 +237,12 @@ def edge_cost_refine(plan, poses, lam, upstream, loss, grad, grad_gamma, grad_al
 
 
 def joint_step(plan, gamma, alpha, beta, m_gamma, v_gamma, m_depth, v_depth, grad_gamma,
-               grad_alpha, grad_beta, lr, phase, beta1, beta2, eps, wd_focal, wd_depth, step,
+               grad_alpha, grad_beta, lr, phase, beta1, beta2, eps, wd_focal, wd_depth, steps,
                stream):
     _check(load().epo_joint_step(plan, _ptr(gamma), _ptr(alpha), _ptr(beta), _ptr(m_gamma),
                                  _ptr(v_gamma), _ptr(m_depth), _ptr(v_depth), _ptr(grad_gamma),
                                  _ptr(grad_alpha), _ptr(grad_beta), _ptr(lr), _ptr(phase), beta1,
-                                 beta2, eps, wd_focal, wd_depth, _ptr(step), stream))
+                                 beta2, eps, wd_focal, wd_depth, _ptr(steps), stream))
 
 
 def pose_step(poses, m, v, grad, n_views, scene_of_view, fixed_mask, lr, beta1, beta2, eps, step,

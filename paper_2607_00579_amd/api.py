@@ -242,9 +242,11 @@ class EdgePlan:
 
     def joint_state(self):
         """Parameters of the joint phase at their identity values (gamma 0,
-        alpha 1, beta 0) and zero AdamW moments, on the plan's device."""
+        alpha 1, beta 0), zero AdamW moments and step counts (per scene, the
+        focal scales' then the depth parameters'), on the plan's device."""
         d, n, V = self.device, self.n_records, self.n_views
-        return {"gamma": torch.zeros(V, dtype=torch.float64, device=d),
+        return {"steps": torch.zeros(2 * self.n_scenes, dtype=torch.int32, device=d),
+                "gamma": torch.zeros(V, dtype=torch.float64, device=d),
                 "alpha": torch.ones(max(n, 1), dtype=torch.float32, device=d)[:n],
                 "beta": torch.zeros(max(n, 1), dtype=torch.float32, device=d)[:n],
                 "m_gamma": torch.zeros(V, dtype=torch.float64, device=d),
@@ -252,13 +254,13 @@ class EdgePlan:
                 "m_depth": torch.zeros(max(2 * n, 1), dtype=torch.float64, device=d),
                 "v_depth": torch.zeros(max(2 * n, 1), dtype=torch.float64, device=d)}
 
-    def joint_step(self, state, grads, lr, step, phase=None, beta1=0.9, beta2=0.999, eps=1e-8,
+    def joint_step(self, state, grads, lr, phase=None, beta1=0.9, beta2=0.999, eps=1e-8,
                    wd_focal=0.01, wd_depth=0.01):
         """One AdamW step of gamma, alpha, beta (state from joint_state,
-        updated in place; grads from refine()), then the plan's refinement is
-        set to the new values.  phase: int32 [n_scenes] device tensor of
-        convergence phases (depth steps only in phase 1, nothing in phase 2)
-        or None (every parameter steps).  `step` is read, not advanced."""
+        updated in place, its step counts included; grads from refine()),
+        then the plan's refinement is set to the new values.  phase: int32
+        [n_scenes] device tensor of convergence phases (depth steps only in
+        phase 1, nothing in phase 2) or None (every parameter steps)."""
         if not torch.is_tensor(lr):
             lr = torch.full((self.n_scenes,), float(lr), dtype=torch.float64, device=self.device)
         for k in ("grad_gamma", "grad_alpha", "grad_beta"):
@@ -274,7 +276,7 @@ class EdgePlan:
                    ("grad_alpha", grads["grad_alpha"], torch.float64, n),
                    ("grad_beta", grads["grad_beta"], torch.float64, n),
                    ("lr", lr, torch.float64, self.n_scenes),
-                   ("step", step, torch.int32, 1)]
+                   ("state['steps']", state.get("steps"), torch.int32, 2 * self.n_scenes)]
         if phase is not None:
             checks.append(("phase", phase, torch.int32, self.n_scenes))
         for name, t, dt, size in checks:
@@ -287,7 +289,7 @@ class EdgePlan:
                         state["m_gamma"], state["v_gamma"], state["m_depth"], state["v_depth"],
                         grads["grad_gamma"], grads["grad_alpha"], grads["grad_beta"],
                         lr, phase, beta1, beta2,
-                        eps, wd_focal, wd_depth, step, _stream(self.device))
+                        eps, wd_focal, wd_depth, state["steps"], _stream(self.device))
 
     def pose_step(self, poses, m, v, grad, lr, step, fixed_mask=None, beta1=0.9, beta2=0.999,
                   eps=1e-8):
@@ -357,7 +359,10 @@ class EdgeCostFn(torch.autograd.Function):
             ctx.save_for_backward(o["grad"])
         else:
             o = plan.cost(poses, lam, grad=False)
-            ctx.poses, ctx.lam = poses, lam
+            # saved through autograd, so an in-place change of the poses
+            # before backward raises instead of differentiating elsewhere
+            ctx.save_for_backward(poses)
+            ctx.lam = lam.clone() if torch.is_tensor(lam) else lam
         return o["loss"]
 
     @staticmethod
@@ -367,7 +372,8 @@ class EdgeCostFn(torch.autograd.Function):
             (g,) = ctx.saved_tensors
             scale = grad_loss.to(torch.float64)[plan.scene_of_view_t].unsqueeze(1)
             return scale * g, None, None, None, None
-        g = plan.cost_bwd(ctx.poses, ctx.lam, upstream=grad_loss.to(torch.float64).contiguous())
+        (poses,) = ctx.saved_tensors
+        g = plan.cost_bwd(poses, ctx.lam, upstream=grad_loss.to(torch.float64).contiguous())
         return g, None, None, None, None
 
 
@@ -377,17 +383,24 @@ class EdgeRefineFn(torch.autograd.Function):
     per-record depth scale alpha and shift beta [n_records] (derivatives at
     the given values, which the forward pass installs in the plan).  The
     backward pass is the hand-written adjoint: one refinement call with the
-    upstream gradient (recompute)."""
+    upstream gradient (recompute), after installing the forward's gamma,
+    alpha and beta again (another forward or joint step may have changed the
+    plan's refinement in between).  Poses and refinement values are saved
+    through autograd, so changing them in place before backward raises."""
 
     @staticmethod
     def forward(ctx, xi, gamma, alpha, beta, plan: EdgePlan, poses, lam):
         plan.set_refinement(gamma.detach(), alpha.detach(), beta.detach())
-        ctx.plan, ctx.poses, ctx.lam = plan, poses, lam
+        ctx.plan = plan
+        ctx.lam = lam.clone() if torch.is_tensor(lam) else lam
+        ctx.save_for_backward(poses, gamma, alpha, beta)
         return plan.refine(poses, lam, grad=False, focal=False, depth=False)["loss"]
 
     @staticmethod
     def backward(ctx, grad_loss):
-        o = ctx.plan.refine(ctx.poses, ctx.lam, upstream=grad_loss.to(torch.float64).contiguous(),
+        poses, gamma, alpha, beta = ctx.saved_tensors
+        ctx.plan.set_refinement(gamma.detach(), alpha.detach(), beta.detach())
+        o = ctx.plan.refine(poses, ctx.lam, upstream=grad_loss.to(torch.float64).contiguous(),
                             loss=False)
         return (o["grad"], o["grad_gamma"], o["grad_alpha"], o["grad_beta"], None, None, None)
 

@@ -159,24 +159,30 @@ void launch_depth_fmt(Plan& p, const uint32_t* tex, const double* upstream, doub
 }
 
 // AdamW step of the joint phase's parameters (decoupled weight decay, then
-// Adam with bias correction at t = step + 1), one thread per view (its focal
-// scale gamma, float64) and one per edge record (its alpha and beta, float32
-// parameters: the update is formed in float64 from the stored value and
-// rounded once).  Moments are float64: m_depth / v_depth hold alpha's at
-// [0, n) and beta's at [n, 2n).  With a phase array, the scene's phase gates
-// the step: gamma moves unless the scene has stopped (phase 2), alpha and
-// beta only in the joint phase (phase 1); a gated parameter and its moments
-// are left as they are.  With z0 and records, each record's depth is then
-// rewritten from the current alpha and beta, as the refinement update does.
+// Adam with bias correction at the 1-based step of the optimizer that owns
+// the parameter), one thread per view (its focal scale gamma, float64) and
+// one per edge record (its alpha and beta, float32 parameters: the update is
+// formed in float64 from the stored value and rounded once).  Each scene's
+// focal scales and depth parameters count their own steps: steps[s] and
+// steps[S + s] hold the steps taken so far (advanced afterwards by
+// count_joint_steps_kernel), so a scene's first depth step after its switch
+// to the joint phase is its depth optimizer's step 1.  Moments are float64:
+// m_depth / v_depth hold alpha's at [0, n) and beta's at [n, 2n).  With a
+// phase array, the scene's phase gates the step: gamma moves unless the
+// scene has stopped (phase 2), alpha and beta only in the joint phase
+// (phase 1); a gated parameter and its moments are left as they are.  With
+// z0 and records, each record's depth is then rewritten from the current
+// alpha and beta, as the refinement update does.
 __global__ __launch_bounds__(256) void joint_step_kernel(
     double* __restrict__ gamma, float* __restrict__ alpha, float* __restrict__ beta,
     double* __restrict__ m_gamma, double* __restrict__ v_gamma, double* __restrict__ m_depth,
     double* __restrict__ v_depth, const double* __restrict__ g_gamma,
     const double* __restrict__ g_alpha, const double* __restrict__ g_beta,
     const int64_t* __restrict__ rec_off, const int32_t* __restrict__ scene_of_view, int32_t V,
-    int64_t n, const double* __restrict__ lr, const int32_t* __restrict__ phase, double b1,
-    double b2, double eps, double wd_focal, double wd_depth, const int32_t* __restrict__ step,
-    const float* __restrict__ z0, uint2* __restrict__ records, int32_t* __restrict__ status) {
+    int64_t n, int32_t S, const double* __restrict__ lr, const int32_t* __restrict__ phase,
+    double b1, double b2, double eps, double wd_focal, double wd_depth,
+    const int32_t* __restrict__ steps, const float* __restrict__ z0, uint2* __restrict__ records,
+    int32_t* __restrict__ status) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // the view of the workgroup's first record, found once (records are in
     // view order, so each thread then advances a few views at most)
@@ -192,11 +198,11 @@ __global__ __launch_bounds__(256) void joint_step_kernel(
     }
     __syncthreads();
     if (k >= (int64_t)V + n) return;
-    const double t = (double)(step[0] + 1);
-    const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
     if (k < V) {
         const int sc = scene_of_view[k];
         if (phase && phase[sc] == 2) return;
+        const double t = (double)(steps[sc] + 1);
+        const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
         const double a = lr[sc];
         const double g = g_gamma[k];
         const double mk = b1 * m_gamma[k] + (1.0 - b1) * g;
@@ -212,6 +218,8 @@ __global__ __launch_bounds__(256) void joint_step_kernel(
     const int sc = scene_of_view[view];
     float xa = alpha[r], xb = beta[r];
     if (!phase || phase[sc] == 1) {
+        const double t = (double)(steps[S + sc] + 1);
+        const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
         const double a = lr[sc];
         const double ga = g_alpha[r], gb = g_beta[r];
         const double ma = b1 * m_depth[r] + (1.0 - b1) * ga;
@@ -232,6 +240,19 @@ __global__ __launch_bounds__(256) void joint_step_kernel(
         if (!isfinite(z)) atomicOr(status, 4);
         records[r].y = __float_as_uint(z);
     }
+}
+
+// the steps the joint step just took: a scene's focal count advances unless
+// it has stopped, its depth count only in the joint phase (every count when
+// no phases are given)
+__global__ __launch_bounds__(256) void count_joint_steps_kernel(int32_t* __restrict__ steps,
+                                                                const int32_t* __restrict__ phase,
+                                                                int32_t S) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const int ph = phase ? phase[s] : 1;
+    if (ph != 2) steps[s] += 1;
+    if (ph == 1) steps[S + s] += 1;
 }
 
 }  // namespace
@@ -321,12 +342,12 @@ extern "C" epo_status epo_joint_step(epo_plan plan, double* gamma, float* alpha,
                                      const double* grad_alpha, const double* grad_beta,
                                      const double* lr, const int32_t* phase, double beta1,
                                      double beta2, double eps, double wd_focal, double wd_depth,
-                                     const int32_t* step, void* stream) {
+                                     int32_t* steps, void* stream) {
     bool installed = false;
     const epo_status st = guarded([&] {
         EPO_REQUIRE(plan, "null plan");
         EPO_REQUIRE(gamma && alpha && beta && m_gamma && v_gamma && m_depth && v_depth &&
-                        grad_gamma && grad_alpha && grad_beta && lr && step,
+                        grad_gamma && grad_alpha && grad_beta && lr && steps,
                     "null pointer argument (only phase may be null)");
         EPO_REQUIRE(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0,
                     "beta1, beta2 must be in [0, 1) and eps > 0");
@@ -345,9 +366,11 @@ extern "C" epo_status epo_joint_step(epo_plan plan, double* gamma, float* alpha,
         const int64_t total = (int64_t)p.V + n;
         joint_step_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(
             gamma, alpha, beta, m_gamma, v_gamma, m_depth, v_depth, grad_gamma, grad_alpha,
-            grad_beta, p.rec_off_d.p, p.scene_of_view_d.p, p.V, n, lr, phase, beta1, beta2, eps,
-            wd_focal, wd_depth, step, installed ? p.z0.p : nullptr,
+            grad_beta, p.rec_off_d.p, p.scene_of_view_d.p, p.V, n, p.S, lr, phase, beta1, beta2,
+            eps, wd_focal, wd_depth, steps, installed ? p.z0.p : nullptr,
             installed ? reinterpret_cast<uint2*>(p.records.p) : nullptr, p.status.p);
+        EPO_CHECK_LAUNCH();
+        count_joint_steps_kernel<<<(unsigned)ceil_div(p.S, 256), 256, 0, s>>>(steps, phase, p.S);
         EPO_CHECK_LAUNCH();
         if (installed) {
             refine_intrinsics_kernel<<<(unsigned)ceil_div(p.V, 256), 256, 0, s>>>(

@@ -26,12 +26,10 @@ def setup(seed=0):
     vor = plan.record_pixels()[:, 0]
     sv = np.asarray(plan.scene_of_view, np.int64)
     rng = np.random.default_rng(seed)
-    host = {"gamma": rng.normal(0, 0.02, V), "alpha": (1 + rng.normal(0, 0.05, n)).astype(np.float32),
-            "beta": rng.normal(0, 0.05, n).astype(np.float32),
-            "m_gamma": np.zeros(V), "v_gamma": np.zeros(V)}
-    for k in ("alpha", "beta"):
-        host["m_" + k] = np.zeros(n)
-        host["v_" + k] = np.zeros(n)
+    host = oj.initial_state(V, n, plan.n_scenes)
+    host["gamma"] = rng.normal(0, 0.02, V)
+    host["alpha"] = (1 + rng.normal(0, 0.05, n)).astype(np.float32)
+    host["beta"] = rng.normal(0, 0.05, n).astype(np.float32)
     dev = plan.joint_state()
     dev["gamma"].copy_(torch.from_numpy(host["gamma"]))
     dev["alpha"].copy_(torch.from_numpy(host["alpha"]))
@@ -57,6 +55,7 @@ def check_first_moment(got, want, prev_m, g, tag):
 
 def compare(dev, want, prev, g, n, tag):
     got = {k: t.cpu().numpy() for k, t in dev.items()}
+    assert np.array_equal(got["steps"], want["steps"].reshape(-1)), f"{tag} step counts"
     for k in ("gamma", "v_gamma"):
         np.testing.assert_allclose(got[k], want[k], rtol=1e-13, atol=1e-300, err_msg=f"{tag} {k}")
     check_first_moment(got["m_gamma"], want["m_gamma"], prev["m_gamma"], g["grad_gamma"],
@@ -87,13 +86,46 @@ def test_joint_step_matches_oracle(gpu):
     for s, ph in enumerate(phases):
         g = grads_of(rng, V, n)
         gt = {k: torch.from_numpy(v).cuda() for k, v in g.items()}
-        step = torch.tensor([s], dtype=torch.int32, device="cuda")
         ph_t = None if ph is None else torch.tensor(ph, dtype=torch.int32, device="cuda")
-        plan.joint_step(dev, gt, lr_t, step, phase=ph_t)
+        plan.joint_step(dev, gt, lr_t, phase=ph_t)
         torch.cuda.synchronize()
-        prev, want = want, oj.joint_step(want, g, lr, sv, vor, s, phase=ph)
+        prev, want = want, oj.joint_step(want, g, lr, sv, vor, phase=ph)
         compare(dev, want, prev, g, n, f"step {s}")
-        assert int(step.item()) == s                 # read, not advanced
+
+
+def test_depth_steps_count_from_the_switch(gpu):
+    """Six gated steps after 40 steps of the pose phase (the focal counts
+    start at 40): scene 0 switches to the joint phase at step 2, scene 1 at
+    step 0 and stops at step 4.  The depth parameters' bias correction counts
+    the depth optimizer's own steps, so a scene's first depth step is the
+    closed form -lr g / (|g| + eps) after the decay; every step against the
+    oracle."""
+    prob, plan, sv, vor, rng, host, dev = setup(seed=2)
+    V, n, S = plan.n_views, plan.n_records, plan.n_scenes
+    host["steps"][0] = 40
+    dev["steps"].copy_(torch.from_numpy(host["steps"].reshape(-1).astype(np.int32)))
+    lr = np.array([3e-3, 1e-3])
+    lr_t = torch.from_numpy(lr).cuda()
+    phases = [[0, 1], [0, 1], [1, 1], [1, 1], [1, 2], [1, 2]]
+    want = host
+    sr = sv[vor]
+    for s, ph in enumerate(phases):
+        g = grads_of(rng, V, n)
+        gt = {k: torch.from_numpy(v).cuda() for k, v in g.items()}
+        before = dev["beta"].cpu().numpy().astype(np.float64)
+        plan.joint_step(dev, gt, lr_t, phase=torch.tensor(ph, dtype=torch.int32, device="cuda"))
+        torch.cuda.synchronize()
+        prev, want = want, oj.joint_step(want, g, lr, sv, vor, phase=ph)
+        compare(dev, want, prev, g, n, f"gated step {s}")
+        first = [sc for sc in range(S) if ph[sc] == 1 and prev["steps"][1][sc] == 0]
+        for sc in first:
+            idx = sr == sc
+            gb = g["grad_beta"][idx]
+            closed = before[idx] * (1 - lr[sc] * 0.01) - lr[sc] * gb / (np.abs(gb) + 1e-8)
+            got = dev["beta"].cpu().numpy()[idx].astype(np.float64)
+            assert np.all(np.abs(got - closed) <= np.spacing(np.abs(closed).astype(np.float32))), \
+                f"first depth step of scene {sc} at iteration {s}"
+    assert dev["steps"].cpu().tolist() == [46, 44, 4, 4]
 
 
 def test_joint_step_sets_refinement(gpu):
@@ -108,9 +140,8 @@ def test_joint_step_sets_refinement(gpu):
     P = torch.from_numpy(prob.poses_init.copy()).cuda()
     for s, ph in enumerate((None, None, [1, 0])):
         g = {k: torch.from_numpy(v).cuda() for k, v in grads_of(rng, V, n).items()}
-        step = torch.tensor([s], dtype=torch.int32, device="cuda")
         ph_t = None if ph is None else torch.tensor(ph, dtype=torch.int32, device="cuda")
-        plan.joint_step(dev, g, 1e-2, step, phase=ph_t)
+        plan.joint_step(dev, g, 1e-2, phase=ph_t)
         after = {k: t.cpu().numpy() for k, t in plan.refine(P, 10.0).items()}
         plan.set_refinement(dev["gamma"], dev["alpha"], dev["beta"])
         explicit = {k: t.cpu().numpy() for k, t in plan.refine(P, 10.0).items()}
@@ -126,18 +157,19 @@ def test_joint_step_rejects_bad_arguments(gpu):
     from paper_2607_00579_amd import _lib
     prob, plan, sv, vor, rng, host, dev = setup()
     g = {k: torch.from_numpy(v).cuda() for k, v in grads_of(rng, plan.n_views, plan.n_records).items()}
-    step = torch.zeros(1, dtype=torch.int32, device="cuda")
     with pytest.raises(RuntimeError):
-        plan.joint_step(dev, g, 1e-3, step, beta1=1.0)
+        plan.joint_step(dev, g, 1e-3, beta1=1.0)
     with pytest.raises(ValueError):
-        plan.joint_step(dev, {"grad_gamma": g["grad_gamma"]}, 1e-3, step)
+        plan.joint_step(dev, {"grad_gamma": g["grad_gamma"]}, 1e-3)
     with pytest.raises(ValueError):             # fewer phases than scenes
-        plan.joint_step(dev, g, 1e-3, step, phase=torch.zeros(1, dtype=torch.int32, device="cuda"))
+        plan.joint_step(dev, g, 1e-3, phase=torch.zeros(1, dtype=torch.int32, device="cuda"))
     with pytest.raises(ValueError):             # host memory
-        plan.joint_step(dev, dict(g, grad_beta=g["grad_beta"].cpu()), 1e-3, step)
+        plan.joint_step(dev, dict(g, grad_beta=g["grad_beta"].cpu()), 1e-3)
     with pytest.raises(ValueError):             # wrong dtype
-        plan.joint_step(dev, dict(g, grad_alpha=g["grad_alpha"].float()), 1e-3, step)
-    with pytest.raises(_lib.EpoError):          # null step counter, seen by the C side
+        plan.joint_step(dev, dict(g, grad_alpha=g["grad_alpha"].float()), 1e-3)
+    with pytest.raises(ValueError):             # step counts for fewer scenes
+        plan.joint_step(dict(dev, steps=dev["steps"][:1]), g, 1e-3)
+    with pytest.raises(_lib.EpoError):          # null step counts, seen by the C side
         _lib.joint_step(plan.handle, dev["gamma"], dev["alpha"], dev["beta"], dev["m_gamma"],
                         dev["v_gamma"], dev["m_depth"], dev["v_depth"], g["grad_gamma"],
                         g["grad_alpha"], g["grad_beta"],
@@ -172,12 +204,10 @@ def test_joint_step_views_without_edges(gpu):
     assert (V, n) == (6, 807)
     vor = plan.record_pixels()[:, 0]
     sv = np.asarray(plan.scene_of_view, np.int64)
-    host = {"gamma": rng.normal(0, 0.02, V), "alpha": (1 + rng.normal(0, 0.05, n)).astype(np.float32),
-            "beta": rng.normal(0, 0.05, n).astype(np.float32),
-            "m_gamma": np.zeros(V), "v_gamma": np.zeros(V)}
-    for k in ("alpha", "beta"):
-        host["m_" + k] = np.zeros(n)
-        host["v_" + k] = np.zeros(n)
+    host = oj.initial_state(V, n, plan.n_scenes)
+    host["gamma"] = rng.normal(0, 0.02, V)
+    host["alpha"] = (1 + rng.normal(0, 0.05, n)).astype(np.float32)
+    host["beta"] = rng.normal(0, 0.05, n).astype(np.float32)
     dev = plan.joint_state()
     for k in ("gamma", "alpha", "beta"):
         dev[k].copy_(torch.from_numpy(host[k]))
@@ -186,11 +216,10 @@ def test_joint_step_views_without_edges(gpu):
     want = host
     for s in range(2):
         g = grads_of(rng, V, n)
-        step = torch.tensor([s], dtype=torch.int32, device="cuda")
         plan.joint_step(dev, {k: torch.from_numpy(v).cuda() for k, v in g.items()},
-                        torch.from_numpy(lr).cuda(), step)
+                        torch.from_numpy(lr).cuda())
         after = {k: t.cpu().numpy() for k, t in plan.refine(poses, 10.0).items()}
-        prev, want = want, oj.joint_step(want, g, lr, sv, vor, s)
+        prev, want = want, oj.joint_step(want, g, lr, sv, vor)
         compare(dev, want, prev, g, n, f"empty views, step {s}")
         plan.set_refinement(dev["gamma"], dev["alpha"], dev["beta"])
         explicit = {k: t.cpu().numpy() for k, t in plan.refine(poses, 10.0).items()}

@@ -196,6 +196,53 @@ def test_refine_focal_vs_oracle_finite_differences(gpu):
     assert e < TOL
 
 
+def test_refine_autograd_interleaved_forwards(gpu):
+    """Two forwards at different refinements before either backward: each
+    backward gives the gradients at its own forward's gamma, alpha, beta
+    (bitwise those of a direct call there), whatever the plan holds when it
+    runs; changing the poses in place before backward raises."""
+    from paper_2607_00579_amd.api import EdgeRefineFn
+    p = problem("c1")
+    plan = plan_for(p)
+    P = torch.from_numpy(p.poses_init.copy()).cuda()
+    n, V = plan.n_records, p.n_views
+    vals = []
+    for k, (g0, a0, b0) in enumerate(((0.01, 1.0, 0.0), (-0.02, 1.03, 0.02))):
+        vals.append((torch.full((V,), g0, dtype=torch.float64, device="cuda", requires_grad=True),
+                     torch.full((n,), a0, dtype=torch.float32, device="cuda", requires_grad=True),
+                     torch.full((n,), b0, dtype=torch.float32, device="cuda", requires_grad=True),
+                     torch.zeros(V, 6, dtype=torch.float64, device="cuda", requires_grad=True)))
+    losses = [EdgeRefineFn.apply(xi, g, a, b, plan, P, 10.0) for g, a, b, xi in vals]
+    # the plan now holds the second refinement; run the first backward first
+    for (g, a, b, xi), loss in zip(vals, losses):
+        loss.sum().backward()
+    for g, a, b, xi in vals:
+        plan.set_refinement(g.detach(), a.detach(), b.detach())
+        ref = plan.refine(P, 10.0)
+        assert torch.equal(xi.grad, ref["grad"])
+        assert torch.equal(g.grad, ref["grad_gamma"])
+        assert torch.equal(a.grad, ref["grad_alpha"].float())
+        assert torch.equal(b.grad, ref["grad_beta"].float())
+    g, a, b, xi = vals[0]
+    Q = P.clone()
+    loss = EdgeRefineFn.apply(xi, g, a, b, plan, Q, 10.0)
+    Q.add_(1e-3)
+    with pytest.raises(RuntimeError):
+        loss.sum().backward()
+
+
+def test_cost_autograd_recompute_sees_in_place_pose_change(gpu):
+    from paper_2607_00579_amd.api import EdgeCostFn
+    p = problem("c1")
+    plan = plan_for(p)
+    Q = torch.from_numpy(p.poses_init.copy()).cuda()
+    xi = torch.zeros(p.n_views, 6, dtype=torch.float64, device="cuda", requires_grad=True)
+    loss = EdgeCostFn.apply(xi, plan, Q, 10.0, "recompute")
+    Q[0, 0, 3] += 1e-3
+    with pytest.raises(RuntimeError):
+        loss.sum().backward()
+
+
 @pytest.mark.parametrize("fmt", [2, 3])
 def test_depth_pass_stored_and_recomputed_forms_agree_bitwise(gpu, fmt):
     """Before the first refinement update the depth pass re-evaluates every

@@ -1,8 +1,10 @@
 """Oracle pins of the joint-phase optimizer step (focal scales gamma, depth
 scale alpha and shift beta; AdamW, paper Sec. 4 "Implementation Details"):
 against torch.optim.AdamW in float64 over several steps with one learning
-rate per scene, the first-step closed forms, and the phase gate of Alg.
-EPO.Forward (depth steps only in the joint phase, nothing after the stop)."""
+rate per scene, with the depth optimizer created at each scene's phase
+switch (Alg. EPO.Forward builds one optimizer per module and steps the depth
+one only in the joint phase), the first-step closed forms, and the phase
+gate (depth steps only in the joint phase, nothing after the stop)."""
 import numpy as np
 import torch
 
@@ -14,12 +16,10 @@ def make_case(seed=0, V=5, per_view=(3, 0, 4, 2, 5), n_scenes=2):
     sv = np.array([0, 0, 1, 1, 0][:V], np.int64) % n_scenes
     vor = np.repeat(np.arange(V), per_view)
     n = vor.size
-    state = {"gamma": rng.normal(0, 0.05, V), "alpha": (1 + rng.normal(0, 0.1, n)).astype(np.float32),
-             "beta": rng.normal(0, 0.1, n).astype(np.float32),
-             "m_gamma": np.zeros(V), "v_gamma": np.zeros(V)}
-    for k in ("alpha", "beta"):
-        state["m_" + k] = np.zeros(n)
-        state["v_" + k] = np.zeros(n)
+    state = oj.initial_state(V, n, n_scenes)
+    state["gamma"] = rng.normal(0, 0.05, V)
+    state["alpha"] = (1 + rng.normal(0, 0.1, n)).astype(np.float32)
+    state["beta"] = rng.normal(0, 0.1, n).astype(np.float32)
     return rng, sv, vor, state
 
 
@@ -29,9 +29,9 @@ def grads_of(rng, V, n):
 
 
 def test_matches_torch_adamw_per_scene_lr():
-    """Five steps, wd 0.01, learning rates 3e-3 and 1e-3 by scene: the
-    oracle (depth rounding off) against torch.optim.AdamW, one parameter group
-    per scene and parameter kind."""
+    """Five ungated steps, wd 0.01, learning rates 3e-3 and 1e-3 by scene:
+    the oracle (depth rounding off) against torch.optim.AdamW, one parameter
+    group per scene and parameter kind."""
     rng, sv, vor, state = make_case(seed=3)
     V, n = sv.size, vor.size
     lr = np.array([3e-3, 1e-3])
@@ -49,7 +49,7 @@ def test_matches_torch_adamw_per_scene_lr():
     st = {k: (np.asarray(v, np.float64) if k in ("alpha", "beta") else v) for k, v in state.items()}
     for step in range(5):
         g = grads_of(rng, V, n)
-        st = oj.joint_step(st, g, lr, sv, vor, step, round_depth=False)
+        st = oj.joint_step(st, g, lr, sv, vor, round_depth=False)
         for (name, s), (p, idx) in params.items():
             p.grad = torch.tensor(g["grad_" + name][idx], dtype=torch.float64)
         opt.step()
@@ -61,6 +61,126 @@ def test_matches_torch_adamw_per_scene_lr():
                                        atol=1e-20)
             np.testing.assert_allclose(st["v_" + name][idx], ts["exp_avg_sq"].numpy(),
                                        rtol=1e-13, atol=1e-24)
+    assert np.array_equal(st["steps"], np.full((2, 2), 5))
+
+
+def test_focal_optimizer_steps_until_the_stop():
+    """Three scenes over eight steps with per-step phases (scene 1 stops at
+    step 5) and learning rates changing every step: the focal scales against
+    one torch.optim.AdamW per scene, created at step 0 and stepped while the
+    scene has not stopped."""
+    rng = np.random.default_rng(21)
+    V, per_view = 6, (3, 2, 4, 1, 3, 2)
+    sv = np.array([0, 1, 2, 0, 1, 2])
+    vor = np.repeat(np.arange(V), per_view)
+    n = vor.size
+    st = oj.initial_state(V, n, 3)
+    st["gamma"] = rng.normal(0, 0.05, V)
+    phases = [[0, 0, 0], [0, 1, 0], [0, 1, 0], [1, 1, 0], [1, 1, 0], [1, 2, 0], [1, 2, 0],
+              [1, 2, 0]]
+    focal = {}
+    for s in range(3):
+        p = torch.tensor(st["gamma"][sv == s], dtype=torch.float64, requires_grad=True)
+        focal[s] = (p, torch.optim.AdamW([p], lr=1.0, betas=(0.9, 0.999), eps=1e-8,
+                                         weight_decay=0.01))
+    for k, ph in enumerate(phases):
+        lr = np.array([1e-3, 2e-3, 3e-3]) * (1.0 + 0.1 * k)
+        g = grads_of(rng, V, n)
+        st = oj.joint_step(st, g, lr, sv, vor, phase=ph, round_depth=False)
+        for s in range(3):
+            p, opt = focal[s]
+            if ph[s] != 2:
+                for grp in opt.param_groups:
+                    grp["lr"] = float(lr[s])
+                p.grad = torch.tensor(g["grad_gamma"][sv == s], dtype=torch.float64)
+                opt.step()
+            np.testing.assert_allclose(st["gamma"][sv == s], p.detach().numpy(), rtol=1e-13,
+                                       atol=1e-18, err_msg=f"step {k} scene {s} gamma")
+            np.testing.assert_allclose(st["m_gamma"][sv == s], opt.state[p]["exp_avg"].numpy(),
+                                       rtol=1e-13, atol=1e-20)
+            assert int(opt.state[p]["step"]) == st["steps"][0][s]
+
+
+def _depth_reference(phases, lr_of, grads, alpha0, beta0, sr):
+    """Per scene a torch AdamW over (alpha, beta) created at the first step
+    in phase 1 and stepped only in phase 1."""
+    out_a = np.asarray(alpha0, np.float64).copy()
+    out_b = np.asarray(beta0, np.float64).copy()
+    opts = {}
+    for k, ph in enumerate(phases):
+        for s, p in enumerate(ph):
+            if p != 1:
+                continue
+            idx = sr == s
+            if s not in opts:
+                pa = torch.tensor(out_a[idx], dtype=torch.float64, requires_grad=True)
+                pb = torch.tensor(out_b[idx], dtype=torch.float64, requires_grad=True)
+                opts[s] = (pa, pb, torch.optim.AdamW([pa, pb], lr=1.0, betas=(0.9, 0.999),
+                                                     eps=1e-8, weight_decay=0.01))
+            pa, pb, opt = opts[s]
+            for grp in opt.param_groups:
+                grp["lr"] = float(lr_of(k)[s])
+            pa.grad = torch.tensor(grads[k]["grad_alpha"][idx], dtype=torch.float64)
+            pb.grad = torch.tensor(grads[k]["grad_beta"][idx], dtype=torch.float64)
+            opt.step()
+            out_a[idx] = pa.detach().numpy()
+            out_b[idx] = pb.detach().numpy()
+    return out_a, out_b, {s: (o[2].state[o[0]], o[2].state[o[1]]) for s, o in opts.items()}
+
+
+def test_depth_optimizer_counts_from_the_switch():
+    """alpha and beta after eight steps with scenes switching to the joint
+    phase at steps 3 and 1 (and the second stopping at step 5) equal a
+    torch.optim.AdamW per scene created at the switch; their moments and the
+    oracle's depth step counts (5 and 4 steps) match the reference."""
+    rng = np.random.default_rng(22)
+    V, per_view = 6, (3, 2, 4, 1, 3, 2)
+    sv = np.array([0, 1, 2, 0, 1, 2])
+    vor = np.repeat(np.arange(V), per_view)
+    n = vor.size
+    sr = sv[vor]
+    st = oj.initial_state(V, n, 3)
+    st["alpha"] = (1 + rng.normal(0, 0.1, n))
+    st["beta"] = rng.normal(0, 0.1, n)
+    a0, b0 = st["alpha"].copy(), st["beta"].copy()
+    phases = [[0, 0, 0], [0, 1, 0], [0, 1, 0], [1, 1, 0], [1, 1, 0], [1, 2, 0], [1, 2, 0],
+              [1, 2, 0]]
+
+    def lr_of(k):
+        return np.array([1e-3, 2e-3, 3e-3]) * (1.0 + 0.1 * k)
+
+    grads = [grads_of(rng, V, n) for _ in phases]
+    for k, ph in enumerate(phases):
+        st = oj.joint_step(st, grads[k], lr_of(k), sv, vor, phase=ph, round_depth=False)
+    ra, rb, states = _depth_reference(phases, lr_of, grads, a0, b0, sr)
+    np.testing.assert_allclose(st["alpha"], ra, rtol=1e-13, atol=1e-16)
+    np.testing.assert_allclose(st["beta"], rb, rtol=1e-13, atol=1e-16)
+    for s, (sa, sb) in states.items():
+        idx = sr == s
+        np.testing.assert_allclose(st["m_alpha"][idx], sa["exp_avg"].numpy(), rtol=1e-13,
+                                   atol=1e-20)
+        np.testing.assert_allclose(st["v_beta"][idx], sb["exp_avg_sq"].numpy(), rtol=1e-13,
+                                   atol=1e-24)
+        assert int(sa["step"]) == st["steps"][1][s]
+    assert list(st["steps"][1]) == [5, 4, 0]
+    assert list(st["steps"][0]) == [8, 5, 8]
+    # scene 2 never switched: its depth parameters are untouched
+    assert np.array_equal(st["alpha"][sr == 2], a0[sr == 2])
+    # the reading matters: bias correction at the iteration count instead
+    # moves the first depth step of a late switch by more than 2x
+    late = oj.initial_state(V, n, 3)
+    late["steps"][:] = [[900, 900, 900], [0, 0, 0]]
+    early = oj.initial_state(V, n, 3)
+    early["steps"][:] = [[900, 900, 900], [900, 900, 900]]
+    g = grads_of(rng, V, n)
+    lr = np.full(3, 1e-3)
+    d_late = oj.joint_step(late, g, lr, sv, vor, phase=[1, 1, 1], round_depth=False,
+                           wd_depth=0.0)["beta"] - late["beta"]
+    d_early = oj.joint_step(early, g, lr, sv, vor, phase=[1, 1, 1], round_depth=False,
+                            wd_depth=0.0)["beta"] - early["beta"]
+    np.testing.assert_allclose(d_late, -lr[sr] * g["grad_beta"] / (np.abs(g["grad_beta"]) + 1e-8),
+                               rtol=1e-12)
+    assert np.all(np.abs(d_early) > 2.0 * np.abs(d_late))
 
 
 def test_first_step_closed_forms():
@@ -70,7 +190,7 @@ def test_first_step_closed_forms():
     V, n = sv.size, vor.size
     lr = np.array([2e-3, 5e-4])
     g = grads_of(rng, V, n)
-    out = oj.joint_step(state, g, lr, sv, vor, 0, wd_focal=0.0, wd_depth=0.0, round_depth=False)
+    out = oj.joint_step(state, g, lr, sv, vor, wd_focal=0.0, wd_depth=0.0, round_depth=False)
     gg = g["grad_gamma"]
     np.testing.assert_allclose(out["gamma"], state["gamma"] - lr[sv] * gg / (np.abs(gg) + 1e-8),
                                rtol=1e-15, atol=1e-18)
@@ -78,7 +198,7 @@ def test_first_step_closed_forms():
     want = state["alpha"].astype(np.float64) - lr[sv[vor]] * ga / (np.abs(ga) + 1e-8)
     np.testing.assert_allclose(out["alpha"], want, rtol=1e-15, atol=1e-18)
     zero = {k: np.zeros_like(v) for k, v in g.items()}
-    out = oj.joint_step(state, zero, lr, sv, vor, 0, wd_focal=0.01, wd_depth=0.1)
+    out = oj.joint_step(state, zero, lr, sv, vor, wd_focal=0.01, wd_depth=0.1)
     assert np.array_equal(out["gamma"], state["gamma"] * (1 - lr[sv] * 0.01))
     want = (state["beta"].astype(np.float64) * (1 - lr[sv[vor]] * 0.1)).astype(np.float32)
     assert np.array_equal(out["beta"], want)
@@ -88,16 +208,16 @@ def test_first_step_closed_forms():
 
 def test_phase_gate():
     """Scene phases (0, 1, 2): phase 0 moves gamma only, phase 1 moves
-    everything, phase 2 nothing; gated values and moments stay bitwise."""
+    everything, phase 2 nothing; gated values, moments and step counts stay
+    bitwise."""
     rng, sv, vor, state = make_case(seed=7, V=6, per_view=(2, 3, 1, 4, 2, 3), n_scenes=3)
     sv = np.array([0, 1, 2, 0, 1, 2])
     V, n = sv.size, vor.size
     lr = np.array([1e-3, 2e-3, 3e-3])
     g = grads_of(rng, V, n)
-    s1 = oj.joint_step(state, g, lr, sv, vor, 0)
-    s1 = oj.joint_step(s1, grads_of(rng, V, n), lr, sv, vor, 1)
-    out = oj.joint_step(s1, grads_of(rng, V, n), lr, sv, vor, 2, phase=[0, 1, 2])
-    ref = oj.joint_step(s1, grads_of(np.random.default_rng(99), V, n), lr, sv, vor, 2)
+    s1 = oj.joint_step(state, g, lr, sv, vor)
+    s1 = oj.joint_step(s1, grads_of(rng, V, n), lr, sv, vor)
+    out = oj.joint_step(s1, grads_of(rng, V, n), lr, sv, vor, phase=[0, 1, 2])
     sr = sv[vor]
     for k in ("gamma", "m_gamma", "v_gamma"):
         assert np.array_equal(out[k][sv == 2], s1[k][sv == 2]), k
@@ -105,4 +225,5 @@ def test_phase_gate():
     for k in ("alpha", "beta", "m_alpha", "v_alpha", "m_beta", "v_beta"):
         assert np.array_equal(out[k][sr != 1], s1[k][sr != 1]), k
         assert not np.any(out[k][sr == 1] == s1[k][sr == 1]), k
-    assert ref["gamma"].shape == out["gamma"].shape
+    assert list(out["steps"][0]) == [3, 3, 2]
+    assert list(out["steps"][1]) == [2, 3, 2]
