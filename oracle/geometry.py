@@ -14,9 +14,10 @@ for the rotation and the left Jacobian V(omega) for the translation,
 
 with Taylor expansions below th = 1e-4.  Log is its inverse (tests only).
 
-Pins: Exp(Log T) = T on random poses, Rodrigues against the matrix
-exponential of the twist (scipy.linalg.expm), pure translations, continuity of
-the small-angle branch.
+Pins: Exp(Log T) = T on random poses and at angles within 1e-6 of pi (the
+near-pi branch of Log), Rodrigues against the matrix exponential of the
+twist (scipy.linalg.expm), pure translations, continuity of the small-angle
+branch.
 """
 from __future__ import annotations
 
@@ -54,18 +55,27 @@ def se3_exp(xi: np.ndarray) -> np.ndarray:
 
 
 def so3_log(R: np.ndarray) -> np.ndarray:
-    cos = np.clip((np.trace(R) - 1.0) / 2.0, -1.0, 1.0)
-    th = float(np.arccos(cos))
+    # the angle from both parts of R = I + sin(th) [n]x + (1 - cos th) [n]x^2:
+    # (trace - 1)/2 = cos th and the antisymmetric part's vee = 2 sin(th) n,
+    # so atan2 keeps full precision near 0 and near pi (arccos alone loses
+    # half the digits there)
+    anti = np.array([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]])
+    th = float(np.arctan2(0.5 * np.linalg.norm(anti), (np.trace(R) - 1.0) / 2.0))
     if th < SMALL:
-        return 0.5 * np.array([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0], R[1, 0] - R[0, 1]])
+        return 0.5 * anti
     if np.pi - th < 1e-6:
-        # near pi: axis from the symmetric part
-        M = (R + np.eye(3)) / 2.0
+        # near pi the antisymmetric part sin(th) [n]x vanishes: the axis up
+        # to its sign comes from the symmetric part, (R + R^T)/4 + I/2 =
+        # n n^T + O((pi - th)^2), the column of its largest diagonal entry;
+        # the sign is that of the (small) antisymmetric part, either sign at
+        # exactly pi
+        M = ((R + R.T) / 2.0 + np.eye(3)) / 2.0
         k = int(np.argmax(np.diag(M)))
-        axis = M[:, k] / np.sqrt(M[k, k])
-        return th * axis / np.linalg.norm(axis)
-    return th / (2.0 * np.sin(th)) * np.array([R[2, 1] - R[1, 2], R[0, 2] - R[2, 0],
-                                               R[1, 0] - R[0, 1]])
+        axis = M[:, k] / np.linalg.norm(M[:, k])
+        if axis @ anti < 0.0:
+            axis = -axis
+        return th * axis
+    return th / (2.0 * np.sin(th)) * anti
 
 
 def se3_log(T: np.ndarray) -> np.ndarray:
