@@ -567,11 +567,25 @@ EPO_API epo_status epo_plan_set_options(epo_plan plan, const epo_plan_options* o
 EPO_API epo_status epo_get_device_status(epo_plan plan, int32_t* flags, void* stream);
 
 /* Duration in milliseconds of the fused cost+adjoint kernel in the most recent
- * epo_edge_cost_fwd / epo_edge_cost_bwd / iteration replay, measured with HIP
- * events recorded around that kernel on the stream it ran on.  Synchronises
- * on the end event.  Requires epo_plan_enable_timing(plan, 1) beforehand. */
+ * eager epo_edge_cost_fwd / epo_edge_cost_bwd / epo_edge_cost_refine call,
+ * measured with HIP events recorded around that kernel on the stream it ran
+ * on.  Synchronises on the end event.  Requires epo_plan_enable_timing(plan,
+ * 1) beforehand.  A captured iteration records no events (its replays are not
+ * timed by this). */
 EPO_API epo_status epo_plan_enable_timing(epo_plan plan, int32_t enable);
 EPO_API epo_status epo_plan_last_kernel_ms(epo_plan plan, float* ms);
+
+/* Mean duration in milliseconds (*ms, host) of the fused cost+adjoint kernel
+ * of the plan's current schedule: the pair descriptors are set up once at
+ * `poses` and `lambda` (device, as for epo_edge_cost_fwd), then the kernel is
+ * launched `reps` times back to back on `stream` between two HIP events; the
+ * elapsed time over reps is the per-launch mean, with no other kernel between
+ * the launches.  Overwrites the plan's per-tile partial sums (call
+ * epo_edge_cost_fwd again before reading per-pair results).  Creates two
+ * events and synchronises.  Errors: EPO_ERR_INVALID_ARG for a null argument or
+ * reps outside [1, 100000]. */
+EPO_API epo_status epo_plan_time_kernel(epo_plan plan, const double* poses, const float* lambda,
+                                        int32_t reps, float* ms, void* stream);
 
 /* Thread-local description of the last error (empty string if none). */
 EPO_API const char* epo_last_error(void);

@@ -214,13 +214,18 @@ class OracleProblem:
         return L, w, scale
 
     def evaluate(self, poses: np.ndarray, lam, params: CostParams = CostParams(),
-                 frozen=None, pair_ids=None, K=None, depth=None, selected=None):
+                 frozen=None, pair_ids=None, K=None, depth=None, selected=None,
+                 pair_results=None):
         """Loss per scene, per-pair S, n, L_d, G, the gradient per view, the
         focal-scale gradient per view (grad_focal) and the depth gradient of
         every edge pixel (grad_depth: {view: array in edge-pixel order}).
         `selected` (boolean mask over directed pairs) evaluates one
         sub-sampled step: only those pairs, each scene's loss the mean over
-        its selected pairs."""
+        its selected pairs.  `pair_results` ({d: the sums direction() returns
+        for pair d at these arguments}) supplies the per-pair sums computed
+        elsewhere (worker processes); they are combined here in the same
+        order, so the result is the same bits (without grad_depth unless the
+        results carry dZ)."""
         lam = np.broadcast_to(np.asarray(lam, np.float64), (self.n_scenes,))
         D = self.pairs.shape[0]
         ids = range(D) if pair_ids is None else pair_ids
@@ -237,13 +242,16 @@ class OracleProblem:
         decisions = {}
         for d in ids:
             s = int(self.scene_of_pair[d])
-            r = self.direction(d, poses, float(lam[s]), params,
-                               frozen=None if frozen is None else frozen[d], K=K, depth=depth)
+            if pair_results is not None:
+                r = pair_results[d]
+            else:
+                r = self.direction(d, poses, float(lam[s]), params,
+                                   frozen=None if frozen is None else frozen[d], K=K, depth=depth)
             S[d], n[d], n_src[d] = r["S"], r["n"], r["n_src"]
             G_tgt[d], G_src[d] = r["G_tgt"], r["G_src"]
             F_tgt[d], F_src[d] = r["F_tgt"], r["F_src"]
-            dZ[d] = r["dZ"]
-            decisions[d] = r["decisions"]
+            dZ[d] = r.get("dZ")
+            decisions[d] = r.get("decisions")
         L, w, scale = self.weights(S, n, n_src, params, selected)
         loss = np.zeros(self.n_scenes)
         grad = np.zeros((self.V, 6))
@@ -257,6 +265,8 @@ class OracleProblem:
             grad[i] += w[d] * G_src[d]
             grad_focal[j] += w[d] * F_tgt[d]
             grad_focal[i] += w[d] * F_src[d]
+            if dZ[d] is None:
+                continue
             if i not in grad_depth:
                 grad_depth[i] = np.zeros(self.pts[i][0].size)
             grad_depth[i] += w[d] * dZ[d]

@@ -63,14 +63,16 @@ def adam_se3_step(poses, m, v, g, step: int, lr, b1=0.9, b2=0.999, eps=1e-8, fix
 
 def run(op: OracleProblem, poses0: np.ndarray, n_iters: int, params: CostParams = CostParams(),
         fixed=None, start_step: int = 0, record_every: int = 1, m0=None, v0=None,
-        sampling=None):
+        sampling=None, evaluate=None):
     """The optimisation loop: for s = start .. start + n - 1 evaluate lambda(s)
     and lr(s), the loss and the gradient at the current poses, then step.
     Recorded per iteration: the loss, the gradient norm, and the state the
     iteration starts from (poses and Adam moments).  `sampling = (seed, M)`
     evaluates each step on the fresh pair subset of that step (stochastic
-    viewgraph sub-sampling)."""
+    viewgraph sub-sampling).  `evaluate` replaces op.evaluate (same
+    arguments and result; a process-parallel form of it)."""
     from .sampling import selected_pairs
+    evaluate = op.evaluate if evaluate is None else evaluate
     poses = poses0.copy()
     m = np.zeros((op.V, 6)) if m0 is None else m0.copy()
     v = np.zeros((op.V, 6)) if v0 is None else v0.copy()
@@ -79,7 +81,7 @@ def run(op: OracleProblem, poses0: np.ndarray, n_iters: int, params: CostParams 
         sel = None
         if sampling is not None:
             sel = selected_pairs(op.pairs, op.scene_of_pair, sampling[0], s, sampling[1])
-        r = op.evaluate(poses, clamp_lambda(s), params, selected=sel)
+        r = evaluate(poses, clamp_lambda(s), params, selected=sel)
         if (s - start_step) % record_every == 0:
             hist["loss"].append(r["loss"].copy())
             hist["grad_norm"].append(float(np.linalg.norm(r["grad"])))

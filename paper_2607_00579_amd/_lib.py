@@ -76,6 +76,7 @@ _SIGS = {
     "epo_get_device_status": [P, P, P],
     "epo_plan_enable_timing": [P, I32],
     "epo_plan_last_kernel_ms": [P, P],
+    "epo_plan_time_kernel": [P, P, P, I32, P, P],
 }
 EXPORTS = sorted(list(_SIGS) + ["epo_last_error", "epo_version"])
 
@@ -313,6 +314,13 @@ def get_device_status(plan, stream) -> int:
 
 def plan_enable_timing(plan, enable: bool):
     _check(load().epo_plan_enable_timing(plan, 1 if enable else 0))
+
+
+def plan_time_kernel(plan, poses, lam, reps: int, stream) -> float:
+    ms = C.c_float(0.0)
+    _check(load().epo_plan_time_kernel(plan, _ptr(poses), _ptr(lam), int(reps), C.byref(ms),
+                                       stream))
+    return float(ms.value)
 
 
 def plan_last_kernel_ms(plan) -> float:

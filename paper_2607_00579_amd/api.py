@@ -341,6 +341,12 @@ class EdgePlan:
     def last_kernel_ms(self) -> float:
         return _lib.plan_last_kernel_ms(self.handle)
 
+    def time_kernel(self, poses, lam, reps=20) -> float:
+        """Mean duration (ms) of the fused kernel over `reps` back-to-back
+        launches at these poses (HIP events on the current stream)."""
+        return _lib.plan_time_kernel(self.handle, poses, self.lam_tensor(lam), reps,
+                                     _stream(self.device))
+
 
 class EdgeCostFn(torch.autograd.Function):
     """loss[s] of every scene as a differentiable function of left twists xi

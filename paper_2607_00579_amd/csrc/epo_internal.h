@@ -63,6 +63,8 @@ epo_status guarded(F&& f) {
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// ==== data layout read by the fused kernel: begin (the fused kernel's
+// measured counters are keyed to this section's text)
 // pixel blocks of the u8 quad texture (8 x 4 texels of 4 bytes = 128 bytes)
 constexpr int kQuadBlockW = 8;
 constexpr int kQuadBlockH = 4;
@@ -138,6 +140,7 @@ struct Tile {
 struct alignas(64) Partial {
     double v[8];
 };
+// ==== data layout read by the fused kernel: end
 
 // per-scene convergence state (pose-change signal history and phase)
 constexpr int kConvRing = 128;          // >= 2 w - 1 for windows up to 64

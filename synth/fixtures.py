@@ -87,3 +87,24 @@ def odd_size_views(seed: int = 0, density: float = 0.15):
     n = len(sizes)
     pairs = [(i, j) for i in range(n) for j in range(n) if i != j]
     return problem_from_maps(Ws, Hs, Ks, E, Z, P, pairs, name="odd_sizes")
+
+
+def camera_inside(seed: int = 5):
+    """Residuals behind the target camera: the two views of the small
+    wireframe workload plus a third camera placed inside the wireframe (near
+    the centre of the cube, looking along a seeded random direction), which
+    sees the third view's maps of the second view.  Pairs 0 -> 2 and 1 -> 2
+    put about half of the source points behind camera 2 (z <= 0) and others
+    just in front of it; 2 -> 0, 2 -> 1 and 0 -> 1 are ordinary."""
+    from .scenes import config_c1, look_at
+    p = config_c1()
+    rng = np.random.default_rng(seed)
+    d = rng.normal(size=3)
+    d /= np.linalg.norm(d)
+    c = 0.05 * rng.normal(size=3)
+    P2 = look_at(c, c + d)
+    poses = np.concatenate([p.poses_init, P2[None]], axis=0)
+    idx = [0, 1, 1]
+    return problem_from_maps(p.width[idx], p.height[idx], p.K[idx],
+                             [p.edge_map(v) for v in idx], [p.depth_map(v) for v in idx], poses,
+                             [[0, 2], [1, 2], [2, 0], [2, 1], [0, 1]], name="camera_inside")

@@ -46,3 +46,42 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_kernel_hash_covers_only_the_fused_kernels_device_code(tmp_path, monkeypatch):
+    """Host-side edits (the launch code, the plan structure) keep the committed
+    counters valid; edits of the kernel's device code or of the data layout it
+    reads invalidate them."""
+    import shutil
+    src = os.path.join(ROOT, "paper_2607_00579_amd", "csrc")
+    dst = tmp_path / "paper_2607_00579_amd" / "csrc"
+    shutil.copytree(src, dst)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.kernel_source_hash()
+
+    def edit(name, old, new):
+        p = dst / name
+        text = p.read_text()
+        assert old in text
+        p.write_text(text.replace(old, new, 1))
+
+    edit("edge_cost.hip", "namespace epo {", "namespace epo {\n// host-side note")
+    edit("epo_internal.h", "struct Plan {", "// plan note\nstruct Plan {")
+    assert bench.kernel_source_hash() == h0
+    edit("epo_internal.h", "struct Tile {", "// layout note\nstruct Tile {")
+    h1 = bench.kernel_source_hash()
+    assert h1 != h0
+    edit("fused_kernel.h", "namespace fused {", "namespace fused {\n// kernel note")
+    assert bench.kernel_source_hash() not in (h0, h1)
+
+
+def test_cpu_baseline_reports_the_host(monkeypatch):
+    """The oracle baseline on the host's cores: a positive rate, the worker
+    count as cores, and the host description (core count, CPU model, NumPy)."""
+    from synth import make
+    r = bench.cpu_baseline(make("c1"), budget_s=0.5)
+    assert r["kind"] == "oracle" and r["value"] > 0
+    assert 1 <= r["cores"] <= 16
+    for k in ("nproc", "affinity", "cpu_model", "numpy"):
+        assert r["host"][k], k
+    assert "directed pairs" in r["sample"]

@@ -84,6 +84,33 @@ def test_zero_cost_dilated_projection_map(gpu):
     assert np.all(g["grad"] == 0.0)
 
 
+@pytest.mark.parametrize("zmin", [1e-4, 0.3])
+@pytest.mark.parametrize("fmt", [1, 2, 3])
+def test_residuals_behind_the_target_camera(gpu, zmin, fmt):
+    """A camera inside the wireframe: hundreds of residuals of the pairs into
+    it lie behind it (some of whose negative-depth projections fall inside
+    the image) or just in front of it.  Per pair, the valid counts equal the
+    oracle's exactly, and L_d, the target gradient sums G_d and the pose
+    gradients agree within the bar, with the validity test on z and the
+    clamped reciprocal of z both exercised (z_min = 0.3 moves the test)."""
+    q = fixtures.camera_inside()
+    params = ocost.CostParams(z_min=zmin)
+    plan = plan_for(q, z_min=zmin, options=dict(texture_format=fmt, points_per_thread=4,
+                                                 tile_order=1, persistent=2))
+    g = gpu_eval(plan, q.poses_init, 10.0)
+    r = ocost.OracleProblem(q).evaluate(q.poses_init, 10.0, params)
+    say(f"camera inside, z_min {zmin}, format {fmt}: valid {g['pair_valid']} (oracle {r['n']})")
+    assert np.array_equal(g["pair_valid"], r["n"])
+    ok = r["n"] > 0
+    assert np.allclose(g["pair_cost"][ok], r["L"][ok], rtol=TOL, atol=0)
+    for d in np.flatnonzero(ok):
+        assert np.linalg.norm(g["pair_grad"][d] - r["G_tgt"][d]) <= \
+            TOL * np.linalg.norm(r["G_tgt"][d]), d
+    assert rel_norm_err(g["loss"], r["loss"]) < TOL
+    assert rel_norm_err(g["grad"], r["grad"], axis=1) < TOL
+    assert plan.device_status() == 0
+
+
 @pytest.mark.parametrize("name", ["c1", "c2"])
 @pytest.mark.parametrize("lam", [10.0, 3.0])
 def test_cost_and_gradient_vs_oracle(gpu, name, lam):

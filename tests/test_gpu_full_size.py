@@ -8,29 +8,35 @@ import pytest
 import torch
 
 from oracle import cost as ocost
-from oracle import edt as oedt
 from tests.gpu_helpers import check_depth, problem, rel_norm_err, say
 
 pytestmark = pytest.mark.gpu
 
 
-def sample_pairs(prob, n, rng, max_px=None):
-    """Pairs spread over scenes; targets limited to images of at most max_px
-    pixels (the oracle's distance transform is O(W^2 H) per view)."""
-    ok = np.ones(prob.n_pairs, bool)
-    if max_px is not None:
-        px = prob.width.astype(np.int64) * prob.height
-        ok &= px[prob.pairs[:, 1]] <= max_px
-    cand = np.flatnonzero(ok)
-    return np.sort(rng.choice(cand, size=min(n, cand.size), replace=False))
+def sample_pairs(prob, n, rng):
+    """n pairs spread over scenes, the same number for every target
+    resolution of the workload (256 x 192 up to 1024 x 768 for the batch)."""
+    px = prob.width.astype(np.int64) * prob.height
+    tpx = px[prob.pairs[:, 1]]
+    sizes = np.unique(tpx)
+    per = int(np.ceil(n / sizes.size))
+    out = []
+    for sz in sizes:
+        cand = np.flatnonzero(tpx == sz)
+        out.append(rng.choice(cand, size=min(per, cand.size), replace=False))
+    return np.sort(np.concatenate(out))
 
 
 def check_pairs(prob, plan, pair_ids, lam=10.0):
+    from oracle import parallel as opar
     poses = torch.from_numpy(prob.poses_init.copy()).cuda()
     o = plan.cost(poses, lam, grad=True, pairs=True)
     g = {k: v.cpu().numpy() for k, v in o.items()}
     views = sorted(set(prob.pairs[pair_ids].ravel().tolist()))
-    op = ocost.OracleProblem(prob, views=views)
+    # the oracle's own distance transforms of the views involved, in fresh
+    # worker processes (this one holds a GPU context)
+    d2 = opar.distance_fields(prob, views=views, context="spawn")
+    op = ocost.OracleProblem(prob, d2=d2, views=views)
     worst_L, worst_G, dn_max = 0.0, 0.0, 0
     for d in pair_ids:
         r = op.direction(int(d), prob.poses_init, lam, ocost.CostParams())
@@ -44,18 +50,25 @@ def check_pairs(prob, plan, pair_ids, lam=10.0):
     return worst_L, worst_G, dn_max, g
 
 
-@pytest.mark.parametrize("name,n_pairs,max_px", [("c4", 60, 518 * 392), ("c5", 12, None)])
-def test_full_size_sampled_pairs(gpu, name, n_pairs, max_px):
+@pytest.mark.parametrize("name,n_pairs", [("c4", 64), ("c5", 12)])
+def test_full_size_sampled_pairs(gpu, name, n_pairs):
+    """Sampled pairs of the full workloads in the benchmark's launch
+    configuration; for the batch, 16 pairs into targets of each of its four
+    resolutions."""
     from paper_2607_00579_amd.api import EdgePlan
     prob = problem(name)
     plan = EdgePlan.from_problem(prob)
     poses = torch.from_numpy(prob.poses_init.copy()).cuda()
     chosen = plan.autotune(poses, 10.0, iters=1)
     rng = np.random.default_rng(11)
-    ids = sample_pairs(prob, n_pairs, rng, max_px)
+    ids = sample_pairs(prob, n_pairs, rng)
+    tres = sorted({(int(prob.width[j]), int(prob.height[j])) for j in prob.pairs[ids, 1]})
+    if name == "c4":
+        assert len(tres) == 4, tres
     worst_L, worst_G, dn, g = check_pairs(prob, plan, ids)
-    say(f"{name} ({plan.n_residuals} residuals, schedule {chosen}): {ids.size} sampled pairs, "
-        f"max |dn| {dn}, worst L_d rel err {worst_L:.2e}, worst G_d rel err {worst_G:.2e}")
+    say(f"{name} ({plan.n_residuals} residuals, schedule {chosen}): {ids.size} sampled pairs "
+        f"into targets of {tres}, max |dn| {dn}, worst L_d rel err {worst_L:.2e}, "
+        f"worst G_d rel err {worst_G:.2e}")
     assert dn == 0
     assert worst_L < 1e-5
     assert worst_G < 1e-4
@@ -103,10 +116,13 @@ def test_full_size_graph_equals_eager_c4(gpu):
     assert int(s2.item()) == 2
 
 
-@pytest.mark.parametrize("name,n_views", [("c4", 6), ("c5", 2)])
-def test_full_size_edt_sampled(gpu, name, n_views):
-    """Whole views bit-exact against the oracle's separable transform (smaller
-    views), and 4000 random pixels per view by brute force on the largest."""
+@pytest.mark.parametrize("name,per_size", [("c4", 2), ("c5", 6)])
+def test_full_size_edt_sampled(gpu, name, per_size):
+    """Whole views bit-exact against the oracle's separable transform (for the
+    batch, `per_size` views of each of its four resolutions; for the large
+    scene six 1024 x 768 views), and 4000 random pixels per view by brute
+    force on the largest view and a random one."""
+    from oracle import parallel as opar
     from paper_2607_00579_amd.api import build_distance_fields
     prob = problem(name)
     e = torch.from_numpy(prob.edge_flat).cuda()
@@ -114,12 +130,15 @@ def test_full_size_edt_sampled(gpu, name, n_views):
     d2 = d2.cpu().numpy()
     rng = np.random.default_rng(5)
     px = prob.width.astype(np.int64) * prob.height
-    small = np.flatnonzero(px <= 518 * 392)
-    views = list(rng.choice(small, size=min(n_views, small.size), replace=False)) if small.size else []
+    views = []
+    for sz in np.unique(px):
+        cand = np.flatnonzero(px == sz)
+        views += [int(v) for v in rng.choice(cand, size=min(per_size, cand.size), replace=False)]
+    want = opar.distance_fields(prob, views=views, context="spawn")
     for v in views:
         a, b = prob.view_offset[v], prob.view_offset[v + 1]
         got = d2[a:b].reshape(prob.height[v], prob.width[v])
-        assert np.array_equal(got, oedt.edt_separable(prob.edge_map(v))), v
+        assert np.array_equal(got, want[v]), v
     big = int(np.argmax(px))
     for v in {big, int(rng.integers(prob.n_views))}:
         m = prob.edge_map(v)

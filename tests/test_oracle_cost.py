@@ -251,3 +251,32 @@ def test_depth_gradient_of_a_pure_translation_fixture():
     r = cost.OracleProblem(p).evaluate(p.poses_init, 10.0)
     assert np.all(r["grad_focal"] == 0.0)
     assert all(np.all(g == 0.0) for g in r["grad_depth"].values())
+
+
+def test_camera_inside_fixture_has_residuals_behind_the_camera():
+    """The behind-camera fixture (a camera inside the wireframe) holds, for
+    both pairs into it, residuals behind the camera whose projections with
+    the negative depth would land inside the image, and residuals just in
+    front of it (0 < z <= 0.3) inside the image: only the depth test decides
+    them, and the oracle drops both kinds at z_min = 0.3."""
+    q = fixtures.camera_inside()
+    op = cost.OracleProblem(q)
+    for d in (0, 1):
+        i, j = (int(x) for x in q.pairs[d])
+        u, v, Z = op.pts[i]
+        fx, fy, cx, cy = op.K[i]
+        Xc = np.stack([(u - cx) / fx * Z, (v - cy) / fy * Z, Z], 1)
+        Pi, Pj = q.poses_init[i], q.poses_init[j]
+        Xp = ((Xc - Pi[:, 3]) @ Pi[:, :3]) @ Pj[:, :3].T + Pj[:, 3]
+        z = Xp[:, 2]
+        fxj, fyj, cxj, cyj = op.K[j]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            up = fxj * Xp[:, 0] / z + cxj
+            vp = fyj * Xp[:, 1] / z + cyj
+        inb = (up >= 0) & (up < op.W[j] - 1) & (vp >= 0) & (vp < op.H[j] - 1)
+        assert ((z <= 0) & inb).sum() >= 30
+        assert ((z > 0) & (z <= 0.3) & inb).sum() >= 20
+        for zmin in (1e-4, 0.3):
+            r = op.direction(d, q.poses_init, 10.0, cost.CostParams(z_min=zmin),
+                             per_residual=True)
+            assert r["n"] == int(((z > zmin) & inb).sum())
