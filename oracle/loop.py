@@ -16,8 +16,20 @@ Test infrastructure only (see the package header).
       P <- Exp(step) P;
     poses in `fixed` skip both the moment update and the step.
 
+The joint loop (run_joint) adds the focal and depth refinement of Sec. 3
+"Camera Refinement" / "Depth Refinement" to the loop of Alg. 2: each step
+evaluates the cost at the refined intrinsics f = f0 (1 + gamma) and edge
+depths Z = Z0 alpha + beta (each formed in float64 and rounded to float32
+once: the paper's FP32 parameters), then the joint-phase AdamW step of
+oracle.joint (gamma in both phases, alpha and beta in the joint phase only,
+each with its own step count), the Adam twist step and the dual-phase test.
+
 Pins: first Adam step equals -lr g/(|g| + eps) componentwise (closed form),
-zero gradient leaves poses unchanged.
+zero gradient leaves poses unchanged; the joint loop on the exact-zero
+fixture takes pure weight-decay steps (closed form), its focal and depth
+gradients against central differences of the loss in gamma, alpha and beta,
+and its depth parameters stay put until their scene's switch, whose first
+depth step is the closed form.
 """
 from __future__ import annotations
 
@@ -187,4 +199,102 @@ def run_mlp(op: OracleProblem, P0: np.ndarray, theta0: np.ndarray, n_iters: int,
         poses = new
     hist["final_poses"] = poses
     hist["params"], hist["delta"] = theta, delta
+    return hist
+
+
+def joint_refinement(op: OracleProblem, gamma, alpha, beta, rounded: bool = True):
+    """Intrinsics and edge depths the cost sees under the refinement (gamma
+    per view; alpha, beta per edge pixel in the oracle's order: views in
+    order, each view's edge pixels row-major): f = f0 (1 + gamma) and
+    Z = Z0 alpha + beta in float64, rounded to float32 unless `rounded` is
+    False (used by finite differences)."""
+    K = op.K.copy()
+    f = op.K[:, :2] * (1.0 + np.asarray(gamma, np.float64))[:, None]
+    K[:, :2] = f.astype(np.float32) if rounded else f
+    depth = {}
+    o = 0
+    for v in range(op.V):
+        z0 = op.pts[v][2]
+        n = z0.size
+        z = z0 * np.asarray(alpha[o:o + n], np.float64) + np.asarray(beta[o:o + n], np.float64)
+        depth[v] = z.astype(np.float32).astype(np.float64) if rounded else z
+        o += n
+    return K, depth
+
+
+def record_views(op: OracleProblem) -> np.ndarray:
+    """View of every edge pixel in the oracle's order."""
+    return np.concatenate([np.full(op.pts[v][0].size, v, np.int64) for v in range(op.V)])
+
+
+def joint_gradients(op: OracleProblem, r, gamma):
+    """dL/dgamma, dL/dalpha, dL/dbeta from an evaluation at the refined state:
+    f dL/df per view (the cost's focal term) times f0/f = 1/(1 + gamma), and
+    by Z = Z0 alpha + beta, dL/dbeta = dL/dZ and dL/dalpha = Z0 dL/dZ."""
+    gz = np.concatenate([r["grad_depth"].get(v, np.zeros(op.pts[v][0].size))
+                         for v in range(op.V)])
+    z0 = np.concatenate([op.pts[v][2] for v in range(op.V)])
+    return {"grad_gamma": r["grad_focal"] / (1.0 + np.asarray(gamma, np.float64)),
+            "grad_alpha": z0 * gz, "grad_beta": gz}
+
+
+def joint_loop_step(op: OracleProblem, s: int, poses, m, v, jstate, phase=None,
+                    params: CostParams = CostParams(), wd_focal=0.01, wd_depth=0.01,
+                    b1=0.9, b2=0.999, eps=1e-8):
+    """Step s of the joint loop from the given state.  `phase` (per scene:
+    0 pose phase, 1 joint phase, 2 stopped) gates the step as in Alg. 2:
+    a stopped scene's learning rate is 0, the focal scales step unless it
+    stopped, the depth parameters only in the joint phase; None steps every
+    parameter.  Returns the new poses, moments, joint state and the
+    evaluation."""
+    from . import joint
+    S = op.n_scenes
+    ph = None if phase is None else np.asarray(phase)
+    lr = np.array([0.0 if (ph is not None and ph[k] == 2) else learning_rate(s) for k in range(S)])
+    K, depth = joint_refinement(op, jstate["gamma"], jstate["alpha"], jstate["beta"])
+    r = op.evaluate(poses, clamp_lambda(s), params, K=K, depth=depth)
+    g = joint_gradients(op, r, jstate["gamma"])
+    jstate = joint.joint_step(jstate, g, lr, op.scene_of_view, record_views(op), phase=ph,
+                              b1=b1, b2=b2, eps=eps, wd_focal=wd_focal, wd_depth=wd_depth)
+    new, m, v = adam_se3_step(poses, m, v, r["grad"], s + 1, lr, b1, b2, eps,
+                              scene_of_view=op.scene_of_view)
+    return new, m, v, jstate, r
+
+
+def run_joint(op: OracleProblem, poses0: np.ndarray, n_iters: int,
+              params: CostParams = CostParams(), convergence=(25, 0.5, 50, 0.1),
+              wd_focal=0.01, wd_depth=0.01):
+    """The two-phase loop of Alg. 2 with focal and depth refinement: per step
+    the phase of each scene at the start of the step gates that step
+    (joint_loop_step), then theta_95 of the scene's pose change updates its
+    dual-phase test.  convergence=None steps every parameter from step 0 with
+    no test."""
+    from . import joint
+    from .convergence import DualPhase, theta95
+    poses = poses0.copy()
+    m = np.zeros((op.V, 6))
+    v = np.zeros((op.V, 6))
+    n_rec = sum(op.pts[k][0].size for k in range(op.V))
+    jstate = joint.initial_state(op.V, n_rec, op.n_scenes)
+    dual = [DualPhase(*convergence) for _ in range(op.n_scenes)] if convergence else None
+    hist = dict(loss=[], theta=[], phase=[], gamma=[])
+    for s in range(n_iters):
+        phase = [d.phase for d in dual] if dual else None
+        new, m, v, jstate, r = joint_loop_step(op, s, poses, m, v, jstate, phase, params,
+                                               wd_focal, wd_depth)
+        hist["loss"].append(r["loss"].copy())
+        hist["gamma"].append(jstate["gamma"].copy())
+        if dual:
+            th = []
+            for k, d in enumerate(dual):
+                views = np.flatnonzero(op.scene_of_view == k)
+                t = theta95(new[views], poses[views])
+                d.update(t)
+                th.append(t)
+            hist["theta"].append(th)
+            hist["phase"].append([d.phase for d in dual])
+        poses = new
+    hist["final_poses"] = poses
+    hist["m"], hist["v"], hist["joint"] = m, v, jstate
+    hist["switch_steps"] = [list(d.switch_step) for d in dual] if dual else None
     return hist

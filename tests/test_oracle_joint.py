@@ -227,3 +227,101 @@ def test_phase_gate():
         assert not np.any(out[k][sr == 1] == s1[k][sr == 1]), k
     assert list(out["steps"][0]) == [3, 3, 2]
     assert list(out["steps"][1]) == [2, 3, 2]
+
+
+def test_joint_loop_first_step_on_the_zero_fixture():
+    """Exact-zero fixture (shifted edges, loss and every gradient exactly 0):
+    the joint loop's first step, everything ungated, is pure weight decay:
+    the poses and gamma stay (0 decays to 0), alpha becomes float32(1 - lr(0)
+    wd), beta stays 0, the moments stay 0 and both step counts advance."""
+    from oracle import cost, loop
+    from synth import fixtures
+    p = fixtures.shifted_pair()
+    op = cost.OracleProblem(p)
+    n = sum(op.pts[v][0].size for v in range(op.V))
+    st = oj.initial_state(op.V, n, 1)
+    m, v = np.zeros((op.V, 6)), np.zeros((op.V, 6))
+    new, m1, v1, st1, r = loop.joint_loop_step(op, 0, p.poses_init, m, v, st, phase=None)
+    assert r["loss"][0] == 0.0 and not np.any(r["grad"]) and not np.any(r["grad_focal"])
+    assert np.array_equal(new, p.poses_init)
+    assert not np.any(st1["gamma"]) and not np.any(st1["beta"])
+    lr0 = loop.learning_rate(0)
+    assert np.all(st1["alpha"] == np.float32(1.0 * (1.0 - lr0 * 0.01)))
+    for k in ("m_gamma", "v_gamma", "m_alpha", "v_alpha", "m_beta", "v_beta"):
+        assert not np.any(st1[k]), k
+    assert st1["steps"].tolist() == [[1], [1]]
+
+
+def test_joint_loop_gradients_against_central_differences():
+    """At a seeded refined state (|gamma|, |alpha - 1|, |beta| <= 0.02, poses
+    of the small workload) the loop's dL/dgamma, dL/dalpha, dL/dbeta against
+    frozen-branch central differences of the scene loss in gamma and in
+    single pixels' alpha and beta (h = 1e-6, unrounded refinement)."""
+    from oracle import cost, loop
+    from synth import make
+    p = make("c1")
+    op = cost.OracleProblem(p)
+    rng = np.random.default_rng(3)
+    n = sum(op.pts[v][0].size for v in range(op.V))
+    gam = rng.uniform(-0.02, 0.02, op.V)
+    al = 1.0 + rng.uniform(-0.02, 0.02, n)
+    be = rng.uniform(-0.02, 0.02, n)
+    params = cost.CostParams()
+    K, depth = loop.joint_refinement(op, gam, al, be, rounded=False)
+    base = op.evaluate(p.poses_init, 10.0, params, K=K, depth=depth)
+    g = loop.joint_gradients(op, base, gam)
+    frozen = base["decisions"]
+    h = 1e-6
+
+    def loss_at(gm, a, b):
+        Kx, dx = loop.joint_refinement(op, gm, a, b, rounded=False)
+        return cost._frozen_loss(op, p.poses_init, 10.0, params, frozen, base, K=Kx,
+                                 depth=dx)[0]
+
+    for vv in range(op.V):
+        gp, gm_ = gam.copy(), gam.copy()
+        gp[vv] += h
+        gm_[vv] -= h
+        fd = (loss_at(gp, al, be) - loss_at(gm_, al, be)) / (2 * h)
+        assert abs(fd - g["grad_gamma"][vv]) <= 1e-6 * abs(fd), (vv, fd, g["grad_gamma"][vv])
+    views = loop.record_views(op)
+    for k in rng.choice(np.flatnonzero(views == 0), 6, replace=False):
+        for name, arr in (("grad_alpha", al), ("grad_beta", be)):
+            ap, am = arr.copy(), arr.copy()
+            ap[k] += h
+            am[k] -= h
+            if name == "grad_alpha":
+                fd = (loss_at(gam, ap, be) - loss_at(gam, am, be)) / (2 * h)
+            else:
+                fd = (loss_at(gam, al, ap) - loss_at(gam, al, am)) / (2 * h)
+            want = g[name][k]
+            assert abs(fd - want) <= 1e-6 * max(abs(want), 1e-3 * np.abs(g[name]).max()), \
+                (name, k, fd, want)
+
+
+def test_joint_loop_depth_waits_for_the_switch():
+    """Phases (0, 0, 0, 1, 1) over five steps of the small workload: the
+    depth parameters keep their identity values through the pose phase; the
+    first step of the joint phase, at iteration 3, is the depth optimizer's
+    step 1 (closed form after the decay), while gamma has stepped at every
+    iteration (its count 5)."""
+    from oracle import cost, loop
+    from synth import make
+    p = make("c1")
+    op = cost.OracleProblem(p)
+    n = sum(op.pts[v][0].size for v in range(op.V))
+    st = oj.initial_state(op.V, n, 1)
+    poses, m, v = p.poses_init.copy(), np.zeros((op.V, 6)), np.zeros((op.V, 6))
+    for s, ph in enumerate((0, 0, 0, 1, 1)):
+        before = st
+        poses, m, v, st, r = loop.joint_loop_step(op, s, poses, m, v, st, phase=[ph])
+        if s < 3:
+            assert np.all(st["alpha"] == 1.0) and np.all(st["beta"] == 0.0)
+            assert not np.any(st["m_alpha"])
+        if s == 3:
+            gb = loop.joint_gradients(op, r, before["gamma"])["grad_beta"]
+            lr = loop.learning_rate(3)
+            want = (-lr * gb / (np.abs(gb) + 1e-8)).astype(np.float32)
+            assert np.all(np.abs(st["beta"] - want) <= np.spacing(np.abs(want)))
+            assert not np.array_equal(st["gamma"], before["gamma"])
+    assert st["steps"].tolist() == [[5], [2]]
