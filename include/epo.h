@@ -314,6 +314,57 @@ EPO_API epo_status epo_joint_step(epo_plan plan, double* gamma, float* alpha, fl
                                   int32_t* steps, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * The two-phase loop of the joint phase as one captured iteration (paper
+ * Alg. 2 with Sec. 3 "Camera Refinement" / "Depth Refinement"): per replay
+ *   schedule (lambda(s), lr(s) per scene; lr 0 once a scene has stopped)
+ *   -> cost, pose, focal and per-pixel depth gradients at the current poses
+ *      and refinement (epo_edge_cost_refine)
+ *   -> joint AdamW step of gamma, alpha, beta gated by the scene's phase on
+ *      the device, which installs the new refinement (epo_joint_step)
+ *   -> Adam twist step of the poses (epo_pose_step)
+ *   -> convergence test (with_convergence 1 or 2), which moves a scene to the
+ *      joint phase (its depth parameters step from the next replay on) and
+ *      then stops it,
+ * with no host synchronisation.  with_convergence 0: no test, every
+ * parameter steps at every replay.  2: a stopped scene's tiles also leave the
+ * fused launch from the next replay on (as for epo_iteration_capture).
+ *
+ * epo_joint_state names the caller's device buffers of the joint phase (as
+ * for epo_joint_step; grad_* are written at every replay and may be read
+ * after it).  The pointers are baked into the graph.  Before capture the
+ * call installs the state's refinement in the plan (allocating, on the
+ * plan's first depth update, the copy of its depths and, if it fits in half
+ * the free memory, the per-residual depth derivatives) and synchronises;
+ * with the test, epo_convergence_reset must have been called on `poses`.
+ * Errors: EPO_ERR_INVALID_ARG for a null pointer (grad may be NULL) or a
+ * schedule out of range.  Replaces a previously captured iteration; replay
+ * with epo_iteration_launch.
+ * ------------------------------------------------------------------------- */
+typedef struct epo_joint_state {
+    double* gamma;        /* [V] focal scales */
+    float* alpha;         /* [n_records] depth scales (plan record order) */
+    float* beta;          /* [n_records] depth shifts */
+    double* m_gamma;      /* [V] AdamW moments of gamma */
+    double* v_gamma;      /* [V] */
+    double* m_depth;      /* [2][n_records]: alpha's, then beta's */
+    double* v_depth;      /* [2][n_records] */
+    int32_t* steps;       /* [2][n_scenes] focal and depth step counts */
+    double* grad_gamma;   /* [V] written by every replay */
+    double* grad_alpha;   /* [n_records] written by every replay */
+    double* grad_beta;    /* [n_records] written by every replay */
+    double wd_focal;      /* weight decay of gamma (the paper: 0.01) */
+    double wd_depth;      /* weight decay of alpha, beta (the paper: 0.01) */
+} epo_joint_state;
+
+EPO_API epo_status epo_joint_iteration_capture(epo_plan plan, double* poses, double* adam_m,
+                                               double* adam_v, int32_t* step, double* loss,
+                                               double* grad, const epo_joint_state* joint,
+                                               float lambda0, float lambda1, int32_t anneal_steps,
+                                               double peak_lr, int32_t warmup, int32_t total,
+                                               double beta1, double beta2, double eps,
+                                               int32_t with_convergence, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Viewgraph estimation (paper Sec. 3 "Viewgraph Estimation", Sec. 4
  * "Implementation Details"; construction kernels of the supplementary
  * material).  For every candidate pair (i, j), each pixel p = (a s, b s) of

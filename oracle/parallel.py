@@ -39,6 +39,13 @@ def _pair_work(args):
     return out
 
 
+def _single_threaded():
+    """Worker initializer: one BLAS thread per worker process, so that the
+    workers are the only parallelism (for timing)."""
+    from threadpoolctl import threadpool_limits
+    _STATE["limits"] = threadpool_limits(1)
+
+
 def default_workers() -> int:
     return max(1, min(os.cpu_count() or 1, 16))
 
@@ -49,16 +56,10 @@ def distance_fields(prob, workers: int | None = None, views=None, context: str =
     be "spawn" (fresh interpreters, for a parent that holds a GPU context)."""
     views = list(range(prob.n_views)) if views is None else list(views)
     jobs = ((v, prob.edge_map(v)) for v in views)
-    with mp.get_context(context).Pool(workers or default_workers()) as pool:
+    with mp.get_context(context).Pool(workers or default_workers(),
+                                      initializer=_single_threaded) as pool:
         out = dict(pool.imap_unordered(_edt_work, jobs, chunksize=1))
     return out
-
-
-def _single_threaded():
-    """Worker initializer: one BLAS thread per worker process, so that the
-    workers are the only parallelism (for timing)."""
-    from threadpoolctl import threadpool_limits
-    _STATE["limits"] = threadpool_limits(1)
 
 
 class ParallelEvaluator:

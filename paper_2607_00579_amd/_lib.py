@@ -32,6 +32,15 @@ class CostParams(C.Structure):
                 ("lambda_max", C.c_float)]
 
 
+class JointState(C.Structure):
+    """epo_joint_state: device addresses of the joint phase's buffers."""
+    _fields_ = [("gamma", C.c_void_p), ("alpha", C.c_void_p), ("beta", C.c_void_p),
+                ("m_gamma", C.c_void_p), ("v_gamma", C.c_void_p), ("m_depth", C.c_void_p),
+                ("v_depth", C.c_void_p), ("steps", C.c_void_p), ("grad_gamma", C.c_void_p),
+                ("grad_alpha", C.c_void_p), ("grad_beta", C.c_void_p), ("wd_focal", C.c_double),
+                ("wd_depth", C.c_double)]
+
+
 class PlanOptions(C.Structure):
     _fields_ = [("texture_format", C.c_int32), ("points_per_thread", C.c_int32),
                 ("tile_order", C.c_int32), ("persistent", C.c_int32)]
@@ -67,6 +76,8 @@ _SIGS = {
     "epo_schedule": [P, I32, F32, F32, I32, F64, I32, I32, P, P, P],
     "epo_iteration_capture": [P, P, P, P, P, P, P, P, F32, F32, I32, F64, I32, I32, F64, F64,
                               F64, I32, P],
+    "epo_joint_iteration_capture": [P, P, P, P, P, P, P, C.POINTER(JointState), F32, F32, I32,
+                                    F64, I32, I32, F64, F64, F64, I32, P],
     "epo_convergence_reset": [P, P, P, P],
     "epo_convergence_update": [P, P, P, P, P],
     "epo_convergence_query": [P, P, P, P, P, P],
@@ -266,6 +277,19 @@ def iteration_capture(plan, poses, m, v, step, loss, grad, fixed_mask, lambda0, 
                                         _ptr(loss), _ptr(grad), _ptr(fixed_mask), lambda0,
                                         lambda1, anneal_steps, peak_lr, warmup, total, beta1,
                                         beta2, eps, int(with_convergence), stream))
+
+
+def joint_iteration_capture(plan, poses, m, v, step, loss, grad, joint: dict, wd_focal, wd_depth,
+                            lambda0, lambda1, anneal_steps, peak_lr, warmup, total, beta1, beta2,
+                            eps, with_convergence, stream):
+    js = JointState(*[_ptr(joint.get(k)) for k in ("gamma", "alpha", "beta", "m_gamma",
+                                                   "v_gamma", "m_depth", "v_depth", "steps",
+                                                   "grad_gamma", "grad_alpha", "grad_beta")],
+                    float(wd_focal), float(wd_depth))
+    _check(load().epo_joint_iteration_capture(plan, _ptr(poses), _ptr(m), _ptr(v), _ptr(step),
+                                              _ptr(loss), _ptr(grad), C.byref(js), lambda0,
+                                              lambda1, anneal_steps, peak_lr, warmup, total,
+                                              beta1, beta2, eps, int(with_convergence), stream))
 
 
 class ConvergenceParams(C.Structure):

@@ -291,6 +291,44 @@ class EdgePlan:
                         lr, phase, beta1, beta2,
                         eps, wd_focal, wd_depth, state["steps"], _stream(self.device))
 
+    def _check_joint_state(self, state):
+        V, n = self.n_views, self.n_records
+        want = {"gamma": (torch.float64, V), "alpha": (torch.float32, n),
+                "beta": (torch.float32, n), "m_gamma": (torch.float64, V),
+                "v_gamma": (torch.float64, V), "m_depth": (torch.float64, 2 * n),
+                "v_depth": (torch.float64, 2 * n), "steps": (torch.int32, 2 * self.n_scenes)}
+        for k, (dt, size) in want.items():
+            t = state.get(k)
+            if (not torch.is_tensor(t) or not t.is_cuda
+                    or t.device.index != (self.device.index or 0) or t.dtype != dt
+                    or t.numel() < size or not t.is_contiguous()):
+                raise ValueError(f"state[{k!r}] must be a contiguous {dt} tensor of at least "
+                                 f"{size} values on {self.device}")
+
+    def capture_joint_iteration(self, poses, m, v, step, loss, state, grad=None, lambda0=10.0,
+                                lambda1=6.0, anneal_steps=1000, peak_lr=3e-3, warmup=25,
+                                total=2000, beta1=0.9, beta2=0.999, eps=1e-8, wd_focal=0.01,
+                                wd_depth=0.01, convergence=False, early_exit=False):
+        """Capture one iteration of the two-phase loop with focal and depth
+        refinement (schedule -> cost with pose, focal and depth gradients ->
+        joint AdamW gated by the device phase -> pose step [-> convergence
+        test]); replay with launch_iteration().  `state` is joint_state()'s
+        dict; its gradient buffers (grad_gamma, grad_alpha, grad_beta) are
+        added if missing and rewritten at every replay.  Without the test
+        every parameter steps at every replay; with it (reset beforehand with
+        convergence_reset) the depth parameters step only in the joint phase
+        and nothing after the stop; early_exit as for capture_iteration."""
+        self._check_joint_state(state)
+        d, n, V = self.device, self.n_records, self.n_views
+        for k, size in (("grad_gamma", V), ("grad_alpha", n), ("grad_beta", n)):
+            if k not in state:
+                state[k] = torch.zeros(max(size, 1), dtype=torch.float64, device=d)
+        self._graph_refs = (poses, m, v, step, loss, grad, dict(state))
+        mode = (2 if early_exit else 1) if convergence else 0
+        _lib.joint_iteration_capture(self.handle, poses, m, v, step, loss, grad, state, wd_focal,
+                                     wd_depth, lambda0, lambda1, anneal_steps, peak_lr, warmup,
+                                     total, beta1, beta2, eps, mode, _stream(self.device))
+
     def pose_step(self, poses, m, v, grad, lr, step, fixed_mask=None, beta1=0.9, beta2=0.999,
                   eps=1e-8):
         if not torch.is_tensor(lr):

@@ -313,6 +313,14 @@ void launch_convergence(Plan& p, const double* poses, double* theta_out, hipStre
 void launch_pair_selection(Plan& p, const int32_t* step, hipStream_t stream);
 void launch_convergence_reset(Plan& p, const double* poses, hipStream_t stream);
 void build_texture(Plan& p, const int32_t* d2, hipStream_t stream);
+// refinement of the joint phase: install (gamma, alpha, beta) in the plan
+// (allocates on the first depth update), the joint AdamW step (needs the
+// record offsets on the device), and the device copy of the record offsets
+void install_refinement(Plan& p, const double* gamma, const float* alpha, const float* beta,
+                        hipStream_t stream);
+void launch_joint_step(Plan& p, const epo_joint_state& j, const double* lr, const int32_t* phase,
+                       double b1, double b2, double eps, hipStream_t stream);
+void ensure_record_offsets(Plan& p, hipStream_t stream);
 void mlp_setup(Plan& p, hipStream_t stream);
 void launch_mlp_forward(Plan& p, const float* params, const double* poses0, const double* delta,
                         double* poses, hipStream_t stream);

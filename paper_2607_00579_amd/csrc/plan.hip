@@ -672,6 +672,66 @@ extern "C" epo_status epo_plan_autotune(epo_plan plan, const double* poses, cons
     });
 }
 
+namespace {
+
+// Captures the launches `body` makes on a fresh stream as the plan's
+// iteration graph: `step` is the device counter the pair selection reads
+// during capture, with_convergence 2 leaves stopped scenes' tiles out of the
+// fused launch, and no timing events are recorded inside the graph.
+template <class F>
+void capture_iteration(Plan& p, const int32_t* step, int32_t with_convergence, hipStream_t user,
+                       F&& body) {
+    EPO_HIP(hipStreamSynchronize(user));
+    release_graph(p);
+    hipStream_t cs;
+    EPO_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    const bool timing = p.timing;
+    p.timing = false;
+    hipError_t cap = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (cap != hipSuccess) {
+        p.timing = timing;
+        (void)hipStreamDestroy(cs);
+        throw Failure{EPO_ERR_HIP, std::string("hipStreamBeginCapture: ") +
+                                       hipGetErrorString(cap)};
+    }
+    p.capture_step = step;
+    p.gate_phase = with_convergence == 2 ? p.conv_phase.p : nullptr;
+    try {
+        body(cs);
+    } catch (...) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(cs, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        (void)hipStreamDestroy(cs);
+        p.timing = timing;
+        p.capture_step = nullptr;
+        p.gate_phase = nullptr;
+        throw;
+    }
+    p.timing = timing;
+    p.capture_step = nullptr;
+    if (p.gate_phase) p.scale_gated = true;
+    p.gate_phase = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &p.graph);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess)
+        throw Failure{EPO_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e)};
+    EPO_HIP(hipGraphInstantiate(&p.graph_exec, p.graph, nullptr, nullptr, 0));
+}
+
+void check_schedule(const Plan& p, float lambda0, float lambda1, int32_t anneal_steps,
+                    int32_t warmup, int32_t total, int32_t with_convergence) {
+    EPO_REQUIRE(warmup >= 1 && total > warmup && anneal_steps >= 0, "schedule out of range");
+    EPO_REQUIRE(lambda0 <= p.params.lambda_max && lambda1 <= p.params.lambda_max,
+                "schedule clamp above the plan's lambda_max");
+    EPO_REQUIRE(with_convergence >= 0 && with_convergence <= 2,
+                "with_convergence must be 0, 1 or 2");
+    EPO_REQUIRE(!with_convergence || p.max_views_per_scene <= kConvMaxViews,
+                "a scene has more views than the convergence kernel supports");
+}
+
+}  // namespace
+
 extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double* adam_m,
                                             double* adam_v, int32_t* step, double* loss,
                                             double* grad, const uint8_t* fixed_mask,
@@ -681,34 +741,11 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
                                             int32_t with_convergence, void* stream) {
     return guarded([&] {
         EPO_REQUIRE(plan && poses && adam_m && adam_v && step && loss, "null argument");
-        EPO_REQUIRE(warmup >= 1 && total > warmup && anneal_steps >= 0, "schedule out of range");
         Plan& p = *reinterpret_cast<Plan*>(plan);
         EPO_HIP(hipSetDevice(p.device));
-        EPO_REQUIRE(lambda0 <= p.params.lambda_max && lambda1 <= p.params.lambda_max,
-                    "schedule clamp above the plan's lambda_max");
-        EPO_REQUIRE(with_convergence >= 0 && with_convergence <= 2,
-                    "with_convergence must be 0, 1 or 2");
-        EPO_REQUIRE(!with_convergence || p.max_views_per_scene <= kConvMaxViews,
-                    "a scene has more views than the convergence kernel supports");
-        hipStream_t user = as_stream(stream);
-        EPO_HIP(hipStreamSynchronize(user));
-        release_graph(p);
+        check_schedule(p, lambda0, lambda1, anneal_steps, warmup, total, with_convergence);
         double* g = grad ? grad : p.grad_scratch.p;
-        hipStream_t cs;
-        EPO_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        const bool timing = p.timing;
-        p.timing = false;                    // no event records inside the graph
-        hipError_t cap = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        if (cap != hipSuccess) {
-            p.timing = timing;
-            (void)hipStreamDestroy(cs);
-            throw Failure{EPO_ERR_HIP, std::string("hipStreamBeginCapture: ") +
-                                           hipGetErrorString(cap)};
-        }
-        p.capture_step = step;               // the selection reads the iteration's counter
-        // with_convergence 2: stopped scenes' tiles are left out of the launch
-        p.gate_phase = with_convergence == 2 ? p.conv_phase.p : nullptr;
-        try {
+        capture_iteration(p, step, with_convergence, as_stream(stream), [&](hipStream_t cs) {
             launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
                             p.lambda_buf.p, p.lr_buf.p,
                             with_convergence ? p.conv_phase.p : nullptr, cs);
@@ -716,25 +753,7 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
             launch_pose_step(poses, adam_m, adam_v, g, p.V, p.scene_of_view_d.p, fixed_mask,
                              p.lr_buf.p, beta1, beta2, eps, step, cs);
             if (with_convergence) launch_convergence(p, poses, nullptr, cs);
-        } catch (...) {
-            hipGraph_t junk = nullptr;
-            (void)hipStreamEndCapture(cs, &junk);
-            if (junk) (void)hipGraphDestroy(junk);
-            (void)hipStreamDestroy(cs);
-            p.timing = timing;
-            p.capture_step = nullptr;
-            p.gate_phase = nullptr;
-            throw;
-        }
-        p.timing = timing;
-        p.capture_step = nullptr;
-        if (p.gate_phase) p.scale_gated = true;
-        p.gate_phase = nullptr;
-        hipError_t e = hipStreamEndCapture(cs, &p.graph);
-        (void)hipStreamDestroy(cs);
-        if (e != hipSuccess)
-            throw Failure{EPO_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e)};
-        EPO_HIP(hipGraphInstantiate(&p.graph_exec, p.graph, nullptr, nullptr, 0));
+        });
     });
 }
 
@@ -749,35 +768,12 @@ extern "C" epo_status epo_mlp_iteration_capture(
         EPO_REQUIRE(plan && params && adam_m && adam_v && param_grad && delta && delta_m &&
                         delta_v && delta_grad && poses0 && poses && step && loss,
                     "null argument");
-        EPO_REQUIRE(warmup >= 1 && total > warmup && anneal_steps >= 0, "schedule out of range");
         Plan& p = *reinterpret_cast<Plan*>(plan);
         EPO_HIP(hipSetDevice(p.device));
         EPO_REQUIRE(p.mlp_act.p, "call epo_mlp_setup first");
-        EPO_REQUIRE(lambda0 <= p.params.lambda_max && lambda1 <= p.params.lambda_max,
-                    "schedule clamp above the plan's lambda_max");
-        EPO_REQUIRE(with_convergence >= 0 && with_convergence <= 2,
-                    "with_convergence must be 0, 1 or 2");
-        EPO_REQUIRE(!with_convergence || p.max_views_per_scene <= kConvMaxViews,
-                    "a scene has more views than the convergence kernel supports");
-        hipStream_t user = as_stream(stream);
-        EPO_HIP(hipStreamSynchronize(user));
-        release_graph(p);
+        check_schedule(p, lambda0, lambda1, anneal_steps, warmup, total, with_convergence);
         double* g = grad ? grad : p.grad_scratch.p;
-        hipStream_t cs;
-        EPO_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        const bool timing = p.timing;
-        p.timing = false;
-        hipError_t cap = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        if (cap != hipSuccess) {
-            p.timing = timing;
-            (void)hipStreamDestroy(cs);
-            throw Failure{EPO_ERR_HIP, std::string("hipStreamBeginCapture: ") +
-                                           hipGetErrorString(cap)};
-        }
-        p.capture_step = step;
-        // with_convergence 2: stopped scenes' tiles are left out of the launch
-        p.gate_phase = with_convergence == 2 ? p.conv_phase.p : nullptr;
-        try {
+        capture_iteration(p, step, with_convergence, as_stream(stream), [&](hipStream_t cs) {
             // schedule -> cost and adjoint at the current poses -> refiner
             // backward (activations of the forward that made them) -> AdamW
             // (advances the step) -> poses of the new parameters ->
@@ -791,25 +787,51 @@ extern "C" epo_status epo_mlp_iteration_capture(
                          delta_grad, p.lr_buf.p, beta1, beta2, eps, wd_mlp, wd_delta, step, cs);
             launch_mlp_forward(p, params, poses0, delta, poses, cs);
             if (with_convergence) launch_convergence(p, poses, nullptr, cs);
-        } catch (...) {
-            hipGraph_t junk = nullptr;
-            (void)hipStreamEndCapture(cs, &junk);
-            if (junk) (void)hipGraphDestroy(junk);
-            (void)hipStreamDestroy(cs);
-            p.timing = timing;
-            p.capture_step = nullptr;
-            p.gate_phase = nullptr;
-            throw;
-        }
-        p.timing = timing;
-        p.capture_step = nullptr;
-        if (p.gate_phase) p.scale_gated = true;
-        p.gate_phase = nullptr;
-        hipError_t e = hipStreamEndCapture(cs, &p.graph);
-        (void)hipStreamDestroy(cs);
-        if (e != hipSuccess)
-            throw Failure{EPO_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e)};
-        EPO_HIP(hipGraphInstantiate(&p.graph_exec, p.graph, nullptr, nullptr, 0));
+        });
+    });
+}
+
+extern "C" epo_status epo_joint_iteration_capture(epo_plan plan, double* poses, double* adam_m,
+                                                  double* adam_v, int32_t* step, double* loss,
+                                                  double* grad, const epo_joint_state* joint,
+                                                  float lambda0, float lambda1,
+                                                  int32_t anneal_steps, double peak_lr,
+                                                  int32_t warmup, int32_t total, double beta1,
+                                                  double beta2, double eps,
+                                                  int32_t with_convergence, void* stream) {
+    return guarded([&] {
+        EPO_REQUIRE(plan && poses && adam_m && adam_v && step && loss && joint, "null argument");
+        const epo_joint_state j = *joint;
+        EPO_REQUIRE(j.gamma && j.alpha && j.beta && j.m_gamma && j.v_gamma && j.m_depth &&
+                        j.v_depth && j.steps && j.grad_gamma && j.grad_alpha && j.grad_beta,
+                    "null pointer in the joint state");
+        EPO_REQUIRE(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0,
+                    "beta1, beta2 must be in [0, 1) and eps > 0");
+        Plan& p = *reinterpret_cast<Plan*>(plan);
+        EPO_HIP(hipSetDevice(p.device));
+        check_schedule(p, lambda0, lambda1, anneal_steps, warmup, total, with_convergence);
+        hipStream_t user = as_stream(stream);
+        // set-up outside the graph: the state's refinement in the plan (the
+        // first depth update allocates), the record offsets on the device
+        ensure_record_offsets(p, user);
+        install_refinement(p, j.gamma, j.alpha, j.beta, user);
+        double* g = grad ? grad : p.grad_scratch.p;
+        const RefineOut out{j.grad_gamma, j.grad_alpha, j.grad_beta};
+        const int32_t* phase = with_convergence ? p.conv_phase.p : nullptr;
+        capture_iteration(p, step, with_convergence, user, [&](hipStream_t cs) {
+            // schedule -> cost, pose, focal and depth gradients at the current
+            // refinement -> joint AdamW gated by the phase (installs the new
+            // refinement) -> pose step (advances the step) -> (pose-change
+            // test, phase switches)
+            launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
+                            p.lambda_buf.p, p.lr_buf.p, phase, cs);
+            launch_cost(p, poses, p.lambda_buf.p, loss, nullptr, nullptr, nullptr, g, nullptr, cs,
+                        &out);
+            launch_joint_step(p, j, p.lr_buf.p, phase, beta1, beta2, eps, cs);
+            launch_pose_step(poses, adam_m, adam_v, g, p.V, p.scene_of_view_d.p, nullptr,
+                             p.lr_buf.p, beta1, beta2, eps, step, cs);
+            if (with_convergence) launch_convergence(p, poses, nullptr, cs);
+        });
     });
 }
 

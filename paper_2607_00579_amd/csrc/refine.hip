@@ -282,6 +282,68 @@ void launch_depth_grad(Plan& p, const double* upstream, double* grad_alpha, doub
 
 using namespace epo;
 
+namespace epo {
+
+void install_refinement(Plan& p, const double* gamma, const float* alpha, const float* beta,
+                        hipStream_t s) {
+    if (!p.dz.p && p.dz_size > 0 && !p.dz_declined) {
+        // room for the per-residual depth derivatives: use at most half
+        // of the free device memory, else keep recomputing them
+        size_t free_b = 0, total_b = 0;
+        EPO_HIP(hipMemGetInfo(&free_b, &total_b));
+        if ((uint64_t)p.dz_size * sizeof(float) <= free_b / 2)
+            p.dz.alloc((size_t)p.dz_size);
+        else
+            p.dz_declined = true;
+    }
+    refine_intrinsics_kernel<<<(unsigned)ceil_div(p.V, 256), 256, 0, s>>>(
+        p.K0_d.p, gamma, p.K_d.p, p.gamma_d.p, p.V, p.status.p);
+    EPO_CHECK_LAUNCH();
+    const int64_t n = p.rec_off.back();
+    if (n == 0) return;
+    if (!p.z0.p) {
+        // first depth update: keep the depths the plan was built with
+        if (!alpha) return;
+        p.z0.alloc((size_t)n);
+        snapshot_depth_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(
+            reinterpret_cast<const uint2*>(p.records.p), p.z0.p, n);
+        EPO_CHECK_LAUNCH();
+    }
+    refine_depth_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(
+        p.z0.p, alpha, beta, reinterpret_cast<uint2*>(p.records.p), n, p.status.p);
+    EPO_CHECK_LAUNCH();
+}
+
+void launch_joint_step(Plan& p, const epo_joint_state& j, const double* lr, const int32_t* phase,
+                       double b1, double b2, double eps, hipStream_t s) {
+    const int64_t n = p.rec_off.back();
+    const bool installed = p.z0.p != nullptr;
+    const int64_t total = (int64_t)p.V + n;
+    joint_step_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(
+        j.gamma, j.alpha, j.beta, j.m_gamma, j.v_gamma, j.m_depth, j.v_depth, j.grad_gamma,
+        j.grad_alpha, j.grad_beta, p.rec_off_d.p, p.scene_of_view_d.p, p.V, n, p.S, lr, phase, b1,
+        b2, eps, j.wd_focal, j.wd_depth, j.steps, installed ? p.z0.p : nullptr,
+        installed ? reinterpret_cast<uint2*>(p.records.p) : nullptr, p.status.p);
+    EPO_CHECK_LAUNCH();
+    count_joint_steps_kernel<<<(unsigned)ceil_div(p.S, 256), 256, 0, s>>>(j.steps, phase, p.S);
+    EPO_CHECK_LAUNCH();
+    if (installed) {
+        refine_intrinsics_kernel<<<(unsigned)ceil_div(p.V, 256), 256, 0, s>>>(
+            p.K0_d.p, j.gamma, p.K_d.p, p.gamma_d.p, p.V, p.status.p);
+        EPO_CHECK_LAUNCH();
+    }
+}
+
+void ensure_record_offsets(Plan& p, hipStream_t s) {
+    if (p.rec_off_d.p) return;
+    p.rec_off_d.alloc(p.rec_off.size());
+    EPO_HIP(hipMemcpyAsync(p.rec_off_d.p, p.rec_off.data(), p.rec_off.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s));
+    EPO_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace epo
+
 extern "C" epo_status epo_plan_set_refinement(epo_plan plan, const double* gamma,
                                               const float* alpha, const float* beta,
                                               void* stream) {
@@ -291,33 +353,7 @@ extern "C" epo_status epo_plan_set_refinement(epo_plan plan, const double* gamma
                     "alpha and beta must be given together");
         Plan& p = *reinterpret_cast<Plan*>(plan);
         EPO_HIP(hipSetDevice(p.device));
-        hipStream_t s = as_stream(stream);
-        if (!p.dz.p && p.dz_size > 0 && !p.dz_declined) {
-            // room for the per-residual depth derivatives: use at most half
-            // of the free device memory, else keep recomputing them
-            size_t free_b = 0, total_b = 0;
-            EPO_HIP(hipMemGetInfo(&free_b, &total_b));
-            if ((uint64_t)p.dz_size * sizeof(float) <= free_b / 2)
-                p.dz.alloc((size_t)p.dz_size);
-            else
-                p.dz_declined = true;
-        }
-        refine_intrinsics_kernel<<<(unsigned)ceil_div(p.V, 256), 256, 0, s>>>(
-            p.K0_d.p, gamma, p.K_d.p, p.gamma_d.p, p.V, p.status.p);
-        EPO_CHECK_LAUNCH();
-        const int64_t n = p.rec_off.back();
-        if (n == 0) return;
-        if (!p.z0.p) {
-            // first depth update: keep the depths the plan was built with
-            if (!alpha) return;
-            p.z0.alloc((size_t)n);
-            snapshot_depth_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(
-                reinterpret_cast<const uint2*>(p.records.p), p.z0.p, n);
-            EPO_CHECK_LAUNCH();
-        }
-        refine_depth_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(
-            p.z0.p, alpha, beta, reinterpret_cast<uint2*>(p.records.p), n, p.status.p);
-        EPO_CHECK_LAUNCH();
+        install_refinement(p, gamma, alpha, beta, as_stream(stream));
     });
 }
 
@@ -343,8 +379,7 @@ extern "C" epo_status epo_joint_step(epo_plan plan, double* gamma, float* alpha,
                                      const double* lr, const int32_t* phase, double beta1,
                                      double beta2, double eps, double wd_focal, double wd_depth,
                                      int32_t* steps, void* stream) {
-    bool installed = false;
-    const epo_status st = guarded([&] {
+    return guarded([&] {
         EPO_REQUIRE(plan, "null plan");
         EPO_REQUIRE(gamma && alpha && beta && m_gamma && v_gamma && m_depth && v_depth &&
                         grad_gamma && grad_alpha && grad_beta && lr && steps,
@@ -354,31 +389,16 @@ extern "C" epo_status epo_joint_step(epo_plan plan, double* gamma, float* alpha,
         Plan& p = *reinterpret_cast<Plan*>(plan);
         EPO_HIP(hipSetDevice(p.device));
         hipStream_t s = as_stream(stream);
-        const int64_t n = p.rec_off.back();
-        if (!p.rec_off_d.p) {
-            p.rec_off_d.alloc(p.rec_off.size());
-            EPO_HIP(hipMemcpyAsync(p.rec_off_d.p, p.rec_off.data(),
-                                   p.rec_off.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        }
+        ensure_record_offsets(p, s);
         // once the plan holds its original depths (after the first depth
         // update), the step kernel rewrites the records' depths itself
-        installed = p.z0.p != nullptr;
-        const int64_t total = (int64_t)p.V + n;
-        joint_step_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(
-            gamma, alpha, beta, m_gamma, v_gamma, m_depth, v_depth, grad_gamma, grad_alpha,
-            grad_beta, p.rec_off_d.p, p.scene_of_view_d.p, p.V, n, p.S, lr, phase, beta1, beta2,
-            eps, wd_focal, wd_depth, steps, installed ? p.z0.p : nullptr,
-            installed ? reinterpret_cast<uint2*>(p.records.p) : nullptr, p.status.p);
-        EPO_CHECK_LAUNCH();
-        count_joint_steps_kernel<<<(unsigned)ceil_div(p.S, 256), 256, 0, s>>>(steps, phase, p.S);
-        EPO_CHECK_LAUNCH();
-        if (installed) {
-            refine_intrinsics_kernel<<<(unsigned)ceil_div(p.V, 256), 256, 0, s>>>(
-                p.K0_d.p, gamma, p.K_d.p, p.gamma_d.p, p.V, p.status.p);
-            EPO_CHECK_LAUNCH();
-        }
+        const bool installed = p.z0.p != nullptr;
+        const epo_joint_state j{gamma,  alpha,      beta,       m_gamma,   v_gamma,
+                                m_depth, v_depth,   steps,      const_cast<double*>(grad_gamma),
+                                const_cast<double*>(grad_alpha),
+                                const_cast<double*>(grad_beta), wd_focal, wd_depth};
+        launch_joint_step(p, j, lr, phase, beta1, beta2, eps, s);
+        // first depth update of the plan: the refinement update keeps its depths
+        if (!installed) install_refinement(p, gamma, alpha, beta, s);
     });
-    if (st != EPO_OK || installed) return st;
-    // first depth update of the plan: the refinement update keeps its depths
-    return epo_plan_set_refinement(plan, gamma, alpha, beta, stream);
 }

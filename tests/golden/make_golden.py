@@ -69,7 +69,7 @@ def write_prefix(name: str, workers=None):
     del d2
     print(f"{name}: distance transforms in {time.time() - t0:.0f} s", flush=True)
     t0 = time.time()
-    with opar.ParallelEvaluator(op, workers) as ev:
+    with opar.ParallelEvaluator(op, workers, single_threaded=True) as ev:
         hist = oloop.run(op, prob.poses_init, n, record_every=1, evaluate=ev)
     print(f"{name}: {n} steps in {time.time() - t0:.0f} s", flush=True)
     steps_at = np.arange(every, n + 1, every)

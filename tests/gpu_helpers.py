@@ -49,3 +49,28 @@ def say(msg):
 
 def env_flag(name):
     return os.environ.get(name, "") not in ("", "0")
+
+
+def oracle_index(prob, plan):
+    """For every plan record, (view, index into the oracle's row-major edge-pixel
+    order of that view)."""
+    px = plan.record_pixels()
+    idx = np.empty(px.shape[0], np.int64)
+    for v in range(prob.n_views):
+        sel = px[:, 0] == v
+        ys, xs = np.nonzero(prob.edge_map(v))
+        keys = ys.astype(np.int64) * int(prob.width[v]) + xs
+        k = px[sel, 2] * int(prob.width[v]) + px[sel, 1]
+        pos = np.searchsorted(keys, k)
+        assert np.array_equal(keys[pos], k)
+        idx[sel] = pos
+    return px[:, 0], idx
+
+
+def gather_depth(r_depth, views, idx, n):
+    out = np.zeros(n)
+    for v in np.unique(views):
+        sel = views == v
+        if v in r_depth:
+            out[sel] = r_depth[v][idx[sel]]
+    return out

@@ -8,7 +8,8 @@ import torch
 
 from oracle import cost as ocost
 from oracle import sampling as osamp
-from tests.gpu_helpers import check_depth, problem, rel_norm_err, say
+from tests.gpu_helpers import (check_depth, gather_depth, oracle_index, problem,
+                               rel_norm_err, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -18,31 +19,6 @@ TOL = 1e-4
 def plan_for(prob, **kw):
     from paper_2607_00579_amd.api import EdgePlan
     return EdgePlan.from_problem(prob, device="cuda:0", **kw)
-
-
-def oracle_index(prob, plan):
-    """For every plan record, (view, index into the oracle's row-major edge-pixel
-    order of that view)."""
-    px = plan.record_pixels()
-    idx = np.empty(px.shape[0], np.int64)
-    for v in range(prob.n_views):
-        sel = px[:, 0] == v
-        ys, xs = np.nonzero(prob.edge_map(v))
-        keys = ys.astype(np.int64) * int(prob.width[v]) + xs
-        k = px[sel, 2] * int(prob.width[v]) + px[sel, 1]
-        pos = np.searchsorted(keys, k)
-        assert np.array_equal(keys[pos], k)
-        idx[sel] = pos
-    return px[:, 0], idx
-
-
-def gather_depth(r_depth, views, idx, n):
-    out = np.zeros(n)
-    for v in np.unique(views):
-        sel = views == v
-        if v in r_depth:
-            out[sel] = r_depth[v][idx[sel]]
-    return out
 
 
 def run_case(prob, poses, lam, gamma=None, alpha=None, beta=None, sampling=None, options=None):

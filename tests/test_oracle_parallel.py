@@ -13,7 +13,7 @@ def test_parallel_evaluation_is_bitwise_serial():
     d2 = parallel.distance_fields(p, 3)
     assert all(np.array_equal(d2[v], op.d2[v]) for v in range(p.n_views))
     want = op.evaluate(p.poses_init, 8.0)
-    with parallel.ParallelEvaluator(op, 3) as ev:
+    with parallel.ParallelEvaluator(op, 3, single_threaded=True) as ev:
         got = ev(p.poses_init, 8.0)
         for k in ("loss", "grad", "grad_focal", "S", "n", "L", "w", "G_tgt", "G_src"):
             assert np.array_equal(got[k], want[k]), k
