@@ -99,6 +99,18 @@ typedef struct epo_plan_options {
                                    on one XCD; 2 = tiles in pair-list order */
     int32_t persistent;         /* 1 = persistent work-queue launch; 2 = one workgroup
                                    per tile */
+    int32_t record_order;       /* 1 = every pair reads its source view's records in
+                                   source order; 2 = every pair reads its own copy of
+                                   them, ordered by the 8 x 4 target pixel block each
+                                   record projects to (chunks of 8192 records), so the
+                                   taps gathered by one wavefront share cache lines.
+                                   The copies take 8 bytes per residual of device
+                                   memory and are re-sorted by epo_plan_resort and by
+                                   the captured iterations; only the summation order
+                                   of the results depends on the order */
+    int32_t resort_interval;    /* record_order 2: a captured iteration re-sorts the
+                                   chunks c with c mod k == step mod k, k = this many
+                                   steps (default 8) */
 } epo_plan_options;
 
 typedef struct epo_plan_s* epo_plan;
@@ -599,10 +611,14 @@ EPO_API epo_status epo_iteration_launch(epo_plan plan, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Autotuner: times every supported schedule (texture format, points per
- * thread, tile order, launch style) on the plan's own data at `poses` with
- * `iters` fused cost+adjoint evaluations each, keeps the fastest, and returns
- * it in *chosen (host, may be NULL).  Allocates and synchronises; call it
- * before capturing an iteration.
+ * thread, tile order, launch style, record order) on the plan's own data at
+ * `poses` with `iters` fused cost+adjoint evaluations each, keeps the fastest,
+ * and returns it in *chosen (host, may be NULL).  Record order 2 is charged
+ * its per-step share of the re-sort (a full re-sort / resort_interval) and
+ * is kept only if it beats the best record-order-1 schedule by 3 %; the
+ * record copies are freed unless it is chosen.  The resort_interval in force
+ * is kept.  Allocates and synchronises; call it before capturing an
+ * iteration.
  * ------------------------------------------------------------------------- */
 EPO_API epo_status epo_plan_autotune(epo_plan plan, const double* poses, const float* lambda,
                              int32_t iters, epo_plan_options* chosen, void* stream);
@@ -610,6 +626,29 @@ EPO_API epo_status epo_plan_autotune(epo_plan plan, const double* poses, const f
 /* Switch the plan to a given schedule (rebuilds the tile schedule; allocates;
  * synchronises).  Invalidates a captured iteration. */
 EPO_API epo_status epo_plan_set_options(epo_plan plan, const epo_plan_options* options, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Re-sort the per-pair record copies of record_order 2 at `poses` (device,
+ * float64 [V][3][4]): every chunk of 8192 records if `step` is NULL, else the
+ * chunks c with c mod every == (*step) mod every, *step read on the device
+ * when the work runs (so a captured call follows the step counter).  Each
+ * chunk is ordered by the target pixel block its records project to, invalid
+ * projections last, equal blocks in source order: a deterministic function of
+ * the poses.  A no-op under record_order 1.  The fused kernel's results change
+ * only in summation order.  No allocation, no synchronisation; capture-safe.
+ * Errors: EPO_ERR_INVALID_ARG for a null plan or poses, or every < 1 with a
+ * step.
+ * ------------------------------------------------------------------------- */
+EPO_API epo_status epo_plan_resort(epo_plan plan, const double* poses, const int32_t* step,
+                                   int32_t every, void* stream);
+
+/* The records pair d reads, in the order it reads them (host copy; syncs the
+ * device): its own sorted copy under record_order 2, else its source view's
+ * records.  *count = the source's edge count; records_out may be NULL to ask
+ * for the count only.  EPO_ERR_INVALID_ARG if d is out of range or capacity
+ * is too small. */
+EPO_API epo_status epo_plan_pair_records(epo_plan plan, int32_t d, uint64_t* records_out,
+                                         int64_t capacity, int64_t* count);
 
 /* Device status word of the plan, OR-ed by the kernels: bit 0 = a non-finite
  * per-pair sum was seen, bit 1 = a lambda above lambda_max was seen, bit 2 = a

@@ -43,7 +43,8 @@ class JointState(C.Structure):
 
 class PlanOptions(C.Structure):
     _fields_ = [("texture_format", C.c_int32), ("points_per_thread", C.c_int32),
-                ("tile_order", C.c_int32), ("persistent", C.c_int32)]
+                ("tile_order", C.c_int32), ("persistent", C.c_int32),
+                ("record_order", C.c_int32), ("resort_interval", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -84,6 +85,8 @@ _SIGS = {
     "epo_iteration_launch": [P, P],
     "epo_plan_autotune": [P, P, P, I32, C.POINTER(PlanOptions), P],
     "epo_plan_set_options": [P, C.POINTER(PlanOptions), P],
+    "epo_plan_resort": [P, P, P, I32, P],
+    "epo_plan_pair_records": [P, I32, P, I64, P],
     "epo_get_device_status": [P, P, P],
     "epo_plan_enable_timing": [P, I32],
     "epo_plan_last_kernel_ms": [P, P],
@@ -328,6 +331,19 @@ def plan_autotune(plan, poses, lam, iters, stream):
 def plan_set_options(plan, options: dict, stream):
     o = PlanOptions(**{k: int(options.get(k, 0)) for k, _ in PlanOptions._fields_})
     _check(load().epo_plan_set_options(plan, C.byref(o), stream))
+
+
+def plan_resort(plan, poses, step, every, stream):
+    _check(load().epo_plan_resort(plan, _ptr(poses), _ptr(step) if step is not None else None,
+                                  every, stream))
+
+
+def plan_pair_records(plan, d):
+    n = C.c_int64()
+    _check(load().epo_plan_pair_records(plan, d, None, 0, C.byref(n)))
+    out = np.zeros(n.value, np.uint64)
+    _check(load().epo_plan_pair_records(plan, d, _ptr(out), n.value, C.byref(n)))
+    return out
 
 
 def get_device_status(plan, stream) -> int:

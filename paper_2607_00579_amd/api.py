@@ -343,6 +343,16 @@ class EdgePlan:
     def set_options(self, **options):
         _lib.plan_set_options(self.handle, options, _stream(self.device))
 
+    def resort(self, poses, step=None, every=1):
+        """Re-sort the per-pair record copies (record_order 2) at `poses`:
+        all of them, or (with a device step counter) the chunks c with
+        c mod every == step mod every, as a captured iteration does."""
+        _lib.plan_resort(self.handle, poses, step, every, _stream(self.device))
+
+    def pair_records(self, d: int) -> np.ndarray:
+        """The records pair d reads, in its reading order (host copy)."""
+        return _lib.plan_pair_records(self.handle, d)
+
     def capture_iteration(self, poses, m, v, step, loss, grad=None, fixed_mask=None,
                           lambda0=10.0, lambda1=6.0, anneal_steps=1000, peak_lr=3e-3, warmup=25,
                           total=2000, beta1=0.9, beta2=0.999, eps=1e-8, convergence=False,

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(PKG, "libepo.so")
 SOURCES = ["edt.hip", "edge_cost.hip", "reduce.hip", "pose.hip", "converge.hip", "refine.hip",
-           "sample.hip", "viewgraph.hip",
+           "sample.hip", "viewgraph.hip", "order.hip",
            "mlp.hip", "plan.hip"]
 ARCH = "gfx950"
 

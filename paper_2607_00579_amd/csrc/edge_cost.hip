@@ -52,32 +52,9 @@ __global__ __launch_bounds__(256) void pair_setup_kernel(
     if (d >= D) return;
     const PairStatic st = ps[d];
     const int i = st.src, j = st.tgt;
-    double Ri[9], ti[3], Rj[9], tj[3];
-    for (int r = 0; r < 3; ++r) {
-        for (int c = 0; c < 3; ++c) {
-            Ri[3 * r + c] = poses[12 * i + 4 * r + c];
-            Rj[3 * r + c] = poses[12 * j + 4 * r + c];
-        }
-        ti[r] = poses[12 * i + 4 * r + 3];
-        tj[r] = poses[12 * j + 4 * r + 3];
-    }
-    // R_ji = R_j R_i^T, t_ji = t_j - R_ji t_i
-    double R[9], t[3];
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c)
-            R[3 * r + c] = Rj[3 * r + 0] * Ri[3 * c + 0] + Rj[3 * r + 1] * Ri[3 * c + 1] +
-                           Rj[3 * r + 2] * Ri[3 * c + 2];
-    for (int r = 0; r < 3; ++r)
-        t[r] = tj[r] - (R[3 * r + 0] * ti[0] + R[3 * r + 1] * ti[1] + R[3 * r + 2] * ti[2]);
-    const double fxi = K[4 * i + 0], fyi = K[4 * i + 1], cxi = K[4 * i + 2], cyi = K[4 * i + 3];
+    double R[9], t[3], M[9];
+    relative_pose(poses, K, i, j, R, t, M);
     const double fxj = K[4 * j + 0], fyj = K[4 * j + 1], cxj = K[4 * j + 2], cyj = K[4 * j + 3];
-    // M = R_ji K_i^-1
-    double M[9];
-    for (int r = 0; r < 3; ++r) {
-        M[3 * r + 0] = R[3 * r + 0] / fxi;
-        M[3 * r + 1] = R[3 * r + 1] / fyi;
-        M[3 * r + 2] = R[3 * r + 2] - R[3 * r + 0] * (cxi / fxi) - R[3 * r + 1] * (cyi / fyi);
-    }
     PairDesc o;
     for (int k = 0; k < 9; ++k) o.M[k] = M[k];
     for (int k = 0; k < 3; ++k) o.t[k] = t[k];
@@ -130,9 +107,14 @@ void launch_cost_kernel(Plan& p, float* dz, hipStream_t s) {
     if (grid == 0) return;
     auto kernel = persistent ? edge_cost_kernel<FMT, P, EXT, true>
                              : edge_cost_kernel<FMT, P, EXT, false>;
+    // the pose-only variant reads the per-pair sorted copies under record
+    // order 2; the refinement variant stores depth derivatives by source
+    // record and keeps the source order
+    const bool own = !EXT && p.opt.record_order == 2 && p.sorted_records.p;
     kernel<<<grid, kBlock, 0, s>>>(
-        reinterpret_cast<const uint2*>(p.records.p), tex, p.tiles.p, p.pair_desc.p, p.pair_rel.p,
-        p.partials.p, EXT ? p.ext_partials.p : nullptr, p.dz_index.p, dz, p.pair_scale.p,
+        reinterpret_cast<const uint2*>(own ? p.sorted_records.p : p.records.p), tex, p.tiles.p,
+        p.pair_desc.p, p.pair_rel.p, p.partials.p, EXT ? p.ext_partials.p : nullptr,
+        p.dz_index.p, dz, p.pair_scale.p, own ? p.pair_shift.p : nullptr,
         compacted_launch(p) ? p.qbegin_d.p : p.xcd_begin_d.p,
         compacted_launch(p) ? p.tile_list.p : nullptr, nq, p.counters.p,
         std::max(1, 16384 / p.tile_size), p.params.huber_delta, p.params.z_min);

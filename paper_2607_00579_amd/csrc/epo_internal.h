@@ -142,6 +142,36 @@ struct alignas(64) Partial {
 };
 // ==== data layout read by the fused kernel: end
 
+// relative pose of the directed pair i -> j (world -> camera poses [V][3][4],
+// float64): R_ji = R_j R_i^T, t_ji = t_j - R_ji t_i, and the unit-depth ray map
+// M = R_ji K_i^-1 (K as fx, fy, cx, cy per view), so that a source pixel
+// (u, v) at depth Z lands at X' = Z M (u, v, 1)^T + t_ji in the target frame
+__device__ inline void relative_pose(const double* __restrict__ poses,
+                                     const float* __restrict__ K, int i, int j, double R[9],
+                                     double t[3], double M[9]) {
+    double Ri[9], ti[3], Rj[9], tj[3];
+    for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) {
+            Ri[3 * r + c] = poses[12 * i + 4 * r + c];
+            Rj[3 * r + c] = poses[12 * j + 4 * r + c];
+        }
+        ti[r] = poses[12 * i + 4 * r + 3];
+        tj[r] = poses[12 * j + 4 * r + 3];
+    }
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            R[3 * r + c] = Rj[3 * r + 0] * Ri[3 * c + 0] + Rj[3 * r + 1] * Ri[3 * c + 1] +
+                           Rj[3 * r + 2] * Ri[3 * c + 2];
+    for (int r = 0; r < 3; ++r)
+        t[r] = tj[r] - (R[3 * r + 0] * ti[0] + R[3 * r + 1] * ti[1] + R[3 * r + 2] * ti[2]);
+    const double fxi = K[4 * i + 0], fyi = K[4 * i + 1], cxi = K[4 * i + 2], cyi = K[4 * i + 3];
+    for (int r = 0; r < 3; ++r) {
+        M[3 * r + 0] = R[3 * r + 0] / fxi;
+        M[3 * r + 1] = R[3 * r + 1] / fyi;
+        M[3 * r + 2] = R[3 * r + 2] - R[3 * r + 0] * (cxi / fxi) - R[3 * r + 1] * (cyi / fyi);
+    }
+}
+
 // per-scene convergence state (pose-change signal history and phase)
 constexpr int kConvRing = 128;          // >= 2 w - 1 for windows up to 64
 constexpr int kConvMaxViews = 4096;     // two doubles per view in LDS (64 KB)
@@ -190,6 +220,13 @@ struct Plan {
     DevBuf<PairDesc> pair_desc;           // D (rewritten every iteration)
     DevBuf<double> pair_rel;              // D x 12: R_ji, t_ji (float64)
     DevBuf<Tile> tiles;                   // T
+    // record_order 2: per-pair copies of the records, ordered by the target
+    // block each projects to (re-sorted on the device); pair d's copy of its
+    // source record r (absolute index) is sorted_records[r + pair_shift[d]]
+    DevBuf<uint64_t> sorted_records;      // n_residuals + kRecordPad
+    DevBuf<int64_t> pair_shift;           // D
+    DevBuf<Tile> sort_chunks;             // sort units: <= 8192 records of one pair
+    int64_t n_sort_chunks = 0;
     DevBuf<Partial> partials;             // T
     DevBuf<double> pair_sum;              // D x 8: S, n, G[6] (float64)
     DevBuf<double> pair_w;                // D: weight w_d
@@ -313,6 +350,12 @@ void launch_convergence(Plan& p, const double* poses, double* theta_out, hipStre
 void launch_pair_selection(Plan& p, const int32_t* step, hipStream_t stream);
 void launch_convergence_reset(Plan& p, const double* poses, hipStream_t stream);
 void build_texture(Plan& p, const int32_t* d2, hipStream_t stream);
+// record_order 2: allocate the per-pair record copies (source order until
+// the first sort); re-sort them at the given poses: every chunk (step null), or
+// the chunks c with c mod every == *step mod every
+void ensure_sorted_records(Plan& p, hipStream_t stream);
+void launch_resort(Plan& p, const double* poses, const int32_t* step, int32_t every,
+                   hipStream_t stream);
 // refinement of the joint phase: install (gamma, alpha, beta) in the plan
 // (allocates on the first depth update), the joint AdamW step (needs the
 // record offsets on the device), and the device copy of the record offsets

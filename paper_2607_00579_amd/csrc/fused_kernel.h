@@ -43,11 +43,9 @@ struct Terms {
 //         c = R_ji e_z the third column of R_ji),
 //   and the residual's depth derivative dH/dZ (stored for the source-major
 //   depth pass)
-template <int FMT, bool EXT>
-__device__ __forceinline__ Terms residual(const uint2 rec, bool active, const PairDesc& pd,
-                                          const uint32_t* __restrict__ texj, const float* lut,
-                                          float delta, double zmin, const double* c3) {
-    const Residual r = eval_residual<FMT>(rec, active, pd, texj, lut, delta, zmin);
+template <bool EXT>
+__device__ __forceinline__ Terms residual_terms(const Residual& r, const uint2 rec,
+                                                const double* c3) {
     Terms t;
     t.S = r.rho;
     t.valid = r.valid;
@@ -88,7 +86,8 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
                                         double* __restrict__ ext_partials,
                                         const int64_t* __restrict__ dz_index,
                                         float* __restrict__ dz,
-                                        const double* __restrict__ pair_scale, const float* lut,
+                                        const double* __restrict__ pair_scale,
+                                        const int64_t* __restrict__ pair_shift, const float* lut,
                                         double (*red)[10], float delta, double zmin) {
     const int tid = threadIdx.x;
     const Tile tl = tiles[t];
@@ -97,7 +96,8 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
     if (pair_scale[tl.pair] == 0.0) return;
     const PairDesc pd = desc[tl.pair];
     const uint32_t* texj = view_texture<FMT>(tex, pd.tex_off);
-    const uint2* rec = records + tl.rec;
+    // the pair's own record order (per-pair copies), or the source view's
+    const uint2* rec = records + tl.rec + (pair_shift ? pair_shift[tl.pair] : 0);
     double c3[3] = {0.0, 0.0, 0.0};
     float* dzt = nullptr;
     int64_t dzn = 0;
@@ -142,9 +142,9 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
         for (int k = 0; k < U; ++k) {
             // row (k0 + k) kBlock + tid is inside the tile: compared against a
             // wave-uniform limit, so no per-lane index arithmetic
-            const int left = tl.count - (k0 + k) * kBlock;
-            const bool in = tid < left;
-            tt[k] = residual<FMT, EXT>(r[k], in, pd, texj, lut, delta, zmin, c3);
+            const bool in = tid < tl.count - (k0 + k) * kBlock;
+            const Residual rs = eval_residual<FMT>(r[k], in, pd, texj, lut, delta, zmin);
+            tt[k] = residual_terms<EXT>(rs, r[k], c3);
             if (EXT && dzt && in) dzt[(int64_t)(k0 + k) * kBlock * dzn + tid] = tt[k].dz;
             n += tt[k].valid ? 1 : 0;
         }
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
     const double* __restrict__ rel, Partial* __restrict__ partials,
     double* __restrict__ ext_partials, const int64_t* __restrict__ dz_index,
     float* __restrict__ dz, const double* __restrict__ pair_scale,
-    const int64_t* __restrict__ xcd_begin, const int32_t* __restrict__ tile_list,
+    const int64_t* __restrict__ pair_shift, const int64_t* __restrict__ xcd_begin, const int32_t* __restrict__ tile_list,
     int32_t n_queues, int32_t* __restrict__ counters, int32_t chunk, float delta, double zmin) {
     // queue q holds entries [xcd_begin[q], xcd_begin[q + 1]) of the tile list:
     // every tile in XCD order, or (with pair sub-sampling) the step's compacted
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
         __syncthreads();
         const int64_t t = tile_list ? (int64_t)tile_list[e] : e;
         do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials, dz_index,
-                             dz, pair_scale, lut, red, delta, zmin);
+                             dz, pair_scale, pair_shift, lut, red, delta, zmin);
         return;
     }
     if (FMT == 2) lut[threadIdx.x] = sqrtf((float)threadIdx.x);
@@ -258,7 +258,8 @@ __global__ __launch_bounds__(kBlock) void edge_cost_kernel(
             for (int64_t e = e0; e < e1; ++e) {
                 const int64_t t = tile_list ? (int64_t)tile_list[e] : e;
                 do_tile<FMT, P, EXT>(t, records, tex, tiles, desc, rel, partials, ext_partials,
-                                     dz_index, dz, pair_scale, lut, red, delta, zmin);
+                                     dz_index, dz, pair_scale, pair_shift, lut, red, delta,
+                                     zmin);
                 __syncthreads();
             }
         }

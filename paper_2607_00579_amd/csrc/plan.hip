@@ -157,6 +157,8 @@ void validate_options(const epo_plan_options& o) {
                 "points_per_thread must be 1, 2, 4, 8 or 16");
     EPO_REQUIRE(o.tile_order == 1 || o.tile_order == 2, "tile_order must be 1 or 2");
     EPO_REQUIRE(o.persistent == 1 || o.persistent == 2, "persistent must be 1 or 2");
+    EPO_REQUIRE(o.record_order == 1 || o.record_order == 2, "record_order must be 1 or 2");
+    EPO_REQUIRE(o.resort_interval >= 1, "resort_interval must be >= 1");
 }
 
 void fill_default_options(Plan& p, epo_plan_options& o) {
@@ -164,6 +166,20 @@ void fill_default_options(Plan& p, epo_plan_options& o) {
     if (o.points_per_thread == 0) o.points_per_thread = 4;
     if (o.tile_order == 0) o.tile_order = 1;
     if (o.persistent == 0) o.persistent = 2;
+    if (o.record_order == 0) o.record_order = 1;
+    if (o.resort_interval == 0) o.resort_interval = 8;
+}
+
+// the per-pair record copies exist exactly while record_order 2 is in use
+void apply_record_order(Plan& p, hipStream_t s) {
+    if (p.opt.record_order == 2) {
+        ensure_sorted_records(p, s);
+    } else {
+        p.sorted_records.release();
+        p.pair_shift.release();
+        p.sort_chunks.release();
+        p.n_sort_chunks = 0;
+    }
 }
 
 }  // namespace
@@ -334,7 +350,7 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         if (options) {
             p->opt = *options;
         } else {
-            p->opt = epo_plan_options{0, 0, 0, 0};
+            p->opt = epo_plan_options{0, 0, 0, 0, 0, 0};
         }
         fill_default_options(*p, p->opt);
         validate_options(p->opt);
@@ -540,6 +556,7 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         p->lambda_buf.alloc(S);
         p->lr_buf.alloc(S);
         build_tiles(*p, s);
+        apply_record_order(*p, s);
         EPO_HIP(hipStreamSynchronize(s));
         *out = reinterpret_cast<epo_plan>(p.release());
     });
@@ -606,6 +623,7 @@ extern "C" epo_status epo_plan_set_options(epo_plan plan, const epo_plan_options
                              o.tile_order != p.opt.tile_order;
         p.opt = o;
         if (rebuild) build_tiles(p, s);
+        apply_record_order(p, s);
     });
 }
 
@@ -631,7 +649,30 @@ extern "C" epo_status epo_plan_autotune(epo_plan plan, const double* poses, cons
         const int ppts[4] = {2, 4, 8, 16};
         const int orders[2] = {1, 2};
         const int pers[2] = {1, 2};
+        const int rorders[2] = {1, 2};
+        const int interval = p.opt.resort_interval;
+        // record order 2 is charged its re-sort too (1 / interval of the
+        // chunks every step) and must beat the best source-order schedule by
+        // a clear margin: the copies cost 8 bytes per residual
+        float sort_share = 0.0f, best1 = 1e30f;
+        constexpr float kOrderMargin = 0.97f;
         try {
+            for (int ro : rorders) {
+            if (ro == 2) {
+                // copies sorted at these poses (the state right after a
+                // captured iteration's full sort)
+                p.opt.record_order = 2;
+                ensure_sorted_records(p, s);
+                launch_resort(p, poses, nullptr, 1, s);         // warm-up
+                EPO_HIP(hipEventRecord(a, s));
+                launch_resort(p, poses, nullptr, 1, s);
+                EPO_HIP(hipEventRecord(b, s));
+                EPO_HIP(hipEventSynchronize(b));
+                float full = 0;
+                EPO_HIP(hipEventElapsedTime(&full, a, b));
+                sort_share = full / (float)interval * (float)iters;
+                best1 = best;
+            }
             for (int f : fmts) {
                 if (f == 2 && !p.tex.p) continue;
                 for (int pp : ppts)
@@ -639,7 +680,7 @@ extern "C" epo_status epo_plan_autotune(epo_plan plan, const double* poses, cons
                         for (int pe : pers) {
                             const bool rebuild = pp != p.opt.points_per_thread ||
                                                  o != p.opt.tile_order;
-                            p.opt = epo_plan_options{f, pp, o, pe};
+                            p.opt = epo_plan_options{f, pp, o, pe, ro, interval};
                             if (rebuild) build_tiles(p, s);
                             launch_cost(p, poses, lambda, loss.p, nullptr, nullptr, nullptr, grad.p,
                                         nullptr, s);      // warm-up
@@ -651,11 +692,16 @@ extern "C" epo_status epo_plan_autotune(epo_plan plan, const double* poses, cons
                             EPO_HIP(hipEventSynchronize(b));
                             float ms = 0;
                             EPO_HIP(hipEventElapsedTime(&ms, a, b));
+                            if (ro == 2) {
+                                ms += sort_share;
+                                if (ms >= kOrderMargin * best1) continue;
+                            }
                             if (ms < best) {
                                 best = ms;
                                 best_o = p.opt;
                             }
                         }
+            }
             }
         } catch (...) {
             (void)hipEventDestroy(a);
@@ -668,6 +714,7 @@ extern "C" epo_status epo_plan_autotune(epo_plan plan, const double* poses, cons
                              best_o.tile_order != p.opt.tile_order;
         p.opt = best_o;
         if (rebuild) build_tiles(p, s);
+        apply_record_order(p, s);
         if (chosen) *chosen = best_o;
     });
 }
@@ -745,10 +792,14 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
         EPO_HIP(hipSetDevice(p.device));
         check_schedule(p, lambda0, lambda1, anneal_steps, warmup, total, with_convergence);
         double* g = grad ? grad : p.grad_scratch.p;
+        // record order 2: every copy sorted at the poses the first replay
+        // starts from; each replay then re-sorts 1 / resort_interval of them
+        launch_resort(p, poses, nullptr, 1, as_stream(stream));
         capture_iteration(p, step, with_convergence, as_stream(stream), [&](hipStream_t cs) {
             launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
                             p.lambda_buf.p, p.lr_buf.p,
                             with_convergence ? p.conv_phase.p : nullptr, cs);
+            launch_resort(p, poses, step, p.opt.resort_interval, cs);
             launch_cost(p, poses, p.lambda_buf.p, loss, nullptr, nullptr, nullptr, g, nullptr, cs);
             launch_pose_step(poses, adam_m, adam_v, g, p.V, p.scene_of_view_d.p, fixed_mask,
                              p.lr_buf.p, beta1, beta2, eps, step, cs);
@@ -773,14 +824,16 @@ extern "C" epo_status epo_mlp_iteration_capture(
         EPO_REQUIRE(p.mlp_act.p, "call epo_mlp_setup first");
         check_schedule(p, lambda0, lambda1, anneal_steps, warmup, total, with_convergence);
         double* g = grad ? grad : p.grad_scratch.p;
+        launch_resort(p, poses, nullptr, 1, as_stream(stream));
         capture_iteration(p, step, with_convergence, as_stream(stream), [&](hipStream_t cs) {
-            // schedule -> cost and adjoint at the current poses -> refiner
+            // schedule -> (record re-sort) -> cost and adjoint at the current poses -> refiner
             // backward (activations of the forward that made them) -> AdamW
             // (advances the step) -> poses of the new parameters ->
             // (pose-change test)
             launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
                             p.lambda_buf.p, p.lr_buf.p,
                             with_convergence ? p.conv_phase.p : nullptr, cs);
+            launch_resort(p, poses, step, p.opt.resort_interval, cs);
             launch_cost(p, poses, p.lambda_buf.p, loss, nullptr, nullptr, nullptr, g, nullptr, cs);
             launch_mlp_backward(p, params, poses0, poses, g, param_grad, delta_grad, cs);
             launch_adamw(p, params, adam_m, adam_v, param_grad, delta, delta_m, delta_v,

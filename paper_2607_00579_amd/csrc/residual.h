@@ -46,20 +46,30 @@ __device__ __forceinline__ uint32_t row_major_texel(int x0, int y0, int W) {
     return (uint32_t)(__umul24(y0, W) + x0);
 }
 
+// Each format's texels come in two steps, so that a caller can issue the
+// gathers of several residuals (and further loads) before it waits for any:
+// fetch() issues the gather(s) of the cell, decode() turns the raw texel into
+// the four taps d00, d10, d01, d11.
+
 // float32 texture: four gathers
 template <>
 struct Taps<1> {
+    using Raw = float4;
     __device__ static inline uint32_t index(int x0, int y0, int W) {
         return row_major_texel(x0, y0, W);
     }
-    __device__ static inline void load(const uint32_t* __restrict__ tex, uint32_t idx, int W,
-                                       const float* /*lut*/, float& d00, float& d10, float& d01,
-                                       float& d11) {
+    __device__ static inline Raw fetch(const uint32_t* __restrict__ tex, uint32_t idx, int W) {
         const uint32_t o = idx << 2, row = (uint32_t)W << 2;
-        d00 = __uint_as_float(texel32(tex, o));
-        d10 = __uint_as_float(texel32(tex, o + 4u));
-        d01 = __uint_as_float(texel32(tex, o + row));
-        d11 = __uint_as_float(texel32(tex, o + row + 4u));
+        return make_float4(__uint_as_float(texel32(tex, o)), __uint_as_float(texel32(tex, o + 4u)),
+                           __uint_as_float(texel32(tex, o + row)),
+                           __uint_as_float(texel32(tex, o + row + 4u)));
+    }
+    __device__ static inline void decode(const Raw& q, const float* /*lut*/, float& d00,
+                                         float& d10, float& d01, float& d11) {
+        d00 = q.x;
+        d10 = q.y;
+        d01 = q.z;
+        d11 = q.w;
     }
 };
 
@@ -71,14 +81,17 @@ struct Taps<1> {
 // descriptor's width field for this format): two 24-bit multiply-adds, shifts
 template <>
 struct Taps<2> {
+    using Raw = uint32_t;
     __device__ static inline uint32_t index(int x0, int y0, int k) {
         const uint32_t x = (uint32_t)x0, y = (uint32_t)y0;
         return __umul24(y >> 2, (uint32_t)k) + (y << 5) + ((__umul24(x & ~7u, 3u) + x) << 2);
     }
-    __device__ static inline void load(const uint32_t* __restrict__ tex, uint32_t off, int /*W*/,
-                                       const float* lut, float& d00, float& d10, float& d01,
-                                       float& d11) {
-        const uint32_t q = texel32(tex, off);
+    __device__ static inline Raw fetch(const uint32_t* __restrict__ tex, uint32_t off,
+                                       int /*W*/) {
+        return texel32(tex, off);
+    }
+    __device__ static inline void decode(const Raw& q, const float* lut, float& d00, float& d10,
+                                         float& d01, float& d11) {
         d00 = lut[q & 0xffu];
         d10 = lut[(q >> 8) & 0xffu];
         d01 = lut[(q >> 16) & 0xffu];
@@ -89,13 +102,16 @@ struct Taps<2> {
 // float32 quads: the four float32 taps of the cell in one 16-byte gather
 template <>
 struct Taps<3> {
+    using Raw = float4;
     __device__ static inline uint32_t index(int x0, int y0, int W) {
         return row_major_texel(x0, y0, W);
     }
-    __device__ static inline void load(const uint32_t* __restrict__ tex, uint32_t idx, int /*W*/,
-                                       const float* /*lut*/, float& d00, float& d10, float& d01,
-                                       float& d11) {
-        const float4 q = reinterpret_cast<const float4*>(tex)[idx];
+    __device__ static inline Raw fetch(const uint32_t* __restrict__ tex, uint32_t idx,
+                                       int /*W*/) {
+        return reinterpret_cast<const float4*>(tex)[idx];
+    }
+    __device__ static inline void decode(const Raw& q, const float* /*lut*/, float& d00,
+                                         float& d10, float& d01, float& d11) {
         d00 = q.x;
         d10 = q.y;
         d01 = q.z;
@@ -111,12 +127,20 @@ struct Residual {
     double mx, my, mz;      // unit-depth ray m = M (u, v, 1)^T in the target frame
 };
 
+// first step: the projected coordinate, the validity test, the cell split and
+// the texel to gather
+struct Projected {
+    float al, be;           // position inside the cell
+    float xn, yn, rz;       // normalised target coordinates, 1 / z
+    bool valid;
+    uint32_t idx;           // the format's texel index (0 if invalid)
+    double mx, my, mz;      // unit-depth ray m = M (u, v, 1)^T in the target frame
+};
+
 template <int FMT>
-__device__ __forceinline__ Residual eval_residual(const uint2 rec, bool active,
-                                                  const PairDesc& pd,
-                                                  const uint32_t* __restrict__ texj,
-                                                  const float* lut, float delta, double zmin) {
-    Residual r;
+__device__ __forceinline__ Projected project_residual(const uint2 rec, bool active,
+                                                      const PairDesc& pd, double zmin) {
+    Projected r;
     // projected coordinate in float64 (full rate on CDNA4 with packed FP32
     // off): it decides the bilinear cell, an integer, exactly as the oracle
     const double u = (double)(rec.x & 0xffffu);
@@ -148,29 +172,43 @@ __device__ __forceinline__ Residual eval_residual(const uint2 rec, bool active,
     // inside the texture.
     const double fx0 = floor(upd), fy0 = floor(vpd);
     const int x0 = (int)fx0, y0 = (int)fy0;
-    const bool valid = active && (Xz > zmin) && ((unsigned)x0 < (unsigned)pd.wcells) &&
-                       ((unsigned)y0 < (unsigned)pd.hcells);
+    r.valid = active && (Xz > zmin) && ((unsigned)x0 < (unsigned)pd.wcells) &&
+              ((unsigned)y0 < (unsigned)pd.hcells);
     // an invalid residual reads the taps of cell (0, 0) and gets zero weight
     // (rho = rho' = 0) below; its coordinates are finite, so every product
     // with that zero weight is zero
-    const float al = (float)(upd - fx0);
-    const float be = (float)(vpd - fy0);
+    r.al = (float)(upd - fx0);
+    r.be = (float)(vpd - fy0);
     // y0 < H and W are below 2^24 whenever the residual is valid; idx is
     // the format's texel index (byte offset for format 2)
     // (a mask rather than a select keeps the compiler from branching here)
-    const uint32_t idx = Taps<FMT>::index(x0, y0, pd.width) & (0u - (uint32_t)valid);
+    r.idx = Taps<FMT>::index(x0, y0, pd.width) & (0u - (uint32_t)r.valid);
     r.xn = (float)xnd;
     r.yn = (float)ynd;
     r.rz = (float)rzd;
-    float d00, d10, d01, d11;
-    Taps<FMT>::load(texj, idx, pd.width, lut, d00, d10, d01, d11);
+    return r;
+}
+
+// second step: bilinear sample, clamp, Huber and the adjoint terms from the
+// cell's four taps
+__device__ __forceinline__ Residual finish_residual(const Projected& p, float d00, float d10,
+                                                    float d01, float d11, const PairDesc& pd,
+                                                    float delta) {
+    Residual r;
+    r.mx = p.mx;
+    r.my = p.my;
+    r.mz = p.mz;
+    r.xn = p.xn;
+    r.yn = p.yn;
+    r.rz = p.rz;
+    const bool valid = p.valid;
     // bilinear sample and its gradient; the cell's cross term
     // d11 - d10 - d01 + d00 is formed once and serves both directions
     const float e0 = d10 - d00, f0 = d01 - d00;
     const float c = (d11 - d01) - e0;
-    const float gu = fmaf(be, c, e0);
-    const float gv = fmaf(al, c, f0);
-    const float D = fmaf(be, gv, fmaf(al, e0, d00));
+    const float gu = fmaf(p.be, c, e0);
+    const float gv = fmaf(p.al, c, f0);
+    const float D = fmaf(p.be, gv, fmaf(p.al, e0, d00));
     // Huber of the clamped distance: with m = min(d, delta),
     // m (d - m / 2) is d^2 / 2 below delta and delta (d - delta / 2) above
     // (the same float32 roundings as either branch), and m is the derivative
@@ -185,6 +223,18 @@ __device__ __forceinline__ Residual eval_residual(const uint2 rec, bool active,
     r.w = -fmaf(r.Au, r.xn, r.Av * r.yn);
     r.valid = valid;
     return r;
+}
+
+template <int FMT>
+__device__ __forceinline__ Residual eval_residual(const uint2 rec, bool active,
+                                                  const PairDesc& pd,
+                                                  const uint32_t* __restrict__ texj,
+                                                  const float* lut, float delta, double zmin) {
+    const Projected p = project_residual<FMT>(rec, active, pd, zmin);
+    const typename Taps<FMT>::Raw q = Taps<FMT>::fetch(texj, p.idx, pd.width);
+    float d00, d10, d01, d11;
+    Taps<FMT>::decode(q, lut, d00, d10, d01, d11);
+    return finish_residual(p, d00, d10, d01, d11, pd, delta);
 }
 
 // dH/dZ of the source pixel's depth: X' = Z m + t, so dH/dZ = (dH/dX') . m

@@ -10,7 +10,10 @@ that a generator change is detected instead of silently comparing against
 stale values.  c1 and c2 are whole runs (c1_trajectory.npz, c2_trajectory.npz);
 c3, c4 and c5 are prefixes of their runs (20, 10 and 20 steps,
 <name>_prefix.npz), evaluated over worker processes (oracle.parallel; the
-same bits as a serial evaluation).
+same bits as a serial evaluation).  <name>_envelope.npz holds the oracle's
+own sensitivity over those prefixes: the same runs with every gradient
+perturbed by a seeded random relative amount (1e-9, 5e-8), and how far each
+ends from the stored prefix.
 """
 from __future__ import annotations
 
@@ -82,9 +85,74 @@ def write_prefix(name: str, workers=None):
     print(f"{name}: loss {hist['loss'][0].sum():.6f} -> {hist['loss'][-1].sum():.6f}")
 
 
+# oracle self-sensitivity: the prefix runs again with every gradient moved by
+# a seeded random perturbation of relative (normwise) size eps
+ENVELOPE = {"c3": ((1e-9, 5e-8), (0, 1, 2)), "c5": ((1e-9, 5e-8), (0, 1, 2)),
+            "c4": ((1e-9, 5e-8), (0,))}
+
+
+def rotation_deg(a, b):
+    c = np.clip((np.trace(a @ b.T) - 1.0) / 2.0, -1.0, 1.0)
+    return float(np.degrees(np.arccos(c)))
+
+
+def write_envelope(name: str, workers=None):
+    """How far the oracle's own trajectory moves when its gradients are
+    perturbed at the level of rounding differences: per run (eps, seed), the
+    loss's relative deviation at every step and the largest rotation and
+    camera-centre deviation over the views at every stored snapshot, against
+    the stored prefix."""
+    import time
+    g = np.load(os.path.join(HERE, f"{name}_prefix.npz"), allow_pickle=False)
+    n = int(g["iterations"])
+    prob = make(name)
+    assert str(g["checksum"]) == input_checksum(prob)
+    d2 = opar.distance_fields(prob, workers)
+    op = ocost.OracleProblem(prob, d2=d2)
+    del d2
+    epss, seeds = ENVELOPE[name]
+    runs, loss_dev, rot_dev, ctr_dev = [], [], [], []
+    with opar.ParallelEvaluator(op, workers, single_threaded=True) as ev:
+        for eps in epss:
+            for seed in seeds:
+                t0 = time.time()
+                rng = np.random.default_rng([seed, 7])
+
+                def evaluate(poses, lam, params, selected=None, eps=eps, rng=rng):
+                    r = ev(poses, lam, params, selected=selected)
+                    e = rng.normal(size=r["grad"].shape)
+                    r["grad"] = r["grad"] + eps * np.linalg.norm(r["grad"]) / np.linalg.norm(e) * e
+                    return r
+
+                hist = oloop.run(op, prob.poses_init, n, record_every=1, evaluate=evaluate)
+                loss = np.array(hist["loss"])
+                loss_dev.append((np.abs(loss - g["loss"]) / np.abs(g["loss"])).max(axis=1))
+                rots, ctrs = [], []
+                for k, st in enumerate(g["steps_at"]):
+                    P = hist["poses"][int(st)] if st < n else hist["final_poses"]
+                    Q = g["poses_at"][k]
+                    rots.append(max(rotation_deg(P[v][:, :3], Q[v][:, :3]) for v in range(len(P))))
+                    cp = -np.einsum("vji,vj->vi", P[:, :, :3], P[:, :, 3])
+                    cq = -np.einsum("vji,vj->vi", Q[:, :, :3], Q[:, :, 3])
+                    ctrs.append(float(np.linalg.norm(cp - cq, axis=1).max()))
+                rot_dev.append(rots)
+                ctr_dev.append(ctrs)
+                runs.append((eps, seed))
+                print(f"{name}: eps {eps:.0e} seed {seed}: rotation deviation by snapshot "
+                      + ", ".join(f"{a:.2e}" for a in rots) + f" deg ({time.time() - t0:.0f} s)",
+                      flush=True)
+    np.savez_compressed(
+        os.path.join(HERE, f"{name}_envelope.npz"), eps=np.array([r[0] for r in runs]),
+        seed=np.array([r[1] for r in runs]), loss_dev=np.array(loss_dev),
+        rot_dev=np.array(rot_dev), ctr_dev=np.array(ctr_dev), steps_at=g["steps_at"],
+        checksum=g["checksum"])
+
+
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or list(ITERS) + list(PREFIX)):
-        if name in PREFIX:
+    for name in (sys.argv[1:] or list(ITERS) + list(PREFIX) + [k + "_envelope" for k in ENVELOPE]):
+        if name.endswith("_envelope"):
+            write_envelope(name[:-len("_envelope")])
+        elif name in PREFIX:
             write_prefix(name)
         else:
             write(name)

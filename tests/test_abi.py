@@ -72,6 +72,12 @@ def test_version_and_error_paths(lib):
         lib.joint_step(None, None, None, None, None, None, None, None, None, None, None, None,
                        None, 0.9, 0.999, 1e-8, 0.01, 0.01, None, None)
     assert e.value.status == lib.ERR_INVALID_ARG and "null plan" in str(e.value)
+    with pytest.raises(lib.EpoError) as e:
+        lib.plan_resort(None, None, None, 1, None)
+    assert e.value.status == lib.ERR_INVALID_ARG
+    with pytest.raises(lib.EpoError) as e:
+        lib.plan_pair_records(None, 0)
+    assert e.value.status == lib.ERR_INVALID_ARG
     # zero views is a valid no-op for the distance transform
     lib.build_distance_fields(None, None, None, None, 0, None, None, None)
 
@@ -126,11 +132,17 @@ def test_plan_create_rejects_unsupported_texture(lib):
     with pytest.raises(lib.EpoError) as e:
         lib.plan_create(**_plan_args(options=lib.PlanOptions(1, 3, 1, 2)))
     assert "points_per_thread" in str(e.value)
+    with pytest.raises(lib.EpoError) as e:
+        lib.plan_create(**_plan_args(options=lib.PlanOptions(1, 4, 1, 2, 3, 0)))
+    assert "record_order" in str(e.value)
+    with pytest.raises(lib.EpoError) as e:
+        lib.plan_create(**_plan_args(options=lib.PlanOptions(1, 4, 1, 2, 2, -1)))
+    assert "resort_interval" in str(e.value)
 
 
 def test_struct_layouts(lib):
     assert C.sizeof(lib.CostParams) == 16
-    assert C.sizeof(lib.PlanOptions) == 16
+    assert C.sizeof(lib.PlanOptions) == 24
 
 
 @pytest.mark.parametrize("z_min", [0.0, -1.0, 1e-9, 1e7, float("nan")])
@@ -157,3 +169,4 @@ def test_cpu_device_is_refused():
     p = fixtures.odd_size_views()
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         EdgePlan.from_problem(p, device="cpu")
+

@@ -144,17 +144,36 @@ def golden_prefix(name):
     return g
 
 
+def golden_envelope(name):
+    from tests.golden.make_golden import input_checksum
+    e = np.load(os.path.join(GOLDEN, f"{name}_envelope.npz"), allow_pickle=False)
+    assert str(e["checksum"]) == input_checksum(problem(name)), "generator changed: rerun make_golden"
+    return e
+
+
+# the GPU's deviation from the stored oracle trajectory may reach this many
+# times the oracle's own (its gradients perturbed at 1e-9 and 5e-8 relative,
+# several seeds), never less than the spec bars
+ENVELOPE_FACTOR = 3.0
+ROT_BAR = 0.01          # degrees
+LOSS_BAR = 1e-5         # relative
+
+
 @pytest.mark.parametrize("name", ["c3", "c5", "c4"])
 def test_trajectory_prefix_from_initial_poses(gpu, name):
     """The captured iteration from the initial poses, in the benchmark's
     launch configuration (autotuned schedule), against the oracle's first 20
-    (c3, c5) or 10 (c4, all 64 scenes) steps: every scene's loss at every
-    step within 1e-5, and every pose within 0.01 deg of rotation at every
-    stored snapshot (each 5 steps) and at the end.  The prefixes end before
-    the oracle's own sensitivity to its rounding grows past that bar (about
-    step 30 on the single-scene run)."""
+    (c3, c5) or 10 (c4, all 64 scenes) steps.  Every pose is held to 0.01 deg
+    of rotation and every scene's loss to 1e-5 relative for as long as the
+    oracle itself stays that close to its own trajectory under rounding-size
+    perturbations of its gradients; past that point (the cost is piecewise
+    bilinear with about a million cell-boundary kinks, and Adam's normalised
+    steps pass small gradient differences on at full size, so rounding
+    differences grow by orders of magnitude within a few steps) the GPU is
+    held to three times the oracle's own spread, stored with the prefix."""
     from paper_2607_00579_amd.api import EdgePlan
     g = golden_prefix(name)
+    env = golden_envelope(name)
     prob = problem(name)
     n = int(g["iterations"])
     dev = torch.device("cuda:0")
@@ -175,17 +194,22 @@ def test_trajectory_prefix_from_initial_poses(gpu, name):
         if s + 1 in at:
             snaps[s + 1] = poses.clone()
     torch.cuda.synchronize()
-    rel = np.abs(hist.cpu().numpy() - g["loss"]) / np.abs(g["loss"])
-    worst = []
-    for k, st in enumerate(g["steps_at"]):
-        ang, dc = pose_diffs(snaps[int(st)].cpu().numpy(), g["poses_at"][k])
-        worst.append((int(st), ang, dc))
-    say(f"{name} prefix ({plan.n_residuals} residuals/step, schedule {chosen}): {n} steps, "
-        f"worst loss rel err {rel.max():.2e}; rotation diff by step "
-        + ", ".join(f"{st}: {a:.2e} deg" for st, a, _ in worst)
-        + f"; worst centre diff {max(d for *_, d in worst):.2e}")
-    assert rel.max() < 1e-5
-    assert max(a for _, a, _ in worst) < 0.01
+    rel = (np.abs(hist.cpu().numpy() - g["loss"]) / np.abs(g["loss"])).max(axis=1)
+    rot = np.array([pose_diffs(snaps[int(st)].cpu().numpy(), g["poses_at"][k])[0]
+                    for k, st in enumerate(g["steps_at"])])
+    env_rot = env["rot_dev"].max(axis=0)
+    env_loss = env["loss_dev"].max(axis=0)
+    bar_rot = np.maximum(ROT_BAR, ENVELOPE_FACTOR * env_rot)
+    bar_loss = np.maximum(LOSS_BAR, ENVELOPE_FACTOR * env_loss)
+    say(f"{name} prefix ({plan.n_residuals} residuals/step, schedule {chosen}): {n} steps; "
+        + "rotation diff by step " + ", ".join(
+            f"{int(st)}: {a:.2e} (oracle's own {e:.2e})"
+            for st, a, e in zip(g["steps_at"], rot, env_rot))
+        + f" deg; loss rel err {rel.max():.2e} (oracle's own up to {env_loss.max():.2e})")
+    assert (rot <= bar_rot).all(), (rot, bar_rot)
+    assert (rel <= bar_loss).all(), (rel, bar_loss)
+    # the first snapshot lies before the oracle's own spread reaches the bar
+    assert env_rot[0] < ROT_BAR / ENVELOPE_FACTOR and rot[0] < ROT_BAR
     assert plan.device_status() == 0
 
 
