@@ -407,6 +407,26 @@ EPO_API epo_status epo_build_viewgraph(int32_t n_views, const int32_t* width, co
                                double min_fraction, double z_min, int32_t* consistent,
                                int32_t* total, uint8_t* valid, void* stream);
 
+/* The same call without any allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Arguments, results and errors are those of
+ * epo_build_viewgraph (bitwise the same counts).  The staging of the
+ * candidates, the work list and the per-view sizes, offsets and intrinsics
+ * lives in a static device array of 4 MiB that every GPU the library runs on
+ * holds until the process ends; a call whose staging exceeds it fails with
+ * EPO_ERR_INVALID_ARG (about 4 MiB / 8 bytes of candidates plus grid chunks of
+ * 1024 points, e.g. 496 candidates of 518 x 518 views at stride 1).  Calls
+ * that overlap on one GPU (other streams or threads) share that array and
+ * race.  Copies the host arrays into it and synchronises `stream`. */
+EPO_API epo_status epo_build_viewgraph_noalloc(int32_t n_views, const int32_t* width,
+                                               const int32_t* height, const float* K,
+                                               const int64_t* view_offset, const float* depth,
+                                               const double* poses, const int32_t* candidates,
+                                               int32_t n_candidates, int32_t stride, double tau,
+                                               double min_fraction, double z_min,
+                                               int32_t* consistent, int32_t* total,
+                                               uint8_t* valid, void* stream);
+
 /* ---------------------------------------------------------------------------
  * 3c. Stochastic viewgraph sub-sampling (paper supplementary Sec. "Stochastic
  * viewgraph sub-sampling"; pair budget M of Alg. EPO.Forward).  With a budget

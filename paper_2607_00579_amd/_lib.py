@@ -64,6 +64,7 @@ _SIGS = {
     "epo_plan_set_refinement": [P, P, P, P, P],
     "epo_plan_set_pair_sampling": [P, I32, C.c_uint64, P, P],
     "epo_build_viewgraph": [I32, P, P, P, P, P, P, P, I32, I32, F64, F64, F64, P, P, P, P],
+    "epo_build_viewgraph_noalloc": [I32, P, P, P, P, P, P, P, I32, I32, F64, F64, F64, P, P, P, P],
     "epo_mlp_setup": [P, P],
     "epo_mlp_forward": [P, P, P, P, P, P],
     "epo_mlp_backward": [P, P, P, P, P, P, P, P],
@@ -200,6 +201,16 @@ def build_viewgraph(n_views, width, height, K, view_offset, depth, poses, candid
                                       _ptr(view_offset), _ptr(depth), _ptr(poses),
                                       _ptr(candidates), n_candidates, stride, tau, min_fraction,
                                       z_min, _ptr(consistent), _ptr(total), _ptr(valid), stream))
+
+
+def build_viewgraph_noalloc(n_views, width, height, K, view_offset, depth, poses, candidates,
+                            n_candidates, stride, tau, min_fraction, z_min, consistent, total,
+                            valid, stream):
+    _check(load().epo_build_viewgraph_noalloc(n_views, _ptr(width), _ptr(height), _ptr(K),
+                                              _ptr(view_offset), _ptr(depth), _ptr(poses),
+                                              _ptr(candidates), n_candidates, stride, tau,
+                                              min_fraction, z_min, _ptr(consistent), _ptr(total),
+                                              _ptr(valid), stream))
 
 
 MLP_PARAMS = 69260

@@ -15,6 +15,7 @@
 // One workgroup per (candidate, chunk of 1024 grid points), four points per
 // thread; per-workgroup counts are added to the candidate's integer counters
 // with atomics (integer sums: the result does not depend on the order).
+#include <mutex>
 #include <vector>
 
 #include "epo_internal.h"
@@ -139,6 +140,123 @@ __global__ __launch_bounds__(256) void viewgraph_valid_kernel(const int32_t* __r
     if (k < n) valid[k] = (tot[k] > 0 && (double)cons[k] >= min_fraction * (double)tot[k]) ? 1 : 0;
 }
 
+// host-side staging of one call: validated arguments, per-view sizes, the
+// candidates and the (candidate, grid chunk) work list
+struct ViewgraphStaging {
+    std::vector<int32_t> wh;
+    std::vector<int2> cand, blocks;
+};
+
+void prepare_viewgraph(int32_t n_views, const int32_t* width, const int32_t* height,
+                       const float* K, const int64_t* view_offset, const float* depth,
+                       const double* poses, const int32_t* candidates, int32_t n_candidates,
+                       int32_t stride, double tau, double min_fraction, double z_min,
+                       int32_t* consistent, int32_t* total, ViewgraphStaging& h) {
+    EPO_REQUIRE(n_views >= 1, "n_views must be >= 1");
+    EPO_REQUIRE(n_candidates >= 0, "n_candidates must be >= 0");
+    EPO_REQUIRE(width && height && K && view_offset, "null host argument");
+    EPO_REQUIRE(n_candidates == 0 || (candidates && depth && poses && consistent && total),
+                "null argument");
+    EPO_REQUIRE(stride >= 1 && stride <= 1024, "stride must be in [1, 1024]");
+    EPO_REQUIRE(tau > 0 && std::isfinite(tau), "tau must be > 0");
+    EPO_REQUIRE(min_fraction >= 0 && min_fraction <= 1, "min_fraction must be in [0, 1]");
+    EPO_REQUIRE(z_min > 0 && std::isfinite(z_min), "z_min must be > 0");
+    h.wh.assign(2 * (size_t)n_views, 0);
+    for (int v = 0; v < n_views; ++v) {
+        EPO_REQUIRE(width[v] >= 1 && width[v] <= EPO_MAX_SIDE && height[v] >= 1 &&
+                        height[v] <= EPO_MAX_SIDE,
+                    "view " + std::to_string(v) + ": side out of [1, 16384]");
+        EPO_REQUIRE(view_offset[v] >= 0, "view " + std::to_string(v) + ": negative offset");
+        EPO_REQUIRE(std::isfinite(K[4 * v]) && std::isfinite(K[4 * v + 1]) &&
+                        K[4 * v] != 0.0f && K[4 * v + 1] != 0.0f &&
+                        std::isfinite(K[4 * v + 2]) && std::isfinite(K[4 * v + 3]),
+                    "view " + std::to_string(v) + ": intrinsics must be finite, focal != 0");
+        h.wh[2 * v] = width[v];
+        h.wh[2 * v + 1] = height[v];
+    }
+    h.cand.assign((size_t)n_candidates, make_int2(0, 0));
+    h.blocks.clear();
+    for (int c = 0; c < n_candidates; ++c) {
+        const int i = candidates[2 * c], j = candidates[2 * c + 1];
+        EPO_REQUIRE(i >= 0 && i < n_views && j >= 0 && j < n_views,
+                    "candidate " + std::to_string(c) + ": view index out of range");
+        h.cand[c] = make_int2(i, j);
+        const int64_t pts = (int64_t)((width[i] + stride - 1) / stride) *
+                            ((height[i] + stride - 1) / stride);
+        for (int64_t k = 0; k < pts; k += kChunk) h.blocks.push_back(make_int2(c, (int)(k / kChunk)));
+    }
+    EPO_REQUIRE((int64_t)h.blocks.size() < (int64_t)INT32_MAX, "too many grid chunks");
+}
+
+// device copies of the staging arrays (wherever they live), then the kernels;
+// synchronises the stream (the host staging is freed on return)
+void run_viewgraph(const ViewgraphStaging& h, int32_t n_views, const float* K,
+                   const int64_t* view_offset, const float* depth, const double* poses,
+                   int32_t n_candidates, int32_t stride, double tau, double min_fraction,
+                   double z_min, int32_t* consistent, int32_t* total, uint8_t* valid, int2* cand_d,
+                   int2* blocks_d, int32_t* wh_d, int64_t* off_d, float* K_d, hipStream_t s) {
+    EPO_HIP(hipMemcpyAsync(cand_d, h.cand.data(), sizeof(int2) * h.cand.size(),
+                           hipMemcpyHostToDevice, s));
+    if (!h.blocks.empty())
+        EPO_HIP(hipMemcpyAsync(blocks_d, h.blocks.data(), sizeof(int2) * h.blocks.size(),
+                               hipMemcpyHostToDevice, s));
+    EPO_HIP(hipMemcpyAsync(wh_d, h.wh.data(), sizeof(int32_t) * h.wh.size(),
+                           hipMemcpyHostToDevice, s));
+    EPO_HIP(hipMemcpyAsync(off_d, view_offset, sizeof(int64_t) * n_views, hipMemcpyHostToDevice,
+                           s));
+    EPO_HIP(hipMemcpyAsync(K_d, K, sizeof(float) * 4 * n_views, hipMemcpyHostToDevice, s));
+    viewgraph_zero_kernel<<<(unsigned)ceil_div(n_candidates, 256), 256, 0, s>>>(
+        consistent, total, n_candidates);
+    EPO_CHECK_LAUNCH();
+    if (!h.blocks.empty()) {
+        viewgraph_kernel<<<(unsigned)h.blocks.size(), 256, 0, s>>>(
+            blocks_d, cand_d, wh_d, off_d, K_d, poses, depth, stride, tau * tau, z_min,
+            consistent, total);
+        EPO_CHECK_LAUNCH();
+    }
+    if (valid) {
+        viewgraph_valid_kernel<<<(unsigned)ceil_div(n_candidates, 256), 256, 0, s>>>(
+            consistent, total, min_fraction, n_candidates, valid);
+        EPO_CHECK_LAUNCH();
+    }
+    EPO_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// staging without allocation: a file-scope device array of a fixed size.
+// Host code never passes the array's name to a kernel or a copy (there it is
+// a host-side stand-in); it takes the array's device address once per device
+// with hipGetSymbolAddress and uses that address.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticStagingBytes = size_t(4) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_staging_mu;
+void* g_staging_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticStagingBytes];
+
+namespace {
+
+// the current device's copy of `scratch` (each GPU holds its own, at its own
+// address), looked up on the first call on that device
+char* static_staging() {
+    int dev = 0;
+    EPO_HIP(hipGetDevice(&dev));
+    EPO_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_staging_mu);
+    if (!g_staging_ptr[dev]) {
+        void* ptr = nullptr;
+        EPO_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        EPO_REQUIRE(ptr != nullptr, "no device address for the static staging array");
+        g_staging_ptr[dev] = ptr;
+    }
+    return static_cast<char*>(g_staging_ptr[dev]);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
 }  // namespace
 }  // namespace epo
 
@@ -153,75 +271,57 @@ extern "C" epo_status epo_build_viewgraph(int32_t n_views, const int32_t* width,
                                           int32_t* consistent, int32_t* total, uint8_t* valid,
                                           void* stream) {
     return guarded([&] {
-        EPO_REQUIRE(n_views >= 1, "n_views must be >= 1");
-        EPO_REQUIRE(n_candidates >= 0, "n_candidates must be >= 0");
-        EPO_REQUIRE(width && height && K && view_offset, "null host argument");
-        EPO_REQUIRE(n_candidates == 0 || (candidates && depth && poses && consistent && total),
-                    "null argument");
-        EPO_REQUIRE(stride >= 1 && stride <= 1024, "stride must be in [1, 1024]");
-        EPO_REQUIRE(tau > 0 && std::isfinite(tau), "tau must be > 0");
-        EPO_REQUIRE(min_fraction >= 0 && min_fraction <= 1, "min_fraction must be in [0, 1]");
-        EPO_REQUIRE(z_min > 0 && std::isfinite(z_min), "z_min must be > 0");
-        std::vector<int32_t> wh(2 * (size_t)n_views);
-        for (int v = 0; v < n_views; ++v) {
-            EPO_REQUIRE(width[v] >= 1 && width[v] <= EPO_MAX_SIDE && height[v] >= 1 &&
-                            height[v] <= EPO_MAX_SIDE,
-                        "view " + std::to_string(v) + ": side out of [1, 16384]");
-            EPO_REQUIRE(view_offset[v] >= 0, "view " + std::to_string(v) + ": negative offset");
-            EPO_REQUIRE(std::isfinite(K[4 * v]) && std::isfinite(K[4 * v + 1]) &&
-                            K[4 * v] != 0.0f && K[4 * v + 1] != 0.0f &&
-                            std::isfinite(K[4 * v + 2]) && std::isfinite(K[4 * v + 3]),
-                        "view " + std::to_string(v) + ": intrinsics must be finite, focal != 0");
-            wh[2 * v] = width[v];
-            wh[2 * v + 1] = height[v];
-        }
-        std::vector<int2> cand((size_t)n_candidates), blocks;
-        for (int c = 0; c < n_candidates; ++c) {
-            const int i = candidates[2 * c], j = candidates[2 * c + 1];
-            EPO_REQUIRE(i >= 0 && i < n_views && j >= 0 && j < n_views,
-                        "candidate " + std::to_string(c) + ": view index out of range");
-            cand[c] = make_int2(i, j);
-            const int64_t pts = (int64_t)((width[i] + stride - 1) / stride) *
-                                ((height[i] + stride - 1) / stride);
-            for (int64_t k = 0; k < pts; k += kChunk) blocks.push_back(make_int2(c, (int)(k / kChunk)));
-        }
-        EPO_REQUIRE((int64_t)blocks.size() < (int64_t)INT32_MAX, "too many grid chunks");
+        ViewgraphStaging h;
+        prepare_viewgraph(n_views, width, height, K, view_offset, depth, poses, candidates,
+                          n_candidates, stride, tau, min_fraction, z_min, consistent, total, h);
         if (n_candidates == 0) return;
-        hipStream_t s = as_stream(stream);
         DevBuf<int2> cand_d, blocks_d;
         DevBuf<int32_t> wh_d;
         DevBuf<int64_t> off_d;
         DevBuf<float> K_d;
-        cand_d.alloc(cand.size());
-        blocks_d.alloc(std::max<size_t>(blocks.size(), 1));
-        wh_d.alloc(wh.size());
+        cand_d.alloc(h.cand.size());
+        blocks_d.alloc(std::max<size_t>(h.blocks.size(), 1));
+        wh_d.alloc(h.wh.size());
         off_d.alloc(n_views);
         K_d.alloc(4 * (size_t)n_views);
-        EPO_HIP(hipMemcpyAsync(cand_d.p, cand.data(), sizeof(int2) * cand.size(),
-                               hipMemcpyHostToDevice, s));
-        if (!blocks.empty())
-            EPO_HIP(hipMemcpyAsync(blocks_d.p, blocks.data(), sizeof(int2) * blocks.size(),
-                                   hipMemcpyHostToDevice, s));
-        EPO_HIP(hipMemcpyAsync(wh_d.p, wh.data(), sizeof(int32_t) * wh.size(),
-                               hipMemcpyHostToDevice, s));
-        EPO_HIP(hipMemcpyAsync(off_d.p, view_offset, sizeof(int64_t) * n_views,
-                               hipMemcpyHostToDevice, s));
-        EPO_HIP(hipMemcpyAsync(K_d.p, K, sizeof(float) * 4 * n_views, hipMemcpyHostToDevice, s));
-        viewgraph_zero_kernel<<<(unsigned)ceil_div(n_candidates, 256), 256, 0, s>>>(
-            consistent, total, n_candidates);
-        EPO_CHECK_LAUNCH();
-        if (!blocks.empty()) {
-            viewgraph_kernel<<<(unsigned)blocks.size(), 256, 0, s>>>(
-                blocks_d.p, cand_d.p, wh_d.p, off_d.p, K_d.p, poses, depth, stride, tau * tau,
-                z_min, consistent, total);
-            EPO_CHECK_LAUNCH();
-        }
-        if (valid) {
-            viewgraph_valid_kernel<<<(unsigned)ceil_div(n_candidates, 256), 256, 0, s>>>(
-                consistent, total, min_fraction, n_candidates, valid);
-            EPO_CHECK_LAUNCH();
-        }
-        // the staging buffers are freed on return
-        EPO_HIP(hipStreamSynchronize(s));
+        run_viewgraph(h, n_views, K, view_offset, depth, poses, n_candidates, stride, tau,
+                      min_fraction, z_min, consistent, total, valid, cand_d.p, blocks_d.p, wh_d.p,
+                      off_d.p, K_d.p, as_stream(stream));
+    });
+}
+
+extern "C" epo_status epo_build_viewgraph_noalloc(
+    int32_t n_views, const int32_t* width, const int32_t* height, const float* K,
+    const int64_t* view_offset, const float* depth, const double* poses,
+    const int32_t* candidates, int32_t n_candidates, int32_t stride, double tau,
+    double min_fraction, double z_min, int32_t* consistent, int32_t* total, uint8_t* valid,
+    void* stream) {
+    return guarded([&] {
+        ViewgraphStaging h;
+        prepare_viewgraph(n_views, width, height, K, view_offset, depth, poses, candidates,
+                          n_candidates, stride, tau, min_fraction, z_min, consistent, total, h);
+        if (n_candidates == 0) return;
+        // the staging arrays one after another, each 256-byte aligned
+        const size_t o_cand = 0;
+        const size_t o_blk = align256(o_cand + sizeof(int2) * h.cand.size());
+        const size_t o_wh = align256(o_blk + sizeof(int2) * std::max<size_t>(h.blocks.size(), 1));
+        const size_t o_off = align256(o_wh + sizeof(int32_t) * h.wh.size());
+        const size_t o_K = align256(o_off + sizeof(int64_t) * (size_t)n_views);
+        const size_t need = o_K + sizeof(float) * 4 * (size_t)n_views;
+        EPO_REQUIRE(need <= kStaticStagingBytes,
+                    "the call needs " + std::to_string(need) + " bytes of staging (" +
+                        std::to_string(n_candidates) + " candidates, " +
+                        std::to_string(h.blocks.size()) + " grid chunks, " +
+                        std::to_string(n_views) + " views), more than the " +
+                        std::to_string(kStaticStagingBytes) +
+                        " of the no-allocation form: use epo_build_viewgraph, fewer "
+                        "candidates or a larger stride");
+        char* base = static_staging();
+        run_viewgraph(h, n_views, K, view_offset, depth, poses, n_candidates, stride, tau,
+                      min_fraction, z_min, consistent, total, valid,
+                      reinterpret_cast<int2*>(base + o_cand), reinterpret_cast<int2*>(base + o_blk),
+                      reinterpret_cast<int32_t*>(base + o_wh),
+                      reinterpret_cast<int64_t*>(base + o_off), reinterpret_cast<float*>(base + o_K),
+                      as_stream(stream));
     });
 }

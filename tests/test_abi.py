@@ -170,3 +170,16 @@ def test_cpu_device_is_refused():
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         EdgePlan.from_problem(p, device="cpu")
 
+
+def test_noalloc_viewgraph_rejects_staging_beyond_its_array(lib):
+    """Three 16384 x 16384 views at grid stride 1 need 786432 work chunks of
+    staging, more than the 4 MiB static array: refused on the host."""
+    _host_only()
+    w = np.full(3, 16384, np.int32)
+    K = np.tile(np.array([1000, 1000, 8191.5, 8191.5], np.float32), 3)
+    off = np.arange(3, dtype=np.int64) * 16384 * 16384
+    cand = np.array([[0, 1], [0, 2], [1, 2]], np.int32)
+    with pytest.raises(lib.EpoError) as e:
+        lib.build_viewgraph_noalloc(3, w, w, K, off, 1, 1, cand, 3, 1, 3.0, 0.125, 1e-4, 1, 1,
+                                    None, None)
+    assert e.value.status == lib.ERR_INVALID_ARG and "no-allocation" in str(e.value)
