@@ -31,6 +31,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_RESIDUAL = 24
+# floating-point operations of one residual and its adjoint terms (forward,
+# adjoint and accumulation, an FMA as two; validity and index arithmetic not
+# counted), the figure the hot-path scope table states per residual
+FLOPS_PER_RESIDUAL = 85
+# vector peak of the non-packed float32 / float64 VALU: 256 CUs x 4 SIMDs x 16
+# lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s; issue: one wave64 instruction per
+# SIMD every 4 cycles = 614.4 G wave-instructions/s
+VALU_PEAK_TFLOPS = 78.6
+VALU_ISSUE_PEAK_G = 614.4
 METRIC = "edge residual+grad evals/s and ms/iter, fused adjoint vs autograd, 1 GPU"
 WORKLOADS = {
     "c4": "batching: 64 scenes, views U{4..48}, 256x192..1024x768, 5k-60k edge px/view, "
@@ -64,18 +73,113 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def load_counter_records() -> list:
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return []
+    return data.get("records", []) if isinstance(data, dict) else []
+
+
 def measured_counters(workload: str, options: dict, n_residuals: int):
     """The committed PMC summary of the fused kernel, if it was taken on the
     current kernel source with the same workload and schedule."""
-    try:
-        with open(TRAFFIC_FILE) as fh:
-            rec = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if (rec.get("kernel_hash") != kernel_source_hash() or rec.get("workload") != workload
-            or rec.get("options") != options or rec.get("n_residuals") != n_residuals):
-        return None
-    return rec
+    for rec in load_counter_records():
+        if (rec.get("kernel_hash") == kernel_source_hash() and rec.get("workload") == workload
+                and rec.get("options") == options and rec.get("n_residuals") == n_residuals):
+            return rec
+    return None
+
+
+# rocprofv3 --pmc passes of the fused kernel, one counter set per run; the
+# directory names summarize_counters() expects under its argument
+COUNTER_PASSES = {
+    "fetch": "FETCH_SIZE",
+    "write": "WRITE_SIZE",
+    "tcc": "TCC_HIT_sum TCC_MISS_sum TCC_REQ_sum TCC_BUSY_sum GRBM_GUI_ACTIVE",
+    "sq": "SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_LDS "
+          "SQ_WAIT_INST_ANY SQ_INSTS_SALU GRBM_GUI_ACTIVE",
+    "tatd": "TA_TA_BUSY_sum TA_ADDR_STALLED_BY_TC_CYCLES_sum TD_TD_BUSY_sum TD_TC_STALL_sum "
+            "TCP_TOTAL_CACHE_ACCESSES_sum TCP_TCC_READ_REQ_sum TCP_PENDING_STALL_CYCLES_sum "
+            "TCP_TCC_READ_REQ_LATENCY_sum GRBM_GUI_ACTIVE",
+}
+KERNEL_NAME = "edge_cost_kernel<2, 16, false, false>"
+
+
+def _pmc_means(path: str, name_part: str) -> dict:
+    """Per-dispatch mean of every counter of the dispatches whose kernel name
+    contains name_part (rocprofv3 --output-format csv counter collection)."""
+    import csv
+    import collections
+    per = collections.defaultdict(dict)
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if name_part in r["Kernel_Name"]:
+                per[int(r["Dispatch_Id"])][r["Counter_Name"]] = float(r["Counter_Value"])
+    assert per, f"no dispatch of {name_part} in {path}"
+    keys = set.intersection(*(set(v) for v in per.values()))
+    return {k: sum(v[k] for v in per.values()) / len(per) for k in keys} | {"dispatches": len(per)}
+
+
+def summarize_counters(root: str, workload: str, options: dict, kernel: str):
+    """Turn the rocprofv3 counter runs under root (one directory per pass of
+    COUNTER_PASSES, plus copy_fetch / copy_write of the calibration copy, each
+    holding run_counter_collection.csv) into the committed record bench.py
+    reads, and print the figures."""
+    from synth import make
+    import glob
+    R = make(workload).residual_count()
+
+    def csvof(d):
+        hits = glob.glob(os.path.join(root, d, "**", "*counter_collection.csv"), recursive=True)
+        assert hits, f"no counter csv under {os.path.join(root, d)}"
+        return hits[0]
+
+    m = {d: _pmc_means(csvof(d), "edge_cost_kernel<" + kernel.split("<", 1)[1])
+         for d in COUNTER_PASSES}
+    cf = _pmc_means(csvof("copy_fetch"), "copyBuffer")
+    cw = _pmc_means(csvof("copy_write"), "copyBuffer")
+    copy_kib = CALIBRATION_BYTES / 1024.0
+    fetch_scale = copy_kib / cf["FETCH_SIZE"]
+    write_scale = copy_kib / cw["WRITE_SIZE"]
+    rd = m["fetch"]["FETCH_SIZE"] * 1024.0 * fetch_scale
+    wr = m["write"]["WRITE_SIZE"] * 1024.0 * write_scale
+    tcc, sq, tt = m["tcc"], m["sq"], m["tatd"]
+    grbm_xcd = tcc["GRBM_GUI_ACTIVE"] / 8.0
+    rec = {"kernel": kernel, "kernel_hash": kernel_source_hash(), "workload": workload,
+           "options": options, "n_residuals": R,
+           "fetch_kib_per_dispatch_raw": m["fetch"]["FETCH_SIZE"],
+           "write_kib_per_dispatch_raw": m["write"]["WRITE_SIZE"],
+           "fetch_scale": fetch_scale, "write_scale": write_scale,
+           "hbm_read_bytes_per_launch": rd, "hbm_write_bytes_per_launch": wr,
+           "hbm_bytes_per_launch": rd + wr,
+           "l2_hit_rate": tcc["TCC_HIT_sum"] / (tcc["TCC_HIT_sum"] + tcc["TCC_MISS_sum"]),
+           "l2_requests_per_launch": tcc["TCC_REQ_sum"],
+           "l2_channel_busy": tcc["TCC_BUSY_sum"] / 128.0 / grbm_xcd,
+           "l2_read_requests_per_launch": tt["TCP_TCC_READ_REQ_sum"],
+           "l2_read_latency_cycles": tt["TCP_TCC_READ_REQ_LATENCY_sum"] / tt["TCP_TCC_READ_REQ_sum"],
+           "l1_accesses_per_launch": tt["TCP_TOTAL_CACHE_ACCESSES_sum"],
+           "valu_insts_per_launch": sq["SQ_INSTS_VALU"], "lds_insts_per_launch": sq["SQ_INSTS_LDS"],
+           "salu_insts_per_launch": sq["SQ_INSTS_SALU"], "waves_per_launch": sq["SQ_WAVES"],
+           "ta_busy": tt["TA_TA_BUSY_sum"] / 256.0 / (tt["GRBM_GUI_ACTIVE"] / 8.0),
+           "td_busy": tt["TD_TD_BUSY_sum"] / 256.0 / (tt["GRBM_GUI_ACTIVE"] / 8.0),
+           "td_waiting_on_l1": tt["TD_TC_STALL_sum"] / 256.0 / (tt["GRBM_GUI_ACTIVE"] / 8.0),
+           "l1_pending_stall": tt["TCP_PENDING_STALL_CYCLES_sum"] / 256.0 / (tt["GRBM_GUI_ACTIVE"] / 8.0),
+           "dispatches": {d: int(v["dispatches"]) for d, v in m.items()},
+           "calibration": f"{CALIBRATION_BYTES} B device-to-device copy read FETCH_SIZE "
+                          f"{cf['FETCH_SIZE']:.0f} KiB and WRITE_SIZE {cw['WRITE_SIZE']:.0f} KiB "
+                          f"per dispatch"}
+    recs = [r for r in load_counter_records()
+            if not (r.get("workload") == workload and r.get("options") == options)]
+    recs.append(rec)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump({"records": recs}, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec, indent=1))
+
+
+CALIBRATION_BYTES = 1 << 30
 
 
 def host_description() -> dict:
@@ -543,7 +647,14 @@ def main():
                          "report their relative rotation errors")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES bytes (counter calibration)")
+    ap.add_argument("--summarize-counters", default=None, metavar="DIR",
+                    help="write the committed counter record of --workload / --options from "
+                         "the rocprofv3 runs under DIR (no GPU)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.workload, json.loads(args.options),
+                           KERNEL_NAME)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(--gpus 1)", file=sys.stderr)
@@ -650,41 +761,48 @@ def main():
     log(f"{ms_per_step:.3f} ms/iter ({wall_ms / args.steps:.3f} wall), kernel {kernel_ms:.3f} ms, "
         f"{value / 1e9:.1f} G residual+grad/s")
 
-    # effective roofline: the algorithmic bytes (24 B per residual: the 8 B
-    # record and four float32 taps) over the kernel's mean duration
+    # The fused kernel is bound by VALU issue (a wave64 VALU instruction
+    # occupies a 16-lane SIMD for 4 cycles whether float32 or float64; packed
+    # float32 is not used): the roofline is the ALU one.  achieved = the
+    # algorithm's floating-point operations (FLOPS_PER_RESIDUAL, an FMA as two)
+    # x residuals / kernel time, against the float64 / non-packed float32
+    # vector peak; beside it the issue rate the counters measured (VALU
+    # instructions per launch / kernel time against 256 CUs x 4 SIMDs x
+    # 2.4 GHz / 4 cycles) and the HBM side (algorithmic 24 B per residual and
+    # the bytes the counters measured).
     kernel_s = kernel_ms * 1e-3
-    achieved = BYTES_PER_RESIDUAL * R_expected / kernel_s / 1e9
     counters = measured_counters(args.workload, options, R_expected)
     traffic = counters.get("hbm_bytes_per_launch") if counters else None
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+    tflops = FLOPS_PER_RESIDUAL * R_expected / kernel_s / 1e12
+    roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tflops / VALU_PEAK_TFLOPS, 4),
                 "traffic": traffic, "kernel": "edge_cost_kernel",
                 "kernel_ms": round(kernel_ms, 4),
-                "kernel_ms_source": f"HIP events around {args.steps} back-to-back launches",
-                "frac_kind": "effective: algorithmic bytes / kernel time / HBM peak",
-                "bytes_per_launch": BYTES_PER_RESIDUAL * R_expected}
+                "kernel_ms_source": f"HIP events around one graph replay of {args.steps} "
+                                    "back-to-back launches",
+                "flops_per_residual": FLOPS_PER_RESIDUAL,
+                "flops_per_launch": FLOPS_PER_RESIDUAL * R_expected}
+    eff = BYTES_PER_RESIDUAL * R_expected / kernel_s / 1e9
+    roofline["hbm"] = {"algorithmic_bytes_per_launch": BYTES_PER_RESIDUAL * R_expected,
+                       "effective_GBps": round(eff, 1),
+                       "effective_frac": round(eff / HBM_PEAK_GBS, 4)}
     if traffic:
-        # measured: the HBM bytes the counters saw per launch over the same time
-        roofline["measured_GBps"] = round(traffic / kernel_s / 1e9, 1)
-        roofline["measured_frac"] = round(traffic / kernel_s / 1e9 / HBM_PEAK_GBS, 4)
-    if counters and counters.get("l2_read_requests_per_launch"):
-        # what bounds the kernel: its L1 -> L2 read requests (128-byte lines)
+        roofline["hbm"]["measured_bytes_per_launch"] = traffic
+        roofline["hbm"]["measured_GBps"] = round(traffic / kernel_s / 1e9, 1)
+        roofline["hbm"]["measured_frac"] = round(traffic / kernel_s / 1e9 / HBM_PEAK_GBS, 4)
+    if counters:
+        vi = counters["valu_insts_per_launch"]
+        rate = vi / kernel_s / 1e9
+        roofline["issue"] = {"valu_wave_instructions_per_launch": vi,
+                             "valu_per_residual": round(64.0 * vi / R_expected, 2),
+                             "achieved_G_per_s": round(rate, 1), "peak_G_per_s": VALU_ISSUE_PEAK_G,
+                             "frac": round(rate / VALU_ISSUE_PEAK_G, 4)}
         req = counters["l2_read_requests_per_launch"]
-        l2_bytes = 128.0 * req
         roofline["l2"] = {"read_requests_per_launch": req,
                           "lines_per_residual": round(req / R_expected, 4),
-                          "read_bytes_per_launch": l2_bytes,
-                          "achieved_TBps": round(l2_bytes / kernel_s / 1e12, 2),
+                          "achieved_TBps": round(128.0 * req / kernel_s / 1e12, 2),
                           "hit_rate": round(counters["l2_hit_rate"], 4),
                           "channel_busy": round(counters["l2_channel_busy"], 3)}
-    if counters and counters.get("valu_insts_per_launch"):
-        # the other limit: VALU issue.  A wave64 VALU instruction occupies a
-        # 16-lane SIMD for 4 cycles; 256 CUs x 4 SIMDs at 2.4 GHz
-        vi = counters["valu_insts_per_launch"]
-        roofline["valu"] = {"wave_instructions_per_launch": vi,
-                            "per_residual": round(64.0 * vi / R_expected, 2),
-                            "issue_bound_ms": round(vi * 4 / (1024 * 2.4e9) * 1e3, 4),
-                            "issue_frac": round(vi * 4 / (1024 * 2.4e9) / kernel_s, 4)}
 
     out = {"metric": METRIC, "value": value, "unit": "residual+grad evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,

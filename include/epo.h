@@ -687,13 +687,14 @@ EPO_API epo_status epo_plan_last_kernel_ms(epo_plan plan, float* ms);
 
 /* Mean duration in milliseconds (*ms, host) of the fused cost+adjoint kernel
  * of the plan's current schedule: the pair descriptors are set up once at
- * `poses` and `lambda` (device, as for epo_edge_cost_fwd), then the kernel is
- * launched `reps` times back to back on `stream` between two HIP events; the
- * elapsed time over reps is the per-launch mean, with no other kernel between
- * the launches.  Overwrites the plan's per-tile partial sums (call
- * epo_edge_cost_fwd again before reading per-pair results).  Creates two
- * events and synchronises.  Errors: EPO_ERR_INVALID_ARG for a null argument or
- * reps outside [1, 100000]. */
+ * `poses` and `lambda` (device, as for epo_edge_cost_fwd), then `reps`
+ * back-to-back launches of the kernel are captured as one HIP graph (launched
+ * as a captured iteration launches it), replayed once to warm up and once
+ * between two HIP events on `stream`; the elapsed time over reps is the
+ * per-launch mean, with no other kernel between the launches.  Overwrites the
+ * plan's per-tile partial sums (call epo_edge_cost_fwd again before reading
+ * per-pair results).  Allocates the graph and two events and synchronises.
+ * Errors: EPO_ERR_INVALID_ARG for a null argument or reps outside [1, 100000]. */
 EPO_API epo_status epo_plan_time_kernel(epo_plan plan, const double* poses, const float* lambda,
                                         int32_t reps, float* ms, void* stream);
 

@@ -211,28 +211,49 @@ extern "C" epo_status epo_plan_time_kernel(epo_plan plan, const double* poses,
         *ms = 0.0f;
         if (p.D == 0) return;
         launch_pair_setup(p, poses, lambda, s);
+        EPO_HIP(hipStreamSynchronize(s));
+        // `reps` launches of the kernel captured as one graph (the way a
+        // captured iteration launches it), replayed once to warm up and once
+        // between two events on `stream`
+        hipStream_t cs = nullptr;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
         hipEvent_t a = nullptr, b = nullptr;
-        EPO_HIP(hipEventCreate(&a));
-        hipError_t e = hipEventCreate(&b);
-        if (e != hipSuccess) {
-            (void)hipEventDestroy(a);
-            throw Failure{EPO_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e)};
-        }
+        auto cleanup = [&] {
+            if (ge) (void)hipGraphExecDestroy(ge);
+            if (g) (void)hipGraphDestroy(g);
+            if (cs) (void)hipStreamDestroy(cs);
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        };
         try {
+            EPO_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            EPO_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            try {
+                for (int k = 0; k < reps; ++k) launch_cost_variant<false>(p, nullptr, cs);
+            } catch (...) {
+                hipGraph_t junk = nullptr;
+                (void)hipStreamEndCapture(cs, &junk);
+                if (junk) (void)hipGraphDestroy(junk);
+                throw;
+            }
+            EPO_HIP(hipStreamEndCapture(cs, &g));
+            EPO_HIP(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+            EPO_HIP(hipEventCreate(&a));
+            EPO_HIP(hipEventCreate(&b));
+            EPO_HIP(hipGraphLaunch(ge, s));
             EPO_HIP(hipEventRecord(a, s));
-            for (int k = 0; k < reps; ++k) launch_cost_variant<false>(p, nullptr, s);
+            EPO_HIP(hipGraphLaunch(ge, s));
             EPO_HIP(hipEventRecord(b, s));
             EPO_HIP(hipEventSynchronize(b));
             float total = 0.0f;
             EPO_HIP(hipEventElapsedTime(&total, a, b));
             *ms = total / (float)reps;
         } catch (...) {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
+            cleanup();
             throw;
         }
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
+        cleanup();
     });
 }
 
