@@ -63,6 +63,46 @@ def build(verbose: bool = False) -> str:
     return LIB_PATH
 
 
+# host-code sanitizers: -fsanitize only on the host pass (the device code is
+# built as usual), for the C-ABI's host-side validation checks
+SANITIZE = ("-Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined "
+            "-Xarch_host -fno-sanitize-recover=undefined -Xarch_host -fno-omit-frame-pointer").split()
+HOST_CHECK_SRC = os.path.join(ROOT, "tests", "abi_host_check.cpp")
+HOST_CHECK_DIR = os.path.join(BUILD_DIR, "host_check")
+HOST_CHECK_BIN = os.path.join(HOST_CHECK_DIR, "abi_host_check")
+
+
+def build_host_check(verbose: bool = False) -> str:
+    """Every library source and tests/abi_host_check.cpp compiled with
+    AddressSanitizer and UndefinedBehaviorSanitizer on the host code, linked
+    into one program (runs without a GPU)."""
+    os.makedirs(HOST_CHECK_DIR, exist_ok=True)
+    flags = [f for f in COMMON if f != "-fvisibility=hidden"] + ["-O1", "-g"] + SANITIZE
+
+    def comp(src):
+        path = src if os.path.isabs(src) else os.path.join(CSRC, src)
+        obj = os.path.join(HOST_CHECK_DIR, os.path.splitext(os.path.basename(path))[0] + ".o")
+        cmd = [hipcc(), *flags, "-c", path, "-o", obj]
+        if path.endswith(".cpp"):
+            cmd[1:1] = ["-x", "hip"]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {path}:\n{r.stderr}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES) + 1, os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(comp, SOURCES + [HOST_CHECK_SRC]))
+    cmd = [hipcc(), f"--offload-arch={ARCH}", *SANITIZE, "-o", HOST_CHECK_BIN, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    if verbose:
+        print(f"built {HOST_CHECK_BIN}")
+    return HOST_CHECK_BIN
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    if len(sys.argv) > 1 and sys.argv[1] == "host-check":
+        build_host_check(verbose=True)
     sys.exit(0)

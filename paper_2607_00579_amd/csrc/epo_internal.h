@@ -206,12 +206,15 @@ struct Plan {
     // pixels, one 128-byte cache line each, blocks row-major per view:
     // a wave's projected edge points touch about a fifth fewer lines than
     // with whole image rows
-    DevBuf<uint32_t> tex;                 // total_blk texels
+    DevBuf<uint32_t> tex;                 // total_blk texels (format 2 only while in use)
     std::vector<int64_t> blk_off;         // V: first texel of each view's blocks
     DevBuf<int64_t> blk_off_d;
     int64_t total_blk = 0;
-    DevBuf<float> tex_f32;                // float32 sqrt(d2) per pixel
-    DevBuf<float4> tex_q32;               // float32 taps of the cell at each pixel
+    DevBuf<float> tex_f32;                // float32 sqrt(d2) per pixel (always kept: the
+                                          // other formats are derived from it)
+    DevBuf<float4> tex_q32;               // float32 taps of the cell at each pixel (format 3
+                                          // only while it is in use)
+    bool q8_ok = false;                   // lambda_max allows the saturated u8 taps
     DevBuf<int32_t> scene_of_view_d;
     DevBuf<float> K_d;                    // V x 4
     DevBuf<int32_t> wh_d;                 // V x 2
@@ -349,7 +352,11 @@ void launch_schedule(const int32_t* step, int32_t n_scenes, float lambda0, float
 void launch_convergence(Plan& p, const double* poses, double* theta_out, hipStream_t stream);
 void launch_pair_selection(Plan& p, const int32_t* step, hipStream_t stream);
 void launch_convergence_reset(Plan& p, const double* poses, hipStream_t stream);
+// textures: float32 sqrt(d2) from d2 (kept), the format in use derived from
+// it; a format's texture is built when selected and freed when another is
 void build_texture(Plan& p, const int32_t* d2, hipStream_t stream);
+void ensure_texture(Plan& p, int fmt, hipStream_t stream);
+void release_unused_textures(Plan& p);
 // record_order 2: allocate the per-pair record copies (source order until
 // the first sort); re-sort them at the given poses: every chunk (step null), or
 // the chunks c with c mod every == *step mod every

@@ -103,35 +103,53 @@ __global__ __launch_bounds__(256) void scatter_records_kernel(
     }
 }
 
-__global__ __launch_bounds__(256) void texture_kernel(const int32_t* __restrict__ d2,
-                                                      const int64_t* __restrict__ view_off,
-                                                      const int32_t* __restrict__ wh,
-                                                      const int64_t* __restrict__ blk_off,
-                                                      uint32_t* __restrict__ q8,
-                                                      float* __restrict__ f32,
-                                                      float4* __restrict__ q32) {
+// float32 sqrt(d2) per pixel: the texture of format 1, and the source the
+// other formats are derived from (d2 is not kept by the plan)
+__global__ __launch_bounds__(256) void texture_f32_kernel(const int32_t* __restrict__ d2,
+                                                          const int64_t* __restrict__ view_off,
+                                                          const int32_t* __restrict__ wh,
+                                                          float* __restrict__ f32) {
+    const int v = blockIdx.y;
+    const int64_t n = (int64_t)wh[2 * v] * wh[2 * v + 1], base = view_off[v];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        f32[base + i] = sqrtf((float)d2[base + i]);
+}
+
+// min(d2, 255) from the float32 texture: for d2 <= 255, f = sqrt(d2) rounded
+// to float32 squares back to d2 within 5e-5, and f >= 16 exactly when d2 >= 256
+__device__ __forceinline__ uint32_t saturated_d2(float f) {
+    return f < 16.0f ? (uint32_t)rintf(f * f) : 255u;
+}
+
+// the four taps of the bilinear cell at every pixel, as float32 (format 3) or
+// as saturated d2 bytes in 8 x 4 pixel blocks (format 2), from the float32
+// texture.  Format 3 repeats a pixel past the right column / bottom row,
+// format 2 stores 255 there: no valid sample ever uses those cells
+__global__ __launch_bounds__(256) void texture_quads_kernel(const float* __restrict__ f32,
+                                                            const int64_t* __restrict__ view_off,
+                                                            const int32_t* __restrict__ wh,
+                                                            const int64_t* __restrict__ blk_off,
+                                                            uint32_t* __restrict__ q8,
+                                                            float4* __restrict__ q32) {
     const int v = blockIdx.y;
     const int W = wh[2 * v], H = wh[2 * v + 1];
     const int64_t n = (int64_t)W * H, base = view_off[v];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int y = (int)(i / W), x = (int)(i - (int64_t)y * W);
-        const int32_t a = d2[base + i];
-        if (f32) f32[base + i] = sqrtf((float)a);
+        const bool rx = x + 1 < W, dy = y + 1 < H;
+        const float a = f32[base + i];
         if (q32) {
-            // the right column / bottom row of a view repeat their own pixel:
-            // no valid sample ever uses those cells
-            const int64_t ix = x + 1 < W ? 1 : 0, iy = y + 1 < H ? W : 0;
-            q32[base + i] = make_float4(sqrtf((float)a), sqrtf((float)d2[base + i + ix]),
-                                        sqrtf((float)d2[base + i + iy]),
-                                        sqrtf((float)d2[base + i + iy + ix]));
+            const int64_t ix = rx ? 1 : 0, iy = dy ? W : 0;
+            q32[base + i] = make_float4(a, f32[base + i + ix], f32[base + i + iy],
+                                        f32[base + i + iy + ix]);
         }
         if (q8) {
-            const bool rx = x + 1 < W, dy = y + 1 < H;
-            const uint32_t t00 = (uint32_t)min(a, 255);
-            const uint32_t t10 = rx ? (uint32_t)min(d2[base + i + 1], 255) : 255u;
-            const uint32_t t01 = dy ? (uint32_t)min(d2[base + i + W], 255) : 255u;
-            const uint32_t t11 = (rx && dy) ? (uint32_t)min(d2[base + i + W + 1], 255) : 255u;
+            const uint32_t t00 = saturated_d2(a);
+            const uint32_t t10 = rx ? saturated_d2(f32[base + i + 1]) : 255u;
+            const uint32_t t01 = dy ? saturated_d2(f32[base + i + W]) : 255u;
+            const uint32_t t11 = (rx && dy) ? saturated_d2(f32[base + i + W + 1]) : 255u;
             // blocked layout: block (x / 8, y / 4), row-major blocks, the
             // block's 8 x 4 texels row-major inside it
             const int64_t nbx = (W + kQuadBlockW - 1) / kQuadBlockW;
@@ -250,18 +268,35 @@ void build_tiles(Plan& p, hipStream_t s) {
     EPO_HIP(hipStreamSynchronize(s));
 }
 
-void build_texture(Plan& p, const int32_t* d2, hipStream_t s) {
-    const bool q8 = p.params.lambda_max <= kQ8LambdaMax;
-    p.tex_f32.alloc((size_t)p.total_px);
-    p.tex_q32.alloc((size_t)p.total_px);
-    if (q8) p.tex.alloc((size_t)p.total_blk);
+unsigned texture_grid(const Plan& p) {
     int64_t maxWH = 1;
     for (int v = 0; v < p.V; ++v) maxWH = std::max<int64_t>(maxWH, (int64_t)p.width[v] * p.height[v]);
-    const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(maxWH, 256), 1024);
-    texture_kernel<<<dim3(gx, p.V), 256, 0, s>>>(d2, p.view_offset_d.p, p.wh_d.p,
-                                                 p.blk_off_d.p, q8 ? p.tex.p : nullptr, p.tex_f32.p,
-                                                 p.tex_q32.p);
+    return (unsigned)std::min<int64_t>(ceil_div(maxWH, 256), 1024);
+}
+
+void build_texture(Plan& p, const int32_t* d2, hipStream_t s) {
+    p.tex_f32.alloc((size_t)p.total_px);
+    texture_f32_kernel<<<dim3(texture_grid(p), p.V), 256, 0, s>>>(d2, p.view_offset_d.p, p.wh_d.p,
+                                                                  p.tex_f32.p);
     EPO_CHECK_LAUNCH();
+    ensure_texture(p, p.opt.texture_format, s);
+}
+
+void ensure_texture(Plan& p, int fmt, hipStream_t s) {
+    const bool q8 = fmt == 2 && !p.tex.p, q32 = fmt == 3 && !p.tex_q32.p;
+    if (!q8 && !q32) return;
+    EPO_REQUIRE(fmt != 2 || p.q8_ok, "texture_format 2 needs lambda_max <= 14.5");
+    if (q8) p.tex.alloc((size_t)p.total_blk);
+    if (q32) p.tex_q32.alloc((size_t)p.total_px);
+    texture_quads_kernel<<<dim3(texture_grid(p), p.V), 256, 0, s>>>(
+        p.tex_f32.p, p.view_offset_d.p, p.wh_d.p, p.blk_off_d.p, q8 ? p.tex.p : nullptr,
+        q32 ? p.tex_q32.p : nullptr);
+    EPO_CHECK_LAUNCH();
+}
+
+void release_unused_textures(Plan& p) {
+    if (p.opt.texture_format != 2) p.tex.release();
+    if (p.opt.texture_format != 3) p.tex_q32.release();
 }
 
 }  // namespace epo
@@ -352,9 +387,10 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         } else {
             p->opt = epo_plan_options{0, 0, 0, 0, 0, 0};
         }
+        p->q8_ok = p->params.lambda_max <= kQ8LambdaMax;
         fill_default_options(*p, p->opt);
         validate_options(p->opt);
-        if (p->opt.texture_format == 2 && p->params.lambda_max > kQ8LambdaMax)
+        if (p->opt.texture_format == 2 && !p->q8_ok)
             throw Failure{EPO_ERR_UNSUPPORTED,
                           "texture_format 2 needs lambda_max <= 14.5 (saturated taps)"};
 
@@ -613,7 +649,7 @@ extern "C" epo_status epo_plan_set_options(epo_plan plan, const epo_plan_options
         epo_plan_options o = *options;
         fill_default_options(p, o);
         validate_options(o);
-        if (o.texture_format == 2 && !p.tex.p)
+        if (o.texture_format == 2 && !p.q8_ok)
             throw Failure{EPO_ERR_UNSUPPORTED,
                           "texture_format 2 needs lambda_max <= 14.5 (saturated taps)"};
         hipStream_t s = as_stream(stream);
@@ -623,6 +659,8 @@ extern "C" epo_status epo_plan_set_options(epo_plan plan, const epo_plan_options
                              o.tile_order != p.opt.tile_order;
         p.opt = o;
         if (rebuild) build_tiles(p, s);
+        ensure_texture(p, p.opt.texture_format, s);
+        release_unused_textures(p);
         apply_record_order(p, s);
     });
 }
@@ -674,7 +712,8 @@ extern "C" epo_status epo_plan_autotune(epo_plan plan, const double* poses, cons
                 best1 = best;
             }
             for (int f : fmts) {
-                if (f == 2 && !p.tex.p) continue;
+                if (f == 2 && !p.q8_ok) continue;
+                ensure_texture(p, f, s);
                 for (int pp : ppts)
                     for (int o : orders)
                         for (int pe : pers) {
@@ -714,6 +753,7 @@ extern "C" epo_status epo_plan_autotune(epo_plan plan, const double* poses, cons
                              best_o.tile_order != p.opt.tile_order;
         p.opt = best_o;
         if (rebuild) build_tiles(p, s);
+        release_unused_textures(p);
         apply_record_order(p, s);
         if (chosen) *chosen = best_o;
     });

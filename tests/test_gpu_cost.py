@@ -154,6 +154,27 @@ def test_texture_formats_bitwise_equal(gpu, fmt):
         assert np.array_equal(a[k], b[k]), k
 
 
+def test_format_switches_rebuild_the_textures(gpu):
+    """A plan keeps the float32 texture and the format in use; switching
+    formats derives the new one from the float32 texture (and frees the old):
+    every output bitwise equal to format 1's, on one plan switched
+    1 -> 2 -> 3 -> 1 -> 2 and after an autotune."""
+    p = problem("c2")
+    base = dict(points_per_thread=4, tile_order=1, persistent=2)
+    plan = plan_for(p, options=dict(base, texture_format=1))
+    ref = gpu_eval(plan, p.poses_init, 10.0)
+    for fmt in (2, 3, 1, 2):
+        plan.set_options(**base, texture_format=fmt)
+        got = gpu_eval(plan, p.poses_init, 10.0)
+        for k in ref:
+            assert np.array_equal(got[k], ref[k]), (fmt, k)
+    plan.autotune(torch.from_numpy(p.poses_init.copy()).cuda(), 10.0, iters=1)
+    plan.set_options(**base, texture_format=3)
+    got = gpu_eval(plan, p.poses_init, 10.0)
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), k
+
+
 def test_run_to_run_bitwise(gpu):
     p = problem("c2")
     for opts in (dict(persistent=1), dict(persistent=2)):
