@@ -129,15 +129,83 @@ __global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ ed
 // One workgroup per row.  The row's column-pass values live in dtf (the
 // call's scratch); the workgroup reads all of them into LDS before any of its
 // threads writes the row's DTF, and no other workgroup touches the row.
-// The row is split into blocks of 16 pixels with their minimum f in LDS; a
-// pixel scans its own block, then the blocks at block distance R = 1, 2, ...
-// on both sides: a block is scanned only if its minimum plus the squared
-// distance to its nearest pixel is below the best value so far, and the
-// search ends once the nearer of the two blocks is at least sqrt(best) away
-// (every farther pixel adds more).  Every pixel that can attain the minimum
-// is scanned, so the result is the exact minimum, at about D/16 block tests
-// per pixel (D its distance to the nearest edge).
+// d2(x) = min over q of f(q) + (x - q)^2 is found by an exact search over a
+// three-level hierarchy of minima in LDS: blocks of 16 pixels, groups of 16
+// blocks (256 px), supers of 16 groups (4096 px).  A pixel scans its own
+// block, then the other blocks of its group, the other groups of its super,
+// and the other supers, each level outward from the pixel and nearest first
+// inside a region it descends into.  A region (block, group, super) is
+// descended into only if its minimum f plus the squared distance from x to
+// its nearest pixel is below the best value so far, and a level's outward
+// walk ends once its nearer remaining region is at least sqrt(best) away.
+// Every pixel that can attain the minimum is scanned, so the result is the
+// exact minimum.  Near an edge the search ends inside the own group (about
+// D/16 block tests, D the distance to the nearest edge); far from every edge
+// the minima skip empty stretches 4096 or 256 pixels at a time, so a pixel
+// costs O(W/4096 + 16 + 16 + 16) tests whatever the map (a 16384 x 16384 map
+// with one edge pixel: 257 ms with blocks alone).
 constexpr int kRowBlk = 16;
+constexpr int kRowFan = 16;                 // blocks per group, groups per super
+constexpr int kGroupPx = kRowBlk * kRowFan;
+constexpr int kSuperPx = kGroupPx * kRowFan;
+
+// LDS per row: f (W), block, group and super minima
+__host__ __device__ inline int edt_row_lds_ints(int W) {
+    const int nb = (W + kRowBlk - 1) / kRowBlk;
+    const int ng = (W + kGroupPx - 1) / kGroupPx;
+    const int ns = (W + kSuperPx - 1) / kSuperPx;
+    return W + nb + ng + ns;
+}
+
+struct RowMinima {
+    const int32_t* row;
+    const int32_t* bmin;
+    const int32_t* gmin;
+    const int32_t* smin;
+    int W;
+};
+
+// squared distance from x to the nearest pixel of [lo, hi] (x outside it)
+__device__ __forceinline__ int gap2(int x, int lo, int hi) {
+    const int d = x < lo ? lo - x : x - hi;
+    return d * d;
+}
+
+__device__ __forceinline__ void scan_block(const RowMinima& m, int x, int b, int32_t& best) {
+    const int q0 = kRowBlk * b;
+    if (q0 + kRowBlk <= m.W) {
+#pragma unroll
+        for (int u = 0; u < kRowBlk; ++u) best = min(best, m.row[q0 + u] + (x - q0 - u) * (x - q0 - u));
+    } else {
+        for (int q = q0; q < m.W; ++q) best = min(best, m.row[q] + (x - q) * (x - q));
+    }
+}
+
+// the blocks of group g, nearest to x first (g lies wholly on one side of x)
+__device__ __forceinline__ void scan_group(const RowMinima& m, int x, int g, int32_t& best) {
+    const int nb = (m.W + kRowBlk - 1) / kRowBlk;
+    const int b0 = kRowFan * g, b1 = min(b0 + kRowFan, nb) - 1;
+    const bool right = kRowBlk * b0 > x;
+    for (int k = 0; k <= b1 - b0; ++k) {
+        const int b = right ? b0 + k : b1 - k;
+        const int d2b = gap2(x, kRowBlk * b, kRowBlk * b + kRowBlk - 1);
+        if (d2b >= best) break;                  // the rest of the group is farther
+        if (m.bmin[b] + d2b < best) scan_block(m, x, b, best);
+    }
+}
+
+// the groups of super s, nearest to x first (s lies wholly on one side of x)
+__device__ __forceinline__ void scan_super(const RowMinima& m, int x, int sp, int32_t& best) {
+    const int ng = (m.W + kGroupPx - 1) / kGroupPx;
+    const int g0 = kRowFan * sp, g1 = min(g0 + kRowFan, ng) - 1;
+    const bool right = kGroupPx * g0 > x;
+    for (int k = 0; k <= g1 - g0; ++k) {
+        const int g = right ? g0 + k : g1 - k;
+        const int d2g = gap2(x, kGroupPx * g, kGroupPx * g + kGroupPx - 1);
+        if (d2g >= best) break;
+        if (m.gmin[g] + d2g < best) scan_group(m, x, g, best);
+    }
+}
 
 __global__ __launch_bounds__(256) void edt_rows(const int32_t* __restrict__ colsq,
                                                int32_t* __restrict__ d2, float* __restrict__ dtf,
@@ -148,45 +216,90 @@ __global__ __launch_bounds__(256) void edt_rows(const int32_t* __restrict__ cols
     const int y = blockIdx.x;
     if (y >= H) return;                  // whole workgroup
     const int nb = (W + kRowBlk - 1) / kRowBlk;
+    const int ng = (W + kGroupPx - 1) / kGroupPx;
+    const int ns = (W + kSuperPx - 1) / kSuperPx;
     int32_t* row = lds;
     int32_t* bmin = lds + W;
+    int32_t* gmin = bmin + nb;
+    int32_t* smin = gmin + ng;
     const int64_t base = b.off[k] + (int64_t)y * W;
     for (int x = threadIdx.x; x < W; x += blockDim.x) row[x] = colsq[base + x];
     __syncthreads();
-    for (int j = threadIdx.x; j < nb; j += blockDim.x) {
-        int32_t m = row[kRowBlk * j];
-        for (int q = kRowBlk * j + 1; q < min(kRowBlk * j + kRowBlk, W); ++q) m = min(m, row[q]);
-        bmin[j] = m;
+    // block minima, one block per thread; a group's 16 blocks sit on 16
+    // adjacent lanes (256 threads and 16 blocks per group are both multiples
+    // of 16), so the group minimum is a 16-lane butterfly
+    for (int j0 = 0; j0 < nb; j0 += blockDim.x) {
+        const int j = j0 + threadIdx.x;
+        int32_t mn = kInf;
+        if (j < nb) {
+            const int q0 = kRowBlk * j;
+            if (q0 + kRowBlk <= W) {
+#pragma unroll
+                for (int u = 0; u < kRowBlk; ++u) mn = min(mn, row[q0 + u]);
+            } else {
+                for (int q = q0; q < W; ++q) mn = min(mn, row[q]);
+            }
+            bmin[j] = mn;
+        }
+#pragma unroll
+        for (int o = kRowFan / 2; o >= 1; o >>= 1) mn = min(mn, __shfl_xor(mn, o, 64));
+        if (j < nb && (j % kRowFan) == 0) gmin[j / kRowFan] = mn;
     }
     __syncthreads();
-    // f <= (H - 1)^2 < 2^28 or kInf = 2^30, distances < 2^14: no int32 overflow
+    // super minima: only rows wider than one super have other supers
+    if (ns > 1) {
+        for (int j = threadIdx.x; j < ns; j += blockDim.x) {
+            int32_t mn = gmin[kRowFan * j];
+            for (int q = kRowFan * j + 1; q < min(kRowFan * j + kRowFan, ng); ++q) mn = min(mn, gmin[q]);
+            smin[j] = mn;
+        }
+        __syncthreads();
+    }
+    const RowMinima m{row, bmin, gmin, smin, W};
+    // f <= (H - 1)^2 < 2^28 or kInf = 2^30, squared distances < 2^28: no
+    // int32 overflow in any sum below
     for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        const int bx = x / kRowBlk;
+        const int bx = x / kRowBlk, gx = x / kGroupPx, sx = x / kSuperPx;
         int32_t best = row[x];
-        for (int q = kRowBlk * bx; q < min(kRowBlk * bx + kRowBlk, W); ++q)
-            best = min(best, row[q] + (x - q) * (x - q));
-        for (int R = 1;; ++R) {
-            const int bl = bx - R, br = bx + R;
-            const bool lin = bl >= 0, rin = kRowBlk * br < W;
+        scan_block(m, x, bx, best);
+        // the other blocks of the own group, outward
+        {
+            const int lo = kRowFan * gx, hi = min(lo + kRowFan, nb) - 1;
+            for (int R = 1;; ++R) {
+                const int bl = bx - R, br = bx + R;
+                const bool lin = bl >= lo, rin = br <= hi;
+                if (!lin && !rin) break;
+                const int dl = lin ? gap2(x, kRowBlk * bl, kRowBlk * bl + kRowBlk - 1) : 0x7fffffff;
+                const int dr = rin ? gap2(x, kRowBlk * br, kRowBlk * br + kRowBlk - 1) : 0x7fffffff;
+                if (min(dl, dr) >= best) break;
+                if (lin && bmin[bl] + dl < best) scan_block(m, x, bl, best);
+                if (rin && bmin[br] + dr < best) scan_block(m, x, br, best);
+            }
+        }
+        // the other groups of the own super, outward
+        {
+            const int lo = kRowFan * sx, hi = min(lo + kRowFan, ng) - 1;
+            for (int R = 1;; ++R) {
+                const int gl = gx - R, gr = gx + R;
+                const bool lin = gl >= lo, rin = gr <= hi;
+                if (!lin && !rin) break;
+                const int dl = lin ? gap2(x, kGroupPx * gl, kGroupPx * gl + kGroupPx - 1) : 0x7fffffff;
+                const int dr = rin ? gap2(x, kGroupPx * gr, kGroupPx * gr + kGroupPx - 1) : 0x7fffffff;
+                if (min(dl, dr) >= best) break;
+                if (lin && gmin[gl] + dl < best) scan_group(m, x, gl, best);
+                if (rin && gmin[gr] + dr < best) scan_group(m, x, gr, best);
+            }
+        }
+        // the other supers, outward
+        for (int R = 1; ns > 1; ++R) {
+            const int sl = sx - R, sr = sx + R;
+            const bool lin = sl >= 0, rin = sr < ns;
             if (!lin && !rin) break;
-            const int dl = x - (kRowBlk * bl + kRowBlk - 1);     // >= 1 when lin
-            const int dr = kRowBlk * br - x;                    // >= 1 when rin
-            const int dn = min(lin ? dl : 0x7fff, rin ? dr : 0x7fff);
-            if (dn * dn >= best) break;
-            if (lin && bmin[bl] + dl * dl < best) {
-#pragma unroll
-                for (int u = 0; u < kRowBlk; ++u) {
-                    const int q = kRowBlk * bl + u;
-                    best = min(best, row[q] + (x - q) * (x - q));
-                }
-            }
-            if (rin && bmin[br] + dr * dr < best) {
-#pragma unroll
-                for (int u = 0; u < kRowBlk; ++u) {
-                    const int q = kRowBlk * br + u;
-                    if (q < W) best = min(best, row[q] + (x - q) * (x - q));
-                }
-            }
+            const int dl = lin ? gap2(x, kSuperPx * sl, kSuperPx * sl + kSuperPx - 1) : 0x7fffffff;
+            const int dr = rin ? gap2(x, kSuperPx * sr, kSuperPx * sr + kSuperPx - 1) : 0x7fffffff;
+            if (min(dl, dr) >= best) break;
+            if (lin && smin[sl] + dl < best) scan_super(m, x, sl, best);
+            if (rin && smin[sr] + dr < best) scan_super(m, x, sr, best);
         }
         d2[base + x] = best;
         dtf[base + x] = sqrtf((float)best);
@@ -230,9 +343,9 @@ extern "C" epo_status epo_build_distance_fields(const uint8_t* edge_maps, const 
             EPO_CHECK_LAUNCH();
             edt_columns<<<cgrid, 64, 0, s>>>(edge_maps, d2_out, colsq, b);
             EPO_CHECK_LAUNCH();
-            const size_t lds = (size_t)(maxW + ceil_div(maxW, kRowBlk)) * sizeof(int32_t);
+            const size_t lds = (size_t)edt_row_lds_ints(maxW) * sizeof(int32_t);
             if (lds > 65536) {
-                // rows wider than 15420 pixels: more than the default 64 KB of
+                // rows wider than 15360 pixels: more than the default 64 KB of
                 // dynamic LDS (gfx950 has 160 KB per workgroup); an error, never
                 // a short allocation, if the device cannot give it
                 int dev = 0, max_lds = 0;

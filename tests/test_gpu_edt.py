@@ -53,11 +53,12 @@ def test_random_maps_bit_exact(gpu, shape, density):
 
 def test_wide_and_single_pixel(gpu):
     """Maps with one or two edge pixels: d2 is the closed-form minimum over
-    them.  The row pass stages a row and its 16-pixel block minima in LDS:
-    rows of up to 15420 pixels fit in 64 KB, wider ones (15421, 15500,
-    16384) need more."""
+    them.  The row pass stages a row and its block, group and super minima
+    in LDS: rows of up to 15360 pixels fit in 64 KB, wider ones (15361,
+    15420, 15500, 16384) need more."""
     cases = [(3, 4000, [(1, 3999)]), (2000, 2, [(0, 0)]), (64, 2048, [(63, 1000)]),
              (2, 16384, [(1, 5)]), (3, 15500, [(0, 15499)]),
+             (2, 15360, [(1, 15359)]), (2, 15361, [(0, 7000)]),
              (2, 15420, [(1, 15419)]), (2, 15421, [(0, 7000)]),
              (4, 16384, [(0, 9000), (3, 9100)])]
     maps = []
@@ -71,6 +72,31 @@ def test_wide_and_single_pixel(gpu):
         yy, xx = np.mgrid[0:H, 0:W]
         want = np.min([(xx - x0) ** 2 + (yy - y0) ** 2 for y0, x0 in pts], axis=0)
         assert np.array_equal(g, want), (H, W)
+
+
+def test_sparse_wide_rows_closed_form(gpu):
+    """Few edge pixels in wide rows, the case the row pass's group (256 px)
+    and super (4096 px) minima are for: edges on and next to those
+    boundaries, at both ends of a 16384-pixel row, and a few random pixels
+    per map; d2 is the closed-form minimum over the edge pixels."""
+    rng = np.random.default_rng(11)
+    cases = [(2, 16384, [(0, 0), (1, 16383)]), (3, 9000, [(2, 255)]), (3, 9000, [(0, 256)]),
+             (2, 12289, [(0, 4095), (1, 4096)]), (5, 8192, [(4, 8191)]), (1, 16384, [(0, 8192)])]
+    for _ in range(8):
+        H, W = int(rng.integers(1, 9)), int(rng.integers(4000, 16385))
+        n = int(rng.integers(1, 6))
+        cases.append((H, W, [(int(rng.integers(0, H)), int(rng.integers(0, W))) for _ in range(n)]))
+    maps = []
+    for H, W, pts in cases:
+        e = np.zeros((H, W), np.uint8)
+        for y0, x0 in pts:
+            e[y0, x0] = 1
+        maps.append(e)
+    got, _ = gpu_edt(maps)
+    for g, (H, W, pts) in zip(got, cases):
+        yy, xx = np.mgrid[0:H, 0:W]
+        want = np.min([(xx - x0) ** 2 + (yy - y0) ** 2 for y0, x0 in pts], axis=0)
+        assert np.array_equal(g, want), (H, W, pts)
 
 
 @pytest.mark.parametrize("name", ["c1", "c2"])
