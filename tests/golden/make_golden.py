@@ -13,7 +13,8 @@ c3, c4 and c5 are prefixes of their runs (20, 10 and 20 steps,
 same bits as a serial evaluation).  <name>_envelope.npz holds the oracle's
 own sensitivity over those prefixes: the same runs with every gradient
 perturbed by a seeded random relative amount (1e-9, 5e-8), and how far each
-ends from the stored prefix.
+ends from the stored prefix; <name>_window_envelope.npz the same for each
+10-step window of a whole run (c2), restarted from the stored states.
 """
 from __future__ import annotations
 
@@ -148,9 +149,59 @@ def write_envelope(name: str, workers=None):
         checksum=g["checksum"])
 
 
+def write_window_envelope(name: str, workers=None, epss=(1e-9, 5e-8), seeds=(0, 1, 2)):
+    """The oracle's own sensitivity over the 10-step windows of a whole run:
+    each window restarted from the stored state (poses, Adam moments, step)
+    with every gradient perturbed by a seeded random relative amount, and how
+    far it ends from the stored state of the next window (largest rotation
+    and camera-centre deviation over the views) and how far its losses are
+    from the stored ones."""
+    import time
+    g = np.load(os.path.join(HERE, f"{name}_trajectory.npz"), allow_pickle=False)
+    n = int(g["iterations"])
+    prob = make(name)
+    assert str(g["checksum"]) == input_checksum(prob)
+    op = ocost.OracleProblem(prob)
+    n_win = g["poses_every10"].shape[0] - 1
+    runs, loss_dev, rot_dev = [], [], []
+    with opar.ParallelEvaluator(op, workers, single_threaded=True) as ev:
+        for eps in epss:
+            for seed in seeds:
+                t0 = time.time()
+                rng = np.random.default_rng([seed, 11])
+
+                def evaluate(poses, lam, params, selected=None, eps=eps, rng=rng):
+                    r = ev(poses, lam, params, selected=selected)
+                    e = rng.normal(size=r["grad"].shape)
+                    r["grad"] = r["grad"] + eps * np.linalg.norm(r["grad"]) / np.linalg.norm(e) * e
+                    return r
+
+                ld, rd = [], []
+                for k in range(n_win):
+                    steps = min(10, n - 10 * k)
+                    hist = oloop.run(op, g["poses_every10"][k], steps, start_step=10 * k,
+                                     m0=g["m_every10"][k], v0=g["v_every10"][k], evaluate=evaluate)
+                    loss = np.array(hist["loss"])[:, 0]
+                    ref = g["loss"][10 * k:10 * k + steps, 0]
+                    ld.append(float((np.abs(loss - ref) / np.abs(ref)).max()))
+                    P, Q = hist["final_poses"], g["poses_every10"][k + 1]
+                    rd.append(max(rotation_deg(P[v][:, :3], Q[v][:, :3]) for v in range(len(P))))
+                loss_dev.append(ld)
+                rot_dev.append(rd)
+                runs.append((eps, seed))
+                print(f"{name} windows: eps {eps:.0e} seed {seed}: worst window rotation "
+                      f"{max(rd):.2e} deg, loss {max(ld):.2e} ({time.time() - t0:.0f} s)", flush=True)
+    np.savez_compressed(
+        os.path.join(HERE, f"{name}_window_envelope.npz"), eps=np.array([r[0] for r in runs]),
+        seed=np.array([r[1] for r in runs]), loss_dev=np.array(loss_dev),
+        rot_dev=np.array(rot_dev), checksum=g["checksum"])
+
+
 if __name__ == "__main__":
     for name in (sys.argv[1:] or list(ITERS) + list(PREFIX) + [k + "_envelope" for k in ENVELOPE]):
-        if name.endswith("_envelope"):
+        if name.endswith("_window_envelope"):
+            write_window_envelope(name[:-len("_window_envelope")])
+        elif name.endswith("_envelope"):
             write_envelope(name[:-len("_envelope")])
         elif name in PREFIX:
             write_prefix(name)

@@ -97,15 +97,33 @@ def test_captured_iteration_trajectory_c2_full_run(gpu):
     compare("c2 graph", hist, final, g, rot_tol=0.2)
 
 
+# The oracle's own spread at step s: the largest deviation from the stored
+# trajectory that any of its perturbed runs (gradients moved by 1e-9 and 5e-8
+# relative, several seeds) shows at or before s.  The GPU's poses may deviate
+# by ENVELOPE_FACTOR times that spread, never less than the north-star bar;
+# its losses are held to LOSS_BAR while the oracle's own loss spread stays
+# below LOSS_BAR / ENVELOPE_FACTOR, and afterwards, when the poses carry the
+# comparison, to LOSS_SANITY times the spread (a handful of sampled runs
+# underestimate the tail of a chaotic spread: on the 32-view workload the
+# GPU's loss leads the sampled spread by up to 3.5x around steps 12-15 while
+# its rotations stay inside it).
+ENVELOPE_FACTOR = 3.0
+LOSS_SANITY = 10.0
+ROT_BAR = 0.01          # degrees
+LOSS_BAR = 1e-5         # relative
+
+WINDOW_BAR = 1e-3      # degrees, at the end of a 10-step window
+
+
 @pytest.mark.parametrize("name", ["c1", "c2"])
 def test_trajectory_windows_from_oracle_states(gpu, name):
     """Restart the captured iteration from the oracle's state (poses, Adam
-    moments, step) every 10 steps and run 10 steps: every window must end
-    within 5e-3 deg of the oracle (half the 0.01 deg bar), every loss within
-    1e-5.  Reference for the bar: the oracle against itself, with a random
-    normwise perturbation of 5e-8 of every gradient (the size of the GPU's
-    measured gradient error), ends its worst c2 window 3.4e-4 to 8.1e-4 deg
-    away depending only on the draw; 1e-9 still gives 1.2e-4 deg."""
+    moments, step) every 10 steps and run 10 steps.  Every window must end
+    within 1e-3 deg of the oracle and every loss within 1e-5, or, where the
+    oracle itself is that sensitive, within three times the spread the
+    oracle shows over the same window when its gradients are perturbed at
+    rounding size (1e-9 and 5e-8 relative, three seeds each; stored with the
+    whole run in <name>_window_envelope.npz)."""
     from paper_2607_00579_amd.api import EdgePlan
     g = golden(name)
     prob = problem(name)
@@ -118,7 +136,8 @@ def test_trajectory_windows_from_oracle_states(gpu, name):
     loss = torch.zeros(plan.n_scenes, dtype=torch.float64, device=dev)
     plan.capture_iteration(poses, m, v, step, loss)
     n_win = g["poses_every10"].shape[0] - 1
-    worst_ang, worst_loss = 0.0, 0.0
+    ang = np.zeros(n_win)
+    lerr = np.zeros(n_win)
     for k in range(n_win):
         poses.copy_(torch.from_numpy(g["poses_every10"][k]))
         m.copy_(torch.from_numpy(g["m_every10"][k]))
@@ -128,13 +147,29 @@ def test_trajectory_windows_from_oracle_states(gpu, name):
         for s in range(steps):
             plan.launch_iteration()
             ref = g["loss"][10 * k + s, 0]
-            worst_loss = max(worst_loss, abs(float(loss[0].item()) - ref) / abs(ref))
-        ang, _ = pose_diffs(poses.cpu().numpy(), g["poses_every10"][k + 1])
-        worst_ang = max(worst_ang, ang)
-    say(f"{name}: {n_win} windows of 10 steps: worst rotation diff {worst_ang:.2e} deg, "
-        f"worst loss rel err {worst_loss:.2e}")
-    assert worst_ang < 5e-3
-    assert worst_loss < 1e-5
+            lerr[k] = max(lerr[k], abs(float(loss[0].item()) - ref) / abs(ref))
+        ang[k] = pose_diffs(poses.cpu().numpy(), g["poses_every10"][k + 1])[0]
+    bar_rot = np.full(n_win, WINDOW_BAR)
+    bar_loss = np.full(n_win, LOSS_BAR)
+    path = os.path.join(GOLDEN, f"{name}_window_envelope.npz")
+    if os.path.exists(path):
+        from tests.golden.make_golden import input_checksum
+        env = np.load(path, allow_pickle=False)
+        assert str(env["checksum"]) == input_checksum(prob), "generator changed: rerun make_golden"
+        env_rot, env_loss = env["rot_dev"].max(axis=0), env["loss_dev"].max(axis=0)
+        bar_rot = np.maximum(bar_rot, ENVELOPE_FACTOR * env_rot)
+        bar_loss = np.maximum(bar_loss, ENVELOPE_FACTOR * env_loss)
+        say(f"{name}: oracle's own window spread up to {env_rot.max():.2e} deg, "
+            f"{int((ENVELOPE_FACTOR * env_rot > WINDOW_BAR).sum())} of {n_win} windows above "
+            f"a third of the bar")
+    else:
+        assert name == "c1", f"{path} missing: run tests/golden/make_golden.py"
+    k = int(np.argmax(ang / bar_rot))
+    say(f"{name}: {n_win} windows of 10 steps: worst rotation diff {ang.max():.2e} deg, "
+        f"worst against its bar {ang[k]:.2e} of {bar_rot[k]:.2e} (window {k}); "
+        f"worst loss rel err {lerr.max():.2e}")
+    assert (ang <= bar_rot).all(), (ang, bar_rot)
+    assert (lerr <= bar_loss).all(), (lerr, bar_loss)
 
 
 def golden_prefix(name):
@@ -151,20 +186,6 @@ def golden_envelope(name):
     return e
 
 
-# The oracle's own spread at step s: the largest deviation from the stored
-# trajectory that any of its perturbed runs (gradients moved by 1e-9 and 5e-8
-# relative, several seeds) shows at or before s.  The GPU's poses may deviate
-# by ENVELOPE_FACTOR times that spread, never less than the north-star bar;
-# its losses are held to LOSS_BAR while the oracle's own loss spread stays
-# below LOSS_BAR / ENVELOPE_FACTOR, and afterwards, when the poses carry the
-# comparison, to LOSS_SANITY times the spread (a handful of sampled runs
-# underestimate the tail of a chaotic spread: on the 32-view workload the
-# GPU's loss leads the sampled spread by up to 3.5x around steps 12-15 while
-# its rotations stay inside it).
-ENVELOPE_FACTOR = 3.0
-LOSS_SANITY = 10.0
-ROT_BAR = 0.01          # degrees
-LOSS_BAR = 1e-5         # relative
 
 
 @pytest.mark.parametrize("name", ["c3", "c5", "c4"])
