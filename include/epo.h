@@ -205,7 +205,7 @@ EPO_API epo_status epo_plan_view_records(epo_plan plan, int32_t v, uint64_t* rec
  * over the pairs drawn for this launch, see 3c).
  *
  *   poses       float64 [V][3][4]
- *   lambda      float32 [n_scenes] clamp per scene, each <= params.lambda_max
+ *   lambda      float32 [n_scenes] clamp per scene, each in [0, params.lambda_max]
  *   loss        float64 [n_scenes] (written)
  *   pair_cost   float64 [n_pairs] L_d, or NULL
  *   pair_valid  int32 [n_pairs] n_d, or NULL
@@ -671,7 +671,7 @@ EPO_API epo_status epo_plan_pair_records(epo_plan plan, int32_t d, uint64_t* rec
                                          int64_t capacity, int64_t* count);
 
 /* Device status word of the plan, OR-ed by the kernels: bit 0 = a non-finite
- * per-pair sum was seen, bit 1 = a lambda above lambda_max was seen, bit 2 = a
+ * per-pair sum was seen, bit 1 = a lambda outside [0, lambda_max] was seen, bit 2 = a
  * refined focal length or depth was not finite (or a focal length <= 0).  Copies
  * to *flags (host) after synchronising `stream`, then clears the word. */
 EPO_API epo_status epo_get_device_status(epo_plan plan, int32_t* flags, void* stream);

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void pair_setup_kernel(
     o.wcells = wh[2 * j + 0] - 1;
     o.hcells = wh[2 * j + 1] - 1;
     const float lam = lambda[st.scene];
-    if (!(lam <= lambda_max)) atomicOr(status, 2);
+    if (!(lam >= 0.0f && lam <= lambda_max)) atomicOr(status, 2);
     o.lambda = lam;
     // texture addressing of the format in use: blocked u8 quads (blk_off
     // given: width = 128 (blocks per row - 1), the row-of-blocks stride less

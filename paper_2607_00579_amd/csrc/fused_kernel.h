@@ -1,8 +1,8 @@
 // Device code of the fused residual + adjoint kernel and its per-tile
 // reduction (paper Eqs. pi, d_ij, L_ij; supplementary Alg. 3 and Sec. A1.2
 // "Per-iteration kernels"): per residual, residual.h; per thread, float64
-// sums; per workgroup, wave64 butterflies and an LDS step to one float64
-// partial per tile.  Included by edge_cost.hip, which holds the host-side
+// sums; per wave, lane-swap folds and row rotations (no LDS); per workgroup,
+// an LDS step to one float64 partial per tile.  Included by edge_cost.hip, which holds the host-side
 // launches.  The measured counters of this kernel are keyed to the text of
 // this file, residual.h and the data layout section of epo_internal.h.
 #pragma once
@@ -18,20 +18,14 @@ constexpr int kBlock = 256;
 // fused residual + adjoint + tile reduction
 // ---------------------------------------------------------------------------
 
-// per-thread sums: the float32 terms of the U residuals a thread has in flight
-// are added in float32 (one more rounding, of the size of each term's own
-// product rounding), then into float64 (the pose-gradient sums cancel
-// strongly, up to a few hundred in sum |term| / |sum|); the valid count in
-// integers; ft, fs are the focal-scale sums of the refinement variant
+// per-thread sums in float64: from the float32 adjoint factors A_u, A_v of
+// each residual (rounded once), the pose-gradient terms are formed and added
+// in float64 with fused multiply-adds (the sums cancel strongly, up to a few
+// hundred in sum |term| / |sum|); ft, fs are the focal-scale sums of the
+// refinement variant
 struct Acc {
     double S, g0, g1, g2, g3, g4, g5;
     double ft, fs;
-};
-
-// the float32 terms of one residual
-struct Terms {
-    float S, g0, g1, g2, g3, g4, g5, ft, fs, dz;
-    bool valid;
 };
 
 // refinement variant (EXT): besides the pose terms, per pair
@@ -40,37 +34,135 @@ struct Terms {
 //   F_s = sum of f_i dH/df_i = sum of Z (dH/dX') . (c - m)
 //         (X_c = Z ((u - cx)/fx, (v - cy)/fy, 1) and fx, fy scale together, so
 //         dX'/dlog f_i = Z R_ji (-(u - cx)/fx, -(v - cy)/fy, 0) = Z (c - m) with
-//         c = R_ji e_z the third column of R_ji),
-//   and the residual's depth derivative dH/dZ (stored for the source-major
-//   depth pass)
+//         c = R_ji e_z the third column of R_ji)
+// The pose terms (dH/dX' = (A_u, A_v, w) / z, then dH/dxi = (dH/dX', X' x
+// dH/dX') in the target frame, written with X' = z (x_n, y_n, 1)):
+//   g0..g2 = (A_u, A_v, w) / z,
+//   g3 = y_n w - A_v, g4 = A_u - x_n w, g5 = x_n A_v - y_n A_u.
+// An invalid residual has A_u = A_v = rho = 0 and finite coordinates, so it
+// adds exact zeros.
 template <bool EXT>
-__device__ __forceinline__ Terms residual_terms(const Residual& r, const uint2 rec,
-                                                const double* c3) {
-    Terms t;
-    t.S = r.rho;
-    t.valid = r.valid;
-    t.g0 = r.Au * r.rz;
-    t.g1 = r.Av * r.rz;
-    t.g2 = r.w * r.rz;
-    t.g3 = fmaf(r.yn, r.w, -r.Av);
-    t.g4 = fmaf(-r.xn, r.w, r.Au);
-    t.g5 = fmaf(r.xn, r.Av, -r.yn * r.Au);
-    t.ft = t.fs = t.dz = 0.0f;
+__device__ __forceinline__ void accumulate(Acc& a, const Residual& r, const uint2 rec,
+                                           const double* c3) {
+    const double Au = (double)r.Au, Av = (double)r.Av;
+    const double w = -fma(Au, r.xd, Av * r.yd);
+    a.S += (double)r.rho;
+    a.g0 = fma(Au, r.rd, a.g0);
+    a.g1 = fma(Av, r.rd, a.g1);
+    a.g2 = fma(w, r.rd, a.g2);
+    a.g3 = fma(r.yd, w, a.g3) - Av;
+    a.g4 = fma(-r.xd, w, a.g4) + Au;
+    a.g5 = fma(-r.yd, Au, fma(r.xd, Av, a.g5));
     if constexpr (EXT) {
-        t.ft = -r.w;
-        const float cx = (float)(c3[0] - r.mx), cy = (float)(c3[1] - r.my),
-                    cz = (float)(c3[2] - r.mz);
-        const float zr = __uint_as_float(rec.y) * r.rz;
-        t.fs = zr * fmaf(r.Au, cx, fmaf(r.Av, cy, r.w * cz));
-        t.dz = depth_derivative(r);
+        a.ft -= w;
+        const double zr = (double)__uint_as_float(rec.y) * r.rd;
+        a.fs = fma(zr, fma(Au, c3[0] - r.mx, fma(Av, c3[1] - r.my, w * (c3[2] - r.mz))), a.fs);
     }
-    return t;
 }
 
-__device__ inline double wave_sum(double x) {
+// U consecutive rows of a tile (U kBlock residuals, one per thread and row)
+// into the thread's sums; n counts the thread's valid residuals
+template <int FMT, int U, bool EXT>
+__device__ __forceinline__ void tile_rows(Acc& a, uint32_t& n, const uint2* __restrict__ rec,
+                                          int k0, int count, const PairDesc& pd,
+                                          const uint32_t* __restrict__ texj, const float* lut,
+                                          float delta, double zmin, const double* c3, float* dzt,
+                                          int64_t dzn) {
+    const int tid = threadIdx.x;
+    uint2 r[U];
+    // rows past the tile's end read the records that follow it (the record
+    // array carries kRecordPad zero records past its end, more than the at
+    // most kBlock - 1 rows a tile's last row overshoots) and are masked, so
+    // the loads issue back to back without a branch; the row base is
+    // wave-uniform and each lane adds its own fixed byte offset
+    const char* rowb = reinterpret_cast<const char*>(rec) + (size_t)k0 * kBlock * 8;
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    for (int k = 0; k < U; ++k)
+        r[k] = *reinterpret_cast<const uint2*>(rowb + ((uint32_t)tid << 3) + k * kBlock * 8);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        // row (k0 + k) kBlock + tid is inside the tile: compared against a
+        // wave-uniform limit, so no per-lane index arithmetic
+        const bool in = tid < count - (k0 + k) * kBlock;
+        const Residual rs = eval_residual<FMT>(r[k], in, pd, texj, lut, delta, zmin);
+        accumulate<EXT>(a, rs, r[k], c3);
+        // the depth derivative dH/dZ for the source-major depth pass
+        if (EXT && dzt && in) dzt[(int64_t)(k0 + k) * kBlock * dzn + tid] = depth_derivative(rs);
+        n += rs.valid ? 1u : 0u;
+    }
+}
+
+// Wave reduction of several float64 sums at once.  Each fold halves the
+// lanes a sum spans and pairs two sums in one register: fold32 trades lanes
+// 32..63 of x with lanes 0..31 of y (v_permlane32_swap) and adds, so lanes
+// 0..31 then hold x summed over lanes l and l + 32, lanes 32..63 y's;
+// fold16 does the same between the odd 16-lane rows of x and the even rows
+// of y (v_permlane16_swap), leaving x's sums in rows 0 and 2 and y's in rows
+// 1 and 3.  row_sum finishes within each 16-lane row by rotations (DPP
+// row_ror), after which every lane of a row holds the row's total.  No LDS
+// traffic and half the additions of one butterfly per sum.
+__device__ __forceinline__ double join(uint32_t lo, uint32_t hi) {
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double fold32(double x, double y) {
+    const uint64_t xb = (uint64_t)__double_as_longlong(x), yb = (uint64_t)__double_as_longlong(y);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)xb, (uint32_t)yb, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(xb >> 32), (uint32_t)(yb >> 32),
+                                                     false, false);
+    return join(lo[0], hi[0]) + join(lo[1], hi[1]);
+}
+
+__device__ __forceinline__ double fold16(double x, double y) {
+    const uint64_t xb = (uint64_t)__double_as_longlong(x), yb = (uint64_t)__double_as_longlong(y);
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)xb, (uint32_t)yb, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(xb >> 32), (uint32_t)(yb >> 32),
+                                                     false, false);
+    return join(lo[0], hi[0]) + join(lo[1], hi[1]);
+}
+
+template <int N>
+__device__ __forceinline__ double row_ror(double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, 0x120 + N, 0xf, 0xf, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), 0x120 + N, 0xf, 0xf, false);
+    return join(lo, hi);
+}
+
+__device__ __forceinline__ double row_sum(double x) {
+    x += row_ror<8>(x);
+    x += row_ror<4>(x);
+    x += row_ror<2>(x);
+    x += row_ror<1>(x);
     return x;
+}
+
+// the wave totals of v[0..NV) (NV = 8 or 10) into red[0..NV)
+template <int NV>
+__device__ __forceinline__ void wave_sums(const double (&v)[NV], double* red) {
+    static_assert(NV == 8 || NV == 10, "");
+    constexpr int NA = (NV + 1) / 2, NB = (NA + 1) / 2;
+    double A[NA], B[NB];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) A[k] = fold32(v[2 * k], v[2 * k + 1 < NV ? 2 * k + 1 : 2 * k]);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) B[k] = fold16(A[2 * k], A[2 * k + 1 < NA ? 2 * k + 1 : 2 * k]);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) B[k] = row_sum(B[k]);
+    // row r of B[k] holds A[a], a = 2 k + (r & 1), and of that its lower
+    // (r < 2) or upper half: v[2 a + (r >> 1)]; a row that holds a sum paired
+    // with itself (odd counts) is a duplicate and not written
+    const int lane = threadIdx.x & 63;
+    if ((lane & 15) == 0) {
+        const int r = lane >> 4;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int a = 2 * k + (r & 1);
+            const int src = 2 * a + (r >> 1);
+            if (a < NA && src < NV) red[src] = B[k];
+        }
+    }
 }
 
 // per-tile sums: S, n, G[6] into partials[t]; the refinement variant adds
@@ -114,84 +206,32 @@ __device__ __forceinline__ void do_tile(int64_t t, const uint2* __restrict__ rec
         }
     }
     Acc a{0, 0, 0, 0, 0, 0, 0, 0, 0};
-    int n = 0;                                  // valid residuals of this thread
-    // two residuals in flight per thread (59 VGPRs, so the SIMD keeps eight
-    // waves to hide the record load and the dependent tap gather); unrolling
-    // all P would multiply the float64 live ranges (the refinement variant
-    // keeps one: its focal sums and ray components would push two past 64
-    // VGPRs, below eight waves per SIMD)
+    uint32_t n = 0;                             // valid residuals of this thread
+    // two residuals in flight per thread (the SIMD keeps eight waves to hide
+    // the record load and the dependent tap gather); unrolling all P would
+    // multiply the float64 live ranges (the refinement variant keeps one: its
+    // focal sums and ray components would push two past 64 VGPRs, below
+    // eight waves per SIMD)
     constexpr int U = (P < 2 || EXT) ? 1 : 2;
     // the trip count follows the tile's own size (uniform over the
-    // workgroup), so a pair's short last tile costs only its residuals
+    // workgroup), so a pair's short last tile costs only its rows; an odd
+    // last row runs alone
     const int rows = (tl.count + kBlock - 1) / kBlock;
+    int k0 = 0;
 #pragma unroll 1
-    for (int k0 = 0; k0 < rows; k0 += U) {
-        uint2 r[U];
-        // rows past the tile's end read the records that follow it (the
-        // record array carries kRecordPad zero records past its end, more
-        // than the at most U * kBlock - 1 rows a tile's last iteration
-        // overshoots) and are masked, so both loads issue back to back
-        // without a branch; the row base is wave-uniform and each lane adds
-        // its own fixed byte offset
-        const char* rowb = reinterpret_cast<const char*>(rec) + (size_t)k0 * kBlock * 8;
-#pragma unroll
-        for (int k = 0; k < U; ++k)
-            r[k] = *reinterpret_cast<const uint2*>(rowb + ((uint32_t)tid << 3) + k * kBlock * 8);
-        Terms tt[U];
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            // row (k0 + k) kBlock + tid is inside the tile: compared against a
-            // wave-uniform limit, so no per-lane index arithmetic
-            const bool in = tid < tl.count - (k0 + k) * kBlock;
-            const Residual rs = eval_residual<FMT>(r[k], in, pd, texj, lut, delta, zmin);
-            tt[k] = residual_terms<EXT>(rs, r[k], c3);
-            if (EXT && dzt && in) dzt[(int64_t)(k0 + k) * kBlock * dzn + tid] = tt[k].dz;
-            n += tt[k].valid ? 1 : 0;
-        }
-#pragma unroll
-        for (int k = 1; k < U; ++k) {
-            tt[0].S += tt[k].S;
-            tt[0].g0 += tt[k].g0;
-            tt[0].g1 += tt[k].g1;
-            tt[0].g2 += tt[k].g2;
-            tt[0].g3 += tt[k].g3;
-            tt[0].g4 += tt[k].g4;
-            tt[0].g5 += tt[k].g5;
-            tt[0].ft += tt[k].ft;
-            tt[0].fs += tt[k].fs;
-        }
-        a.S += (double)tt[0].S;
-        a.g0 += (double)tt[0].g0;
-        a.g1 += (double)tt[0].g1;
-        a.g2 += (double)tt[0].g2;
-        a.g3 += (double)tt[0].g3;
-        a.g4 += (double)tt[0].g4;
-        a.g5 += (double)tt[0].g5;
-        if constexpr (EXT) {
-            a.ft += (double)tt[0].ft;
-            a.fs += (double)tt[0].fs;
-        }
-    }
+    for (; k0 + U <= rows; k0 += U)
+        tile_rows<FMT, U, EXT>(a, n, rec, k0, tl.count, pd, texj, lut, delta, zmin, c3, dzt, dzn);
+    if (U > 1 && k0 < rows)
+        tile_rows<FMT, 1, EXT>(a, n, rec, k0, tl.count, pd, texj, lut, delta, zmin, c3, dzt, dzn);
+    // per wave: S, n, G[6] (and F_t, F_s) into red[wave][0..NS)
     constexpr int NS = EXT ? 10 : 8;
-    double s[NS];
-    const int wave = tid >> 6, lane = tid & 63;
-    s[0] = a.S;
-    s[1] = (double)n;
-    s[2] = a.g0;
-    s[3] = a.g1;
-    s[4] = a.g2;
-    s[5] = a.g3;
-    s[6] = a.g4;
-    s[7] = a.g5;
+    const int wave = tid >> 6;
     if constexpr (EXT) {
-        s[8] = a.ft;
-        s[9] = a.fs;
-    }
-#pragma unroll
-    for (int k = 0; k < NS; ++k) s[k] = wave_sum(s[k]);
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < NS; ++k) red[wave][k] = s[k];
+        const double v[10] = {a.S, (double)n, a.g0, a.g1, a.g2, a.g3, a.g4, a.g5, a.ft, a.fs};
+        wave_sums<10>(v, red[wave]);
+    } else {
+        const double v[8] = {a.S, (double)n, a.g0, a.g1, a.g2, a.g3, a.g4, a.g5};
+        wave_sums<8>(v, red[wave]);
     }
     __syncthreads();
     if (tid < NS) {

@@ -19,12 +19,19 @@
 namespace epo {
 
 // The tap loads address the view's texture with a 32-bit byte offset from a
-// wave-uniform base (the global_load "saddr" form: no 64-bit address
-// arithmetic per residual).  A view has at most 16384^2 pixels, so a 4-byte
-// texel offset fits in 32 bits; the 16-byte texels of format 3 do not, and use
-// a 64-bit index.
+// wave-uniform base.  A view has at most 16384^2 pixels, so a 4-byte texel
+// offset fits in 32 bits; the 16-byte texels of format 3 do not, and use a
+// 64-bit index.  (Raw buffer loads with the same offsets, which would spare
+// the 64-bit address add, measured 2 % slower on the fused kernel.)
 __device__ __forceinline__ uint32_t texel32(const uint32_t* __restrict__ tex, uint32_t byte_off) {
     return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(tex) + byte_off);
+}
+
+// An invalid residual reads texel 0 of the view (a mask
+// rather than a select keeps the compiler from branching around the index
+// arithmetic).
+__device__ __forceinline__ uint32_t mask_texel(uint32_t idx, bool valid) {
+    return idx & (valid ? ~0u : 0u);
 }
 
 template <int FMT>
@@ -122,9 +129,10 @@ struct Taps<3> {
 struct Residual {
     float rho;              // Huber value (0 if invalid)
     float Au, Av, w;        // adjoint terms (0 if invalid)
-    float xn, yn, rz;       // normalised target coordinates, 1 / z (0 if invalid)
+    float xn, yn, rz;       // normalised target coordinates, 1 / z
     bool valid;
     double mx, my, mz;      // unit-depth ray m = M (u, v, 1)^T in the target frame
+    double xd, yd, rd;      // x_n, y_n, 1 / z in float64
 };
 
 // first step: the projected coordinate, the validity test, the cell split and
@@ -135,6 +143,7 @@ struct Projected {
     bool valid;
     uint32_t idx;           // the format's texel index (0 if invalid)
     double mx, my, mz;      // unit-depth ray m = M (u, v, 1)^T in the target frame
+    double xd, yd, rd;      // x_n, y_n, 1 / z in float64
 };
 
 template <int FMT>
@@ -181,8 +190,10 @@ __device__ __forceinline__ Projected project_residual(const uint2 rec, bool acti
     r.be = (float)(vpd - fy0);
     // y0 < H and W are below 2^24 whenever the residual is valid; idx is
     // the format's texel index (byte offset for format 2)
-    // (a mask rather than a select keeps the compiler from branching here)
-    r.idx = Taps<FMT>::index(x0, y0, pd.width) & (0u - (uint32_t)r.valid);
+    r.idx = mask_texel(Taps<FMT>::index(x0, y0, pd.width), r.valid);
+    r.xd = xnd;
+    r.yd = ynd;
+    r.rd = rzd;
     r.xn = (float)xnd;
     r.yn = (float)ynd;
     r.rz = (float)rzd;
@@ -201,6 +212,9 @@ __device__ __forceinline__ Residual finish_residual(const Projected& p, float d0
     r.xn = p.xn;
     r.yn = p.yn;
     r.rz = p.rz;
+    r.xd = p.xd;
+    r.yd = p.yd;
+    r.rd = p.rd;
     const bool valid = p.valid;
     // bilinear sample and its gradient; the cell's cross term
     // d11 - d10 - d01 + d00 is formed once and serves both directions
@@ -211,13 +225,14 @@ __device__ __forceinline__ Residual finish_residual(const Projected& p, float d0
     const float D = fmaf(p.be, gv, fmaf(p.al, e0, d00));
     // Huber of the clamped distance: with m = min(d, delta),
     // m (d - m / 2) is d^2 / 2 below delta and delta (d - delta / 2) above
-    // (the same float32 roundings as either branch), and m is the derivative
-    const bool unclamped = D < pd.lambda;
-    const float dh = fminf(D, pd.lambda);          // D is finite
+    // (the same float32 roundings as either branch), and m is the derivative,
+    // 0 where the distance is clamped (d >= lambda).  An invalid residual
+    // takes d = 0: value and derivative 0
+    const float Dv = valid ? D : 0.0f;              // D is finite
+    const float dh = fminf(Dv, pd.lambda);
     const float m = fminf(dh, delta);
-    const float rho = m * fmaf(-0.5f, m, dh);
-    r.rho = valid ? rho : 0.0f;
-    const float drho = (valid && unclamped) ? m : 0.0f;
+    r.rho = m * fmaf(-0.5f, m, dh);
+    const float drho = Dv < pd.lambda ? m : 0.0f;
     r.Au = drho * gu * pd.fx;
     r.Av = drho * gv * pd.fy;
     r.w = -fmaf(r.Au, r.xn, r.Av * r.yn);

@@ -247,11 +247,13 @@ def test_empty_target_and_identity_pair(gpu):
     assert np.isclose(g["loss"][0], 2.0 / 3.0 * 9.5)
 
 
-def test_lambda_above_plan_maximum_is_flagged(gpu):
+def test_lambda_outside_plan_range_is_flagged(gpu):
     p = problem("c1")
     plan = plan_for(p)
     plan.device_status()
     gpu_eval(plan, p.poses_init, 12.0)
+    assert plan.device_status() & 2
+    gpu_eval(plan, p.poses_init, -1.0)
     assert plan.device_status() & 2
     gpu_eval(plan, p.poses_init, 9.0)
     assert plan.device_status() == 0
