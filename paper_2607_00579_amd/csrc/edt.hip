@@ -14,15 +14,16 @@
 //                the segments give every view H/64 times the waves of a
 //                thread-per-column pass.
 //   row pass     d2(x, y) = min over q of f(q, y) + (x - q)^2.  One workgroup
-//                per row stages f of the row and its minimum per 16-pixel
-//                block in LDS; each x searches outward block by block,
-//                scanning only blocks whose minimum plus the squared
-//                distance could beat its best value, and stops when the
-//                distance alone cannot (a parallel bounded search instead of
-//                a sequential envelope per row).  Integer arithmetic
+//                per row stages f of the row and its minima per 16, 256 and
+//                4096 pixels in LDS.  The minimizing q is monotone in x, so
+//                the pass first finds a minimizer at every 16th pixel (an
+//                exact search pruned by the minima), and every other pixel
+//                then only scans the q between the minimizers of the block
+//                starts on either side of it (or, when that range is wide,
+//                searches from the bound the two give).  Integer arithmetic
 //                throughout: the exact minimum.  The same kernel writes
 //                DTF = sqrt(d2) in float32.
-//
+
 // Views are processed in batches whose descriptors travel as a kernel
 // argument, so the call needs no device allocation.
 #include "epo_internal.h"
@@ -129,40 +130,67 @@ __global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ ed
 // One workgroup per row.  The row's column-pass values live in dtf (the
 // call's scratch); the workgroup reads all of them into LDS before any of its
 // threads writes the row's DTF, and no other workgroup touches the row.
-// d2(x) = min over q of f(q) + (x - q)^2 is found by an exact search over a
-// three-level hierarchy of minima in LDS: blocks of 16 pixels, groups of 16
-// blocks (256 px), supers of 16 groups (4096 px).  A pixel scans its own
-// block, then the other blocks of its group, the other groups of its super,
-// and the other supers, each level outward from the pixel and nearest first
-// inside a region it descends into.  A region (block, group, super) is
-// descended into only if its minimum f plus the squared distance from x to
-// its nearest pixel is below the best value so far, and a level's outward
-// walk ends once its nearer remaining region is at least sqrt(best) away.
-// Every pixel that can attain the minimum is scanned, so the result is the
-// exact minimum.  Near an edge the search ends inside the own group (about
-// D/16 block tests, D the distance to the nearest edge); far from every edge
-// the minima skip empty stretches 4096 or 256 pixels at a time, so a pixel
-// costs O(W/4096 + 16 + 16 + 16) tests whatever the map (a 16384 x 16384 map
-// with one edge pixel: 257 ms with blocks alone).
+//
+// Minimizers are monotone: with p_q(x) = f(q) + (x - q)^2 and q < q',
+// p_q(x) - p_q'(x) = f(q) - f(q') + (q' - q)(2x - q - q') grows with x, so
+// once q' is a minimizer at x, no q < q' is one at any x' > x (and no
+// q > q' at any x' < x).  Hence for X0 < x < X1 every minimizer of x lies in
+// [a minimizer of X0, a minimizer of X1].  Phase 1 finds d2 and a minimizer
+// at every block start X0 = 16 b by the exact search below; phase 2 takes
+// every other pixel's minimum over the q between the minimizers of its own
+// and the next block start (the last block's right end is the row's end):
+// by scanning the whole blocks that hold them when there are at most
+// kScanMax, else by the same search started from the better of the two end
+// values.
+//
+// The search: a three-level hierarchy of minima in LDS: blocks of 16 pixels,
+// groups of 16 blocks (256 px), supers of 16 groups (4096 px).  A pixel scans
+// its own block, then the other blocks of its group, the other groups of its
+// super, and the other supers, each level outward from the pixel and nearest
+// first inside a region it descends into.  A region is descended into only
+// if its minimum f plus the squared distance from x to its nearest pixel is
+// below the best value so far, and a level's outward walk ends once its
+// nearer remaining region is at least sqrt(best) away.  Every pixel that can
+// attain the minimum is scanned, so the result is the exact minimum, and the
+// recorded q (the first to reach the final value) is a minimizer.  Near an
+// edge the search ends inside the own group; far from every edge the minima
+// skip empty stretches 4096 or 256 pixels at a time, so a search costs
+// O(W/4096 + 16 + 16 + 16) tests whatever the map.
 constexpr int kRowBlk = 16;
 constexpr int kRowFan = 16;                 // blocks per group, groups per super
 constexpr int kGroupPx = kRowBlk * kRowFan;
 constexpr int kSuperPx = kGroupPx * kRowFan;
+constexpr int kScanMax = 48;                // widest range phase 2 scans blockwise
+constexpr int kBlkStride = kRowBlk + 1;     // LDS ints per block of the row
 
-// LDS per row: f (W), block, group and super minima
+// The row sits in LDS with one padding int after every 16 pixels: pixel q at
+// q + q / 16, so block b starts at 17 b and the blocks that different lanes
+// scan at once start on different banks (with 16 ints per block they would
+// all fall on two).  The padding of the last block (pixels W .. 16 nb - 1)
+// holds kInf, so every block is scanned whole.
+__device__ __forceinline__ int rix(int q) { return q + (q >> 4); }
+
+// LDS per row: f (17 per block), block, group and super minima, block-start
+// minimizers
 __host__ __device__ inline int edt_row_lds_ints(int W) {
     const int nb = (W + kRowBlk - 1) / kRowBlk;
     const int ng = (W + kGroupPx - 1) / kGroupPx;
     const int ns = (W + kSuperPx - 1) / kSuperPx;
-    return W + nb + ng + ns;
+    return kBlkStride * nb + nb + ng + ns + nb + 1;
 }
 
 struct RowMinima {
-    const int32_t* row;
+    const int32_t* row;                     // padded: pixel q at rix(q)
     const int32_t* bmin;
     const int32_t* gmin;
     const int32_t* smin;
     int W;
+};
+
+// the best value found so far and the first q that reached it
+struct Best {
+    int32_t v;
+    int32_t q;
 };
 
 // squared distance from x to the nearest pixel of [lo, hi] (x outside it)
@@ -171,138 +199,213 @@ __device__ __forceinline__ int gap2(int x, int lo, int hi) {
     return d * d;
 }
 
-__device__ __forceinline__ void scan_block(const RowMinima& m, int x, int b, int32_t& best) {
-    const int q0 = kRowBlk * b;
-    if (q0 + kRowBlk <= m.W) {
+// block blk (its padding pixels hold kInf), minimizer recorded
+__device__ __forceinline__ void scan_block(const RowMinima& m, int x, int blk, Best& b) {
+    const int32_t* f = m.row + kBlkStride * blk;
+    const int d0 = x - kRowBlk * blk;
 #pragma unroll
-        for (int u = 0; u < kRowBlk; ++u) best = min(best, m.row[q0 + u] + (x - q0 - u) * (x - q0 - u));
-    } else {
-        for (int q = q0; q < m.W; ++q) best = min(best, m.row[q] + (x - q) * (x - q));
+    for (int u = 0; u < kRowBlk; ++u) {
+        const int32_t v = f[u] + (d0 - u) * (d0 - u);
+        if (v < b.v) {
+            b.v = v;
+            b.q = kRowBlk * blk + u;
+        }
     }
 }
 
+// the value alone (phase 2 needs no minimizer)
+__device__ __forceinline__ int32_t scan_block_v(const RowMinima& m, int x, int blk, int32_t v) {
+    const int32_t* f = m.row + kBlkStride * blk;
+    const int d0 = x - kRowBlk * blk;
+#pragma unroll
+    for (int u = 0; u < kRowBlk; ++u) v = min(v, f[u] + (d0 - u) * (d0 - u));
+    return v;
+}
+
 // the blocks of group g, nearest to x first (g lies wholly on one side of x)
-__device__ __forceinline__ void scan_group(const RowMinima& m, int x, int g, int32_t& best) {
+__device__ __forceinline__ void scan_group(const RowMinima& m, int x, int g, Best& b) {
     const int nb = (m.W + kRowBlk - 1) / kRowBlk;
     const int b0 = kRowFan * g, b1 = min(b0 + kRowFan, nb) - 1;
     const bool right = kRowBlk * b0 > x;
     for (int k = 0; k <= b1 - b0; ++k) {
-        const int b = right ? b0 + k : b1 - k;
-        const int d2b = gap2(x, kRowBlk * b, kRowBlk * b + kRowBlk - 1);
-        if (d2b >= best) break;                  // the rest of the group is farther
-        if (m.bmin[b] + d2b < best) scan_block(m, x, b, best);
+        const int blk = right ? b0 + k : b1 - k;
+        const int d2b = gap2(x, kRowBlk * blk, kRowBlk * blk + kRowBlk - 1);
+        if (d2b >= b.v) break;                   // the rest of the group is farther
+        if (m.bmin[blk] + d2b < b.v) scan_block(m, x, blk, b);
     }
 }
 
 // the groups of super s, nearest to x first (s lies wholly on one side of x)
-__device__ __forceinline__ void scan_super(const RowMinima& m, int x, int sp, int32_t& best) {
+__device__ __forceinline__ void scan_super(const RowMinima& m, int x, int sp, Best& b) {
     const int ng = (m.W + kGroupPx - 1) / kGroupPx;
     const int g0 = kRowFan * sp, g1 = min(g0 + kRowFan, ng) - 1;
     const bool right = kGroupPx * g0 > x;
     for (int k = 0; k <= g1 - g0; ++k) {
         const int g = right ? g0 + k : g1 - k;
         const int d2g = gap2(x, kGroupPx * g, kGroupPx * g + kGroupPx - 1);
-        if (d2g >= best) break;
-        if (m.gmin[g] + d2g < best) scan_group(m, x, g, best);
+        if (d2g >= b.v) break;
+        if (m.gmin[g] + d2g < b.v) scan_group(m, x, g, b);
     }
 }
 
-__global__ __launch_bounds__(256) void edt_rows(const int32_t* __restrict__ colsq,
-                                               int32_t* __restrict__ d2, float* __restrict__ dtf,
-                                               EdtBatch b) {
+// the exact minimum over the row for pixel x, from the bound b (a value some
+// q attains, with that q)
+__device__ Best search(const RowMinima& m, int x, Best b) {
+    const int nb = (m.W + kRowBlk - 1) / kRowBlk;
+    const int ng = (m.W + kGroupPx - 1) / kGroupPx;
+    const int ns = (m.W + kSuperPx - 1) / kSuperPx;
+    const int bx = x / kRowBlk, gx = x / kGroupPx, sx = x / kSuperPx;
+    if (m.bmin[bx] < b.v) scan_block(m, x, bx, b);
+    // the other blocks of the own group, outward
+    {
+        const int lo = kRowFan * gx, hi = min(lo + kRowFan, nb) - 1;
+        for (int R = 1;; ++R) {
+            const int bl = bx - R, br = bx + R;
+            const bool lin = bl >= lo, rin = br <= hi;
+            if (!lin && !rin) break;
+            const int dl = lin ? gap2(x, kRowBlk * bl, kRowBlk * bl + kRowBlk - 1) : 0x7fffffff;
+            const int dr = rin ? gap2(x, kRowBlk * br, kRowBlk * br + kRowBlk - 1) : 0x7fffffff;
+            if (min(dl, dr) >= b.v) break;
+            if (lin && m.bmin[bl] + dl < b.v) scan_block(m, x, bl, b);
+            if (rin && m.bmin[br] + dr < b.v) scan_block(m, x, br, b);
+        }
+    }
+    // the other groups of the own super, outward
+    {
+        const int lo = kRowFan * sx, hi = min(lo + kRowFan, ng) - 1;
+        for (int R = 1;; ++R) {
+            const int gl = gx - R, gr = gx + R;
+            const bool lin = gl >= lo, rin = gr <= hi;
+            if (!lin && !rin) break;
+            const int dl = lin ? gap2(x, kGroupPx * gl, kGroupPx * gl + kGroupPx - 1) : 0x7fffffff;
+            const int dr = rin ? gap2(x, kGroupPx * gr, kGroupPx * gr + kGroupPx - 1) : 0x7fffffff;
+            if (min(dl, dr) >= b.v) break;
+            if (lin && m.gmin[gl] + dl < b.v) scan_group(m, x, gl, b);
+            if (rin && m.gmin[gr] + dr < b.v) scan_group(m, x, gr, b);
+        }
+    }
+    // the other supers, outward
+    for (int R = 1; ns > 1; ++R) {
+        const int sl = sx - R, sr = sx + R;
+        const bool lin = sl >= 0, rin = sr < ns;
+        if (!lin && !rin) break;
+        const int dl = lin ? gap2(x, kSuperPx * sl, kSuperPx * sl + kSuperPx - 1) : 0x7fffffff;
+        const int dr = rin ? gap2(x, kSuperPx * sr, kSuperPx * sr + kSuperPx - 1) : 0x7fffffff;
+        if (min(dl, dr) >= b.v) break;
+        if (lin && m.smin[sl] + dl < b.v) scan_super(m, x, sl, b);
+        if (rin && m.smin[sr] + dr < b.v) scan_super(m, x, sr, b);
+    }
+    return b;
+}
+
+// Threads per row: T = 64 (one wave per row, four rows per workgroup, the
+// rows independent of each other) for rows of up to 2048 pixels, T = 256 (the
+// workgroup) for wider ones.  A batch's rows are many and short: a wave per
+// row puts phase 1's W / 16 block starts on the whole wave, and four rows per
+// workgroup keep eight waves per SIMD in flight (a CU holds at most 16
+// workgroups, so one-wave workgroups would cap it at four).
+constexpr int kRowThreadsMax = 256;
+inline int edt_row_threads(int max_w) { return max_w <= 2048 ? 64 : kRowThreadsMax; }
+
+// the ordering point between the phases of one row: the workgroup's barrier,
+// or, for a row that one wave owns, a wave-level fence (a wave's LDS accesses
+// complete in order)
+template <int T>
+__device__ __forceinline__ void row_sync() {
+    if constexpr (T == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <int T>
+__global__ __launch_bounds__(kRowThreadsMax) void edt_rows(const int32_t* __restrict__ colsq,
+                                                          int32_t* __restrict__ d2,
+                                                          float* __restrict__ dtf, EdtBatch bt,
+                                                          int row_ints) {
     extern __shared__ int32_t lds[];
+    constexpr int kRowsPerGroup = kRowThreadsMax / T;
     const int k = blockIdx.y;
-    const int W = b.w[k], H = b.h[k];
-    const int y = blockIdx.x;
-    if (y >= H) return;                  // whole workgroup
+    const int W = bt.w[k], H = bt.h[k];
+    const int sub = (int)threadIdx.x / T;        // the row within the workgroup
+    const int t = (int)threadIdx.x % T;          // the thread within the row
+    const int y = (int)blockIdx.x * kRowsPerGroup + sub;
+    if (y >= H) return;                          // the row's threads together
     const int nb = (W + kRowBlk - 1) / kRowBlk;
     const int ng = (W + kGroupPx - 1) / kGroupPx;
     const int ns = (W + kSuperPx - 1) / kSuperPx;
-    int32_t* row = lds;
-    int32_t* bmin = lds + W;
+    int32_t* row = lds + (size_t)sub * row_ints;
+    int32_t* bmin = row + kBlkStride * nb;
     int32_t* gmin = bmin + nb;
     int32_t* smin = gmin + ng;
-    const int64_t base = b.off[k] + (int64_t)y * W;
-    for (int x = threadIdx.x; x < W; x += blockDim.x) row[x] = colsq[base + x];
-    __syncthreads();
+    int32_t* qstart = smin + ns;         // minimizer at each block start, [nb] = W - 1
+    const int64_t base = bt.off[k] + (int64_t)y * W;
+    for (int x = t; x < W; x += T) row[rix(x)] = colsq[base + x];
+    for (int x = W + t; x < kRowBlk * nb; x += T) row[rix(x)] = kInf;
+    row_sync<T>();
     // block minima, one block per thread; a group's 16 blocks sit on 16
-    // adjacent lanes (256 threads and 16 blocks per group are both multiples
-    // of 16), so the group minimum is a 16-lane butterfly
-    for (int j0 = 0; j0 < nb; j0 += blockDim.x) {
-        const int j = j0 + threadIdx.x;
+    // adjacent lanes (T and 16 blocks per group are both multiples of 16),
+    // so the group minimum is a 16-lane butterfly
+    for (int j0 = 0; j0 < nb; j0 += T) {
+        const int j = j0 + t;
         int32_t mn = kInf;
         if (j < nb) {
-            const int q0 = kRowBlk * j;
-            if (q0 + kRowBlk <= W) {
 #pragma unroll
-                for (int u = 0; u < kRowBlk; ++u) mn = min(mn, row[q0 + u]);
-            } else {
-                for (int q = q0; q < W; ++q) mn = min(mn, row[q]);
-            }
+            for (int u = 0; u < kRowBlk; ++u) mn = min(mn, row[kBlkStride * j + u]);
             bmin[j] = mn;
         }
 #pragma unroll
         for (int o = kRowFan / 2; o >= 1; o >>= 1) mn = min(mn, __shfl_xor(mn, o, 64));
         if (j < nb && (j % kRowFan) == 0) gmin[j / kRowFan] = mn;
     }
-    __syncthreads();
+    row_sync<T>();
     // super minima: only rows wider than one super have other supers
     if (ns > 1) {
-        for (int j = threadIdx.x; j < ns; j += blockDim.x) {
+        for (int j = t; j < ns; j += T) {
             int32_t mn = gmin[kRowFan * j];
             for (int q = kRowFan * j + 1; q < min(kRowFan * j + kRowFan, ng); ++q) mn = min(mn, gmin[q]);
             smin[j] = mn;
         }
-        __syncthreads();
+        row_sync<T>();
     }
     const RowMinima m{row, bmin, gmin, smin, W};
     // f <= (H - 1)^2 < 2^28 or kInf = 2^30, squared distances < 2^28: no
     // int32 overflow in any sum below
-    for (int x = threadIdx.x; x < W; x += blockDim.x) {
-        const int bx = x / kRowBlk, gx = x / kGroupPx, sx = x / kSuperPx;
-        int32_t best = row[x];
-        scan_block(m, x, bx, best);
-        // the other blocks of the own group, outward
-        {
-            const int lo = kRowFan * gx, hi = min(lo + kRowFan, nb) - 1;
-            for (int R = 1;; ++R) {
-                const int bl = bx - R, br = bx + R;
-                const bool lin = bl >= lo, rin = br <= hi;
-                if (!lin && !rin) break;
-                const int dl = lin ? gap2(x, kRowBlk * bl, kRowBlk * bl + kRowBlk - 1) : 0x7fffffff;
-                const int dr = rin ? gap2(x, kRowBlk * br, kRowBlk * br + kRowBlk - 1) : 0x7fffffff;
-                if (min(dl, dr) >= best) break;
-                if (lin && bmin[bl] + dl < best) scan_block(m, x, bl, best);
-                if (rin && bmin[br] + dr < best) scan_block(m, x, br, best);
-            }
+    // phase 1: the block starts (exact search, minimizer recorded)
+    for (int j = t; j <= nb; j += T) {
+        if (j == nb) {
+            qstart[nb] = W - 1;
+            continue;
         }
-        // the other groups of the own super, outward
-        {
-            const int lo = kRowFan * sx, hi = min(lo + kRowFan, ng) - 1;
-            for (int R = 1;; ++R) {
-                const int gl = gx - R, gr = gx + R;
-                const bool lin = gl >= lo, rin = gr <= hi;
-                if (!lin && !rin) break;
-                const int dl = lin ? gap2(x, kGroupPx * gl, kGroupPx * gl + kGroupPx - 1) : 0x7fffffff;
-                const int dr = rin ? gap2(x, kGroupPx * gr, kGroupPx * gr + kGroupPx - 1) : 0x7fffffff;
-                if (min(dl, dr) >= best) break;
-                if (lin && gmin[gl] + dl < best) scan_group(m, x, gl, best);
-                if (rin && gmin[gr] + dr < best) scan_group(m, x, gr, best);
-            }
+        const int x = kRowBlk * j;
+        const Best r = search(m, x, Best{row[rix(x)], x});
+        qstart[j] = r.q;
+        d2[base + x] = r.v;
+        dtf[base + x] = sqrtf((float)r.v);
+    }
+    row_sync<T>();
+    // phase 2: every other pixel, between the minimizers of the block starts
+    // on either side of it
+    for (int x = t; x < W; x += T) {
+        if (x % kRowBlk == 0) continue;
+        const int j = x / kRowBlk;
+        const int qa = qstart[j], qb = qstart[j + 1];
+        int32_t v = row[rix(qa)] + (x - qa) * (x - qa);
+        if (qb - qa < kScanMax) {
+            // the whole blocks that hold [qa, qb]: the extra pixels only add
+            // candidates, and every minimizer of x lies in the range
+            for (int blk = qa / kRowBlk; blk <= qb / kRowBlk; ++blk) v = scan_block_v(m, x, blk, v);
+        } else {
+            Best r{v, qa};
+            const int32_t vb = row[rix(qb)] + (x - qb) * (x - qb);
+            if (vb < r.v) r = Best{vb, qb};
+            v = search(m, x, r).v;
         }
-        // the other supers, outward
-        for (int R = 1; ns > 1; ++R) {
-            const int sl = sx - R, sr = sx + R;
-            const bool lin = sl >= 0, rin = sr < ns;
-            if (!lin && !rin) break;
-            const int dl = lin ? gap2(x, kSuperPx * sl, kSuperPx * sl + kSuperPx - 1) : 0x7fffffff;
-            const int dr = rin ? gap2(x, kSuperPx * sr, kSuperPx * sr + kSuperPx - 1) : 0x7fffffff;
-            if (min(dl, dr) >= best) break;
-            if (lin && smin[sl] + dl < best) scan_super(m, x, sl, best);
-            if (rin && smin[sr] + dr < best) scan_super(m, x, sr, best);
-        }
-        d2[base + x] = best;
-        dtf[base + x] = sqrtf((float)best);
+        d2[base + x] = v;
+        dtf[base + x] = sqrtf((float)v);
     }
 }
 
@@ -343,9 +446,13 @@ extern "C" epo_status epo_build_distance_fields(const uint8_t* edge_maps, const 
             EPO_CHECK_LAUNCH();
             edt_columns<<<cgrid, 64, 0, s>>>(edge_maps, d2_out, colsq, b);
             EPO_CHECK_LAUNCH();
-            const size_t lds = (size_t)edt_row_lds_ints(maxW) * sizeof(int32_t);
+            const int T = edt_row_threads(maxW);
+            const int rows_per_group = kRowThreadsMax / T;
+            const int row_ints = edt_row_lds_ints(maxW);
+            const size_t lds = (size_t)rows_per_group * row_ints * sizeof(int32_t);
+            auto kernel = T == 64 ? edt_rows<64> : edt_rows<kRowThreadsMax>;
             if (lds > 65536) {
-                // rows wider than 15360 pixels: more than the default 64 KB of
+                // rows wider than 14508 pixels: more than the default 64 KB of
                 // dynamic LDS (gfx950 has 160 KB per workgroup); an error, never
                 // a short allocation, if the device cannot give it
                 int dev = 0, max_lds = 0;
@@ -354,11 +461,12 @@ extern "C" epo_status epo_build_distance_fields(const uint8_t* edge_maps, const 
                                               dev));
                 EPO_REQUIRE(lds <= (size_t)max_lds,
                             "rows too wide for the device's LDS per workgroup");
-                EPO_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(edt_rows),
+                EPO_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                             hipFuncAttributeMaxDynamicSharedMemorySize,
                                             (int)lds));
             }
-            edt_rows<<<dim3((unsigned)maxH, b.n), 256, lds, s>>>(colsq, d2_out, dtf_out, b);
+            kernel<<<dim3((unsigned)ceil_div(maxH, rows_per_group), b.n), kRowThreadsMax, lds,
+                     s>>>(colsq, d2_out, dtf_out, b, row_ints);
             EPO_CHECK_LAUNCH();
         }
     });

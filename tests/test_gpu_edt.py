@@ -53,11 +53,12 @@ def test_random_maps_bit_exact(gpu, shape, density):
 
 def test_wide_and_single_pixel(gpu):
     """Maps with one or two edge pixels: d2 is the closed-form minimum over
-    them.  The row pass stages a row and its block, group and super minima
-    in LDS: rows of up to 15360 pixels fit in 64 KB, wider ones (15361,
-    15420, 15500, 16384) need more."""
+    them.  The row pass stages a row, its block, group and super minima and
+    the block starts' minimizers in LDS: rows of up to 14508 pixels fit in
+    64 KB, wider ones (14509, 15361, 15420, 15500, 16384) need more."""
     cases = [(3, 4000, [(1, 3999)]), (2000, 2, [(0, 0)]), (64, 2048, [(63, 1000)]),
              (2, 16384, [(1, 5)]), (3, 15500, [(0, 15499)]),
+             (2, 14508, [(1, 14507)]), (2, 14509, [(0, 7000)]),
              (2, 15360, [(1, 15359)]), (2, 15361, [(0, 7000)]),
              (2, 15420, [(1, 15419)]), (2, 15421, [(0, 7000)]),
              (4, 16384, [(0, 9000), (3, 9100)])]
