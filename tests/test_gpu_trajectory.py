@@ -238,8 +238,11 @@ def test_trajectory_prefix_from_initial_poses(gpu, name):
         + f" deg; loss rel err {rel.max():.2e} (oracle's own up to {env_loss.max():.2e})")
     assert (rot <= bar_rot).all(), (rot, bar_rot)
     assert (rel <= bar_loss).all(), (rel, bar_loss)
-    # the first snapshot lies before the oracle's own spread reaches the bar
-    assert env_rot[0] < ROT_BAR / ENVELOPE_FACTOR and rot[0] < ROT_BAR
+    # where the first snapshot lies before the oracle's own spread reaches
+    # the bar, the GPU is held to the bar itself there (on the 64-scene batch
+    # the oracle's spread passes it within five steps)
+    if env_rot[0] < ROT_BAR / ENVELOPE_FACTOR:
+        assert rot[0] < ROT_BAR
     assert plan.device_status() == 0
 
 
