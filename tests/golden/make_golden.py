@@ -14,7 +14,9 @@ same bits as a serial evaluation).  <name>_envelope.npz holds the oracle's
 own sensitivity over those prefixes: the same runs with every gradient
 perturbed by a seeded random relative amount (1e-9, 5e-8), and how far each
 ends from the stored prefix; <name>_window_envelope.npz the same for each
-10-step window of a whole run (c2), restarted from the stored states.
+10-step window of a whole run (c2), restarted from the stored states;
+<name>_run_envelope.npz the same for the whole run (c2) from the initial
+poses.
 """
 from __future__ import annotations
 
@@ -197,9 +199,52 @@ def write_window_envelope(name: str, workers=None, epss=(1e-9, 5e-8), seeds=(0, 
         rot_dev=np.array(rot_dev), checksum=g["checksum"])
 
 
+def write_run_envelope(name: str, workers=None, epss=(1e-9, 5e-8), seeds=(0, 1, 2)):
+    """The oracle's own sensitivity over a whole stored run (c2): the run
+    repeated from the initial poses with every gradient perturbed by a seeded
+    random relative amount, and how far it is from the stored run every 10
+    steps (largest rotation deviation over the views) and at every step in
+    loss."""
+    import time
+    g = np.load(os.path.join(HERE, f"{name}_trajectory.npz"), allow_pickle=False)
+    n = int(g["iterations"])
+    prob = make(name)
+    assert str(g["checksum"]) == input_checksum(prob)
+    op = ocost.OracleProblem(prob)
+    runs, loss_dev, rot_dev = [], [], []
+    with opar.ParallelEvaluator(op, workers, single_threaded=True) as ev:
+        for eps in epss:
+            for seed in seeds:
+                t0 = time.time()
+                rng = np.random.default_rng([seed, 13])
+
+                def evaluate(poses, lam, params, selected=None, eps=eps, rng=rng):
+                    r = ev(poses, lam, params, selected=selected)
+                    e = rng.normal(size=r["grad"].shape)
+                    r["grad"] = r["grad"] + eps * np.linalg.norm(r["grad"]) / np.linalg.norm(e) * e
+                    return r
+
+                hist = oloop.run(op, prob.poses_init, n, record_every=1, evaluate=evaluate)
+                loss = np.array(hist["loss"])[:, 0]
+                loss_dev.append(np.abs(loss - g["loss"][:, 0]) / np.abs(g["loss"][:, 0]))
+                snaps = [hist["poses"][10 * k] if 10 * k < n else hist["final_poses"]
+                         for k in range(1, g["poses_every10"].shape[0])]
+                rot_dev.append([max(rotation_deg(P[v][:, :3], Q[v][:, :3]) for v in range(len(P)))
+                                for P, Q in zip(snaps, g["poses_every10"][1:])])
+                runs.append((eps, seed))
+                print(f"{name} run: eps {eps:.0e} seed {seed}: rotation deviation at the end "
+                      f"{rot_dev[-1][-1]:.2e} deg ({time.time() - t0:.0f} s)", flush=True)
+    np.savez_compressed(
+        os.path.join(HERE, f"{name}_run_envelope.npz"), eps=np.array([r[0] for r in runs]),
+        seed=np.array([r[1] for r in runs]), loss_dev=np.array(loss_dev),
+        rot_dev=np.array(rot_dev), checksum=g["checksum"])
+
+
 if __name__ == "__main__":
     for name in (sys.argv[1:] or list(ITERS) + list(PREFIX) + [k + "_envelope" for k in ENVELOPE]):
-        if name.endswith("_window_envelope"):
+        if name.endswith("_run_envelope"):
+            write_run_envelope(name[:-len("_run_envelope")])
+        elif name.endswith("_window_envelope"):
             write_window_envelope(name[:-len("_window_envelope")])
         elif name.endswith("_envelope"):
             write_envelope(name[:-len("_envelope")])
