@@ -720,13 +720,6 @@ def main():
         log("refine-only run done")
         return
 
-    # ---- fused kernel duration: the mean of `steps` back-to-back launches
-    # between two HIP events on the stream they run on (after warm-up
-    # launches), so no other kernel of the step is inside the interval
-    for _ in range(args.warmup):
-        plan.cost(poses, lam, grad=True)
-    kernel_ms = plan.time_kernel(poses, lam, reps=args.steps)
-
     # ---- captured iteration: schedule -> cost + adjoint -> reductions -> pose step
     m = torch.zeros(prob.n_views, 6, dtype=torch.float64, device=dev)
     v = torch.zeros_like(m)
@@ -759,6 +752,12 @@ def main():
     assert torch.isfinite(loss).all(), "non-finite loss"
     status = plan.device_status()
     assert status == 0, f"device status {status}"
+
+    # ---- fused kernel duration: the mean of `steps` back-to-back launches
+    # between two HIP events on the stream they run on, right after the timed
+    # iterations (the chip's clock has settled), at the poses the iterations
+    # reached; no other kernel of the step is inside the interval
+    kernel_ms = plan.time_kernel(poses, lam, reps=args.steps)
     value = R_expected / (ms_per_step * 1e-3)
     log(f"{ms_per_step:.3f} ms/iter ({wall_ms / args.steps:.3f} wall), kernel {kernel_ms:.3f} ms, "
         f"{value / 1e9:.1f} G residual+grad/s")
