@@ -139,9 +139,9 @@ __global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ ed
 // at every block start X0 = 16 b by the exact search below; phase 2 takes
 // every other pixel's minimum over the q between the minimizers of its own
 // and the next block start (the last block's right end is the row's end):
-// by scanning the whole half-blocks (8 pixels) that hold them when there
-// are at most kScanMax, else by the same search started from the better of
-// the two end values.
+// by scanning the whole 4-pixel chunks that hold them when there are at
+// most kScanMax, else by the same search started from the better of the two
+// end values.
 //
 // The search: a three-level hierarchy of minima in LDS: blocks of 16 pixels,
 // groups of 16 blocks (256 px), supers of 16 groups (4096 px).  A pixel scans
@@ -213,13 +213,15 @@ __device__ __forceinline__ void scan_block(const RowMinima& m, int x, int blk, B
     }
 }
 
-// the value alone over the eight pixels 8 c .. 8 c + 7 (half a block;
-// phase 2 needs no minimizer)
-__device__ __forceinline__ int32_t scan_half_v(const RowMinima& m, int x, int c, int32_t v) {
-    const int32_t* f = m.row + kBlkStride * (c >> 1) + 8 * (c & 1);
-    const int d0 = x - 8 * c;
+// the value alone over the kChunk pixels kChunk c .. kChunk (c + 1) - 1
+// (within one block; phase 2 needs no minimizer)
+constexpr int kChunk = 4;
+__device__ __forceinline__ int32_t scan_chunk_v(const RowMinima& m, int x, int c, int32_t v) {
+    const int q0 = kChunk * c;
+    const int32_t* f = m.row + rix(q0);
+    const int d0 = x - q0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v = min(v, f[u] + (d0 - u) * (d0 - u));
+    for (int u = 0; u < kChunk; ++u) v = min(v, f[u] + (d0 - u) * (d0 - u));
     return v;
 }
 
@@ -396,9 +398,9 @@ __global__ __launch_bounds__(kRowThreadsMax) void edt_rows(const int32_t* __rest
         const int qa = qstart[j], qb = qstart[j + 1];
         int32_t v = row[rix(qa)] + (x - qa) * (x - qa);
         if (qb - qa < kScanMax) {
-            // the whole half-blocks that hold [qa, qb]: the extra pixels only
-            // add candidates, and every minimizer of x lies in the range
-            for (int c = qa / 8; c <= qb / 8; ++c) v = scan_half_v(m, x, c, v);
+            // the whole 4-pixel chunks that hold [qa, qb]: the extra pixels
+            // only add candidates, and every minimizer of x lies in the range
+            for (int c = qa / kChunk; c <= qb / kChunk; ++c) v = scan_chunk_v(m, x, c, v);
         } else {
             Best r{v, qa};
             const int32_t vb = row[rix(qb)] + (x - qb) * (x - qb);
