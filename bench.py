@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -56,20 +57,29 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and whitespace runs (string literals in
+    this code hold no comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
     """Hash of the fused kernel's device code: its header, the per-residual
-    header and the data-layout section of the internal header (host-side
-    changes elsewhere leave it, and so the committed counters, valid)."""
+    header and the data-layout section of the internal header, comments and
+    layout left out (host-side changes elsewhere, and edits of comments,
+    leave it, and so the committed counters, valid)."""
     csrc = os.path.join(ROOT, "paper_2607_00579_amd", "csrc")
     h = hashlib.sha256()
     for f in ("fused_kernel.h", "residual.h"):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
-    with open(os.path.join(csrc, "epo_internal.h"), "rb") as fh:
+        with open(os.path.join(csrc, f)) as fh:
+            h.update(_code_only(fh.read()).encode())
+    with open(os.path.join(csrc, "epo_internal.h")) as fh:
         text = fh.read()
-    a = text.index(b"// ==== data layout read by the fused kernel: begin")
-    b = text.index(b"// ==== data layout read by the fused kernel: end")
-    h.update(text[a:b])
+    a = text.index("// ==== data layout read by the fused kernel: begin")
+    b = text.index("// ==== data layout read by the fused kernel: end")
+    h.update(_code_only(text[a:b]).encode())
     return h.hexdigest()[:16]
 
 

@@ -70,10 +70,10 @@ __device__ __forceinline__ void tile_rows(Acc& a, uint32_t& n, const uint2* __re
                                           int64_t dzn) {
     const int tid = threadIdx.x;
     uint2 r[U];
-    // rows past the tile's end read the records that follow it (the record
+    // lanes past the tile's end read the records that follow it (the record
     // array carries kRecordPad zero records past its end, more than the at
-    // most kBlock - 1 rows a tile's last row overshoots) and are masked, so
-    // the loads issue back to back without a branch; the row base is
+    // most kBlock - 1 records a tile's last row overshoots) and are masked,
+    // so the loads issue back to back without a branch; the row base is
     // wave-uniform and each lane adds its own fixed byte offset
     const char* rowb = reinterpret_cast<const char*>(rec) + (size_t)k0 * kBlock * 8;
 #pragma unroll

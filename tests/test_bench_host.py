@@ -105,9 +105,9 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_kernel_hash_covers_only_the_fused_kernels_device_code(tmp_path, monkeypatch):
-    """Host-side edits (the launch code, the plan structure) keep the committed
-    counters valid; edits of the kernel's device code or of the data layout it
-    reads invalidate them."""
+    """Host-side edits (the launch code, the plan structure) and comment edits
+    keep the committed counters valid; edits of the kernel's device code or of
+    the data layout it reads invalidate them."""
     import shutil
     src = os.path.join(ROOT, "paper_2607_00579_amd", "csrc")
     dst = tmp_path / "paper_2607_00579_amd" / "csrc"
@@ -121,13 +121,16 @@ def test_kernel_hash_covers_only_the_fused_kernels_device_code(tmp_path, monkeyp
         assert old in text
         p.write_text(text.replace(old, new, 1))
 
-    edit("edge_cost.hip", "namespace epo {", "namespace epo {\n// host-side note")
-    edit("epo_internal.h", "struct Plan {", "// plan note\nstruct Plan {")
-    assert bench.kernel_source_hash() == h0
+    edit("edge_cost.hip", "namespace epo {", "namespace epo {\nconstexpr int kHostOnly = 1;")
+    edit("epo_internal.h", "struct Plan {", "struct PlanNote {};\nstruct Plan {")
+    # comments and layout inside the hashed files do not count either
     edit("epo_internal.h", "struct Tile {", "// layout note\nstruct Tile {")
+    edit("fused_kernel.h", "namespace fused {", "namespace fused {\n/* kernel\n   note */  ")
+    assert bench.kernel_source_hash() == h0
+    edit("epo_internal.h", "struct Tile {", "struct TileNote {};\nstruct Tile {")
     h1 = bench.kernel_source_hash()
     assert h1 != h0
-    edit("fused_kernel.h", "namespace fused {", "namespace fused {\n// kernel note")
+    edit("fused_kernel.h", "namespace fused {", "namespace fused {\nconstexpr int kNote = 1;")
     assert bench.kernel_source_hash() not in (h0, h1)
 
 
