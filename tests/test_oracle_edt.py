@@ -86,3 +86,27 @@ def test_lower_envelope_1d_bruteforce():
         for q in range(n):
             want = min((fp + (q - p) ** 2 for p, fp in fin), default=None)
             assert got[q] == want
+
+
+def test_row_minimizers_are_monotone():
+    """The property the GPU row pass rests on (brute force, no oracle code):
+    for g(x) = min over q of f(q) + (x - q)^2 and X0 < x < X1, some minimizer
+    of x lies between any minimizer of X0 and any minimizer of X1, so the
+    minimum over that range equals g(x).  Random rows with ties, empty
+    stretches (a large f) and single small values."""
+    rng = np.random.default_rng(5)
+    big = 1 << 30
+    for trial in range(300):
+        W = int(rng.integers(2, 80))
+        f = rng.integers(0, 40, W) ** 2
+        f[rng.random(W) < rng.random()] = big
+        x = np.arange(W)
+        cost = f[None, :] + (x[:, None] - x[None, :]) ** 2       # [x, q]
+        g = cost.min(axis=1)
+        for _ in range(10):
+            X0, X1 = sorted(rng.choice(W, 2, replace=False))
+            for qa in np.flatnonzero(cost[X0] == g[X0]):
+                for qb in np.flatnonzero(cost[X1] == g[X1]):
+                    assert qa <= qb
+                    for xx in range(X0 + 1, X1):
+                        assert cost[xx, qa:qb + 1].min() == g[xx], (trial, X0, X1, xx)
