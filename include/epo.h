@@ -118,7 +118,8 @@ typedef struct epo_plan_s* epo_plan;
 /* ---------------------------------------------------------------------------
  * 1. build_distance_fields
  * Exact squared Euclidean distance transform of binary edge maps (the DTF of
- * Sec. 3 "Method", computed with the Felzenszwalb-Huttenlocher transform;
+ * Sec. 3 "Method", computed in the two separable passes of the
+ * Felzenszwalb-Huttenlocher transform;
  * supplementary Sec. A1.2 "Construction kernels"):
  *   d2(x, y) = min over pixels (x', y') with edge(y', x') != 0 of
  *              (x - x')^2 + (y - y')^2,

@@ -3,8 +3,9 @@
 // field of the paper's Sec. 3 and supplementary Sec. A1.2 "Construction
 // kernels".
 //
-//   column pass  f(x, y) = squared distance to the nearest edge pixel of
-//                column x (EPO_D2_EMPTY if the column has none).  One thread
+//   column pass  g(x, y) = distance to the nearest edge pixel of column x,
+//                f = g^2 (EPO_D2_EMPTY if the column has none), stored as
+//                uint16 at the start of row y's DTF slots.  One thread
 //                per (column, 64-row segment), in two kernels: the first
 //                records each segment's first and last edge row (in d2, not
 //                yet written); the second takes the nearest edge above and
@@ -36,6 +37,7 @@ namespace {
 constexpr int kEdtBatch = 240;
 constexpr int32_t kInf = EPO_D2_EMPTY;
 constexpr int kSeg = 64;                 // rows per column-pass thread
+constexpr uint16_t kNoEdge = 0xFFFF;     // column distance of a column without edge pixels
 
 struct EdtBatch {
     int32_t n;
@@ -70,10 +72,12 @@ __global__ __launch_bounds__(64) void edt_segments(const uint8_t* __restrict__ e
 
 // The nearest edge above and below a segment comes from the other segments'
 // summaries (at most H/64 coalesced reads, however far the edge is), then
-// the segment is swept down and up.
+// the segment is swept down and up.  The column
+// distances go out as uint16 at the start of each row's own DTF slots,
+// where the row pass reads them before it writes that row's DTF.
 __global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ edge,
                                                   const int32_t* __restrict__ seg,
-                                                  int32_t* __restrict__ colsq, EdtBatch b) {
+                                                  float* __restrict__ dtf, EdtBatch b) {
     const int k = blockIdx.z;
     const int W = b.w[k], H = b.h[k];
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -83,7 +87,6 @@ __global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ ed
     const int n_seg = (H + kSeg - 1) / kSeg;
     const uint8_t* e = edge + b.off[k] + x;
     const int32_t* sm = seg + b.off[k] + x;
-    int32_t* out = colsq + b.off[k] + x;
     int last = -1;                       // row of the nearest edge at or above
     for (int q = s0 - 1; q >= 0; --q) {
         const int32_t v = sm[(int64_t)q * kSeg * W];
@@ -122,14 +125,15 @@ __global__ __launch_bounds__(64) void edt_columns(const uint8_t* __restrict__ ed
             if ((emask >> i) & 1ull) next = y;
             int best = up[i];
             if (next >= 0 && (best < 0 || next - y < best)) best = next - y;
-            out[(int64_t)y * W] = best >= 0 ? best * best : kInf;
+            reinterpret_cast<uint16_t*>(dtf + b.off[k] + (int64_t)y * W)[x] =
+                best >= 0 ? (uint16_t)best : kNoEdge;
         }
     }
 }
 
-// One workgroup per row.  The row's column-pass values live in dtf (the
-// call's scratch); the workgroup reads all of them into LDS before any of its
-// threads writes the row's DTF, and no other workgroup touches the row.
+// One workgroup per row.  The row's column distances live at the start of its
+// DTF slots; the row's threads read all of them into LDS (as f = g^2) before
+// any of them writes the row's DTF, and no other row touches them.
 //
 // Minimizers are monotone: with p_q(x) = f(q) + (x - q)^2 and q < q',
 // p_q(x) - p_q'(x) = f(q) - f(q') + (q' - q)(2x - q - q') grows with x, so
@@ -325,8 +329,7 @@ __device__ __forceinline__ void row_sync() {
 }
 
 template <int T>
-__global__ __launch_bounds__(kRowThreadsMax) void edt_rows(const int32_t* __restrict__ colsq,
-                                                          int32_t* __restrict__ d2,
+__global__ __launch_bounds__(kRowThreadsMax) void edt_rows(int32_t* __restrict__ d2,
                                                           float* __restrict__ dtf, EdtBatch bt,
                                                           int row_ints) {
     extern __shared__ int32_t lds[];
@@ -346,7 +349,11 @@ __global__ __launch_bounds__(kRowThreadsMax) void edt_rows(const int32_t* __rest
     int32_t* smin = gmin + ng;
     int32_t* qstart = smin + ns;         // minimizer at each block start, [nb] = W - 1
     const int64_t base = bt.off[k] + (int64_t)y * W;
-    for (int x = t; x < W; x += T) row[rix(x)] = colsq[base + x];
+    const uint16_t* grow = reinterpret_cast<const uint16_t*>(dtf + base);
+    for (int x = t; x < W; x += T) {
+        const int32_t g = grow[x];
+        row[rix(x)] = g == kNoEdge ? kInf : g * g;
+    }
     for (int x = W + t; x < kRowBlk * nb; x += T) row[rix(x)] = kInf;
     row_sync<T>();
     // block minima, one block per thread; a group's 16 blocks sit on 16
@@ -432,7 +439,6 @@ extern "C" epo_status epo_build_distance_fields(const uint8_t* edge_maps, const 
             EPO_REQUIRE(view_offset[v] >= 0, "view " + std::to_string(v) + ": negative offset");
         }
         hipStream_t s = as_stream(stream);
-        int32_t* colsq = reinterpret_cast<int32_t*>(dtf_out);   // column-pass scratch
         for (int32_t a = 0; a < n_views; a += kEdtBatch) {
             EdtBatch b{};
             b.n = std::min(kEdtBatch, n_views - a);
@@ -447,7 +453,7 @@ extern "C" epo_status epo_build_distance_fields(const uint8_t* edge_maps, const 
             const dim3 cgrid((unsigned)ceil_div(maxW, 64), (unsigned)ceil_div(maxH, kSeg), b.n);
             edt_segments<<<cgrid, 64, 0, s>>>(edge_maps, d2_out, b);
             EPO_CHECK_LAUNCH();
-            edt_columns<<<cgrid, 64, 0, s>>>(edge_maps, d2_out, colsq, b);
+            edt_columns<<<cgrid, 64, 0, s>>>(edge_maps, d2_out, dtf_out, b);
             EPO_CHECK_LAUNCH();
             const int T = edt_row_threads(maxW);
             const int rows_per_group = kRowThreadsMax / T;
@@ -469,7 +475,7 @@ extern "C" epo_status epo_build_distance_fields(const uint8_t* edge_maps, const 
                                             (int)lds));
             }
             kernel<<<dim3((unsigned)ceil_div(maxH, rows_per_group), b.n), kRowThreadsMax, lds,
-                     s>>>(colsq, d2_out, dtf_out, b, row_ints);
+                     s>>>(d2_out, dtf_out, b, row_ints);
             EPO_CHECK_LAUNCH();
         }
     });
