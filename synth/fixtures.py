@@ -108,3 +108,48 @@ def camera_inside(seed: int = 5):
     return problem_from_maps(p.width[idx], p.height[idx], p.K[idx],
                              [p.edge_map(v) for v in idx], [p.depth_map(v) for v in idx], poses,
                              [[0, 2], [1, 2], [2, 0], [2, 1], [0, 1]], name="camera_inside")
+
+
+# target edge grid of `max_side_pair`: pixels (GRID_X0 + GRID_PITCH a, GRID_Y0 + GRID_PITCH b)
+GRID_PITCH, GRID_X0, GRID_Y0 = 8, 3, 5
+
+
+def max_side_pair(seed: int = 3, n_src: int = 30000):
+    """Two 16384 x 16384 views, the largest side a plan takes.  View 0 holds
+    n_src random edge pixels (a third of them in its last 64 columns or rows,
+    some on the very last ones) at depths in [15, 30]; view 1 holds a regular
+    grid of edge pixels, pitch GRID_PITCH from (GRID_X0, GRID_Y0), at depth 20.
+    Same intrinsics (f = 8000, principal point at the image centre); view 1 is
+    rotated by 2e-4 rad about a random axis and translated by
+    (0.013, -0.007, 0.004), so source points land a few pixels from where they
+    started, at non-integer positions.  Pair 0 -> 1 only."""
+    S = 16384
+    f = 8000.0
+    K = [f, f, (S - 1) / 2.0, (S - 1) / 2.0]
+    rng = np.random.default_rng(seed)
+    us = rng.integers(0, S, n_src)
+    vs = rng.integers(0, S, n_src)
+    k = n_src // 6
+    us[:k] = rng.integers(S - 64, S, k)
+    vs[k:2 * k] = rng.integers(S - 64, S, k)
+    us[2 * k:2 * k + 100] = S - 1
+    vs[2 * k + 100:2 * k + 200] = S - 1
+    lin0 = np.unique(vs.astype(np.int64) * S + us)
+    z0 = rng.uniform(15.0, 30.0, lin0.size).astype(np.float32)
+    gx = np.arange(GRID_X0, S, GRID_PITCH, dtype=np.int64)
+    gy = np.arange(GRID_Y0, S, GRID_PITCH, dtype=np.int64)
+    lin1 = (gy[:, None] * S + gx[None, :]).reshape(-1)
+    z1 = np.full(lin1.size, 20.0, np.float32)
+    axis = rng.normal(size=3)
+    axis /= np.linalg.norm(axis)
+    a = 2e-4
+    Kx = np.array([[0, -axis[2], axis[1]], [axis[2], 0, -axis[0]], [-axis[1], axis[0], 0]])
+    R = np.eye(3) + np.sin(a) * Kx + (1 - np.cos(a)) * (Kx @ Kx)
+    P0 = np.hstack([np.eye(3), np.zeros((3, 1))])
+    P1 = np.hstack([R, np.array([[0.013], [-0.007], [0.004]])])
+    poses = np.stack([P0, P1])
+    sc = Scene(width=np.array([S, S], np.int32), height=np.array([S, S], np.int32),
+               K=np.array([K, K], np.float32), edge_idx=[lin0, lin1], edge_z=[z0, z1],
+               poses_gt=poses, poses_init=poses, pairs=np.array([[0, 1]], np.int32),
+               meta=dict(config="max_side_pair"))
+    return pack([sc], "max_side_pair")

@@ -74,3 +74,23 @@ def gather_depth(r_depth, views, idx, n):
         if v in r_depth:
             out[sel] = r_depth[v][idx[sel]]
     return out
+
+
+class GridDTF:
+    """The exact distance transform of a view whose edge pixels form the grid
+    (x0 + p a, y0 + p b) inside S x S, read only where the oracle reads it:
+    the nearest grid pixel has the nearest grid column and the nearest grid
+    row, so d^2 = dx^2 + dy^2 (closed form, integers)."""
+
+    def __init__(self, S, pitch, x0, y0):
+        self.S, self.p, self.x0, self.y0 = S, pitch, x0, y0
+
+    def _axis(self, c, c0):
+        last = c0 + self.p * ((self.S - 1 - c0) // self.p)
+        k = np.clip(np.rint((c - c0) / self.p), 0, (last - c0) // self.p).astype(np.int64)
+        return np.abs(c - (c0 + self.p * k))
+
+    def __getitem__(self, idx):
+        y, x = (np.asarray(a, np.int64) for a in idx)
+        dx, dy = self._axis(x, self.x0), self._axis(y, self.y0)
+        return np.sqrt((dx * dx + dy * dy).astype(np.float64))

@@ -232,3 +232,41 @@ def test_full_size_joint_phase_whole_scenes_c4(gpu):
         check_depth(g["grad_alpha"][rec], np.concatenate(z0) * want_beta, f"c4 scene {s} dL/dalpha")
     # the other scenes' outputs are finite
     assert np.isfinite(g["loss"]).all() and np.isfinite(g["grad_beta"]).all()
+
+
+def test_max_side_views(gpu):
+    """Two 16384 x 16384 views, the largest side a plan takes: the records'
+    uint16 coordinates up to 16383, texel offsets up to 2^30 bytes into a view
+    (format 2; format 1 the same in float32 words) and 16-byte texels of a
+    4 GiB texture per view (format 3), source pixels on the last rows and
+    columns, projections leaving the image there.  Pair 0 -> 1 in every
+    texture format against the oracle, whose distance field of the target is
+    the grid's closed form at the taps it reads (the GPU's own transform of
+    the target goes into the textures)."""
+    from oracle import cost as ocost
+    from paper_2607_00579_amd.api import EdgePlan
+    from synth import fixtures
+    from tests.gpu_helpers import GridDTF
+    prob = fixtures.max_side_pair()
+    S = int(prob.width[0])
+    say(f"max side: {S} x {S}, {int(prob.edge_counts()[0])} source edge pixels")
+    op = ocost.OracleProblem(prob, d2={0: np.zeros((1, 1), np.int64)}, views=[0])
+    op.D[1] = GridDTF(S, fixtures.GRID_PITCH, fixtures.GRID_X0, fixtures.GRID_Y0)
+    r = op.direction(0, prob.poses_init, 10.0, ocost.CostParams())
+    assert r["n"] > 0.8 * r["n_src"] and r["n"] < r["n_src"]
+    plan = EdgePlan.from_problem(prob)
+    poses = torch.from_numpy(prob.poses_init.copy()).cuda()
+    L = r["S"] / r["n"]
+    Gn = np.linalg.norm(r["G_tgt"])
+    assert Gn > 0
+    for fmt in (1, 2, 3):
+        plan.set_options(texture_format=fmt, points_per_thread=16, tile_order=1, persistent=2)
+        o = plan.cost(poses, 10.0, grad=True, pairs=True)
+        g = {k: v.cpu().numpy() for k, v in o.items()}
+        eL = abs(g["pair_cost"][0] - L) / abs(L)
+        eG = np.linalg.norm(g["pair_grad"][0] - r["G_tgt"]) / Gn
+        say(f"  format {fmt}: n {int(g['pair_valid'][0])} (oracle {r['n']}), L_d rel err "
+            f"{eL:.2e}, G_d rel err {eG:.2e}")
+        assert int(g["pair_valid"][0]) == r["n"]
+        assert eL < 1e-5 and eG < 1e-4
+    assert plan.device_status() == 0

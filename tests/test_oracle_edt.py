@@ -110,3 +110,17 @@ def test_row_minimizers_are_monotone():
                     assert qa <= qb
                     for xx in range(X0 + 1, X1):
                         assert cost[xx, qa:qb + 1].min() == g[xx], (trial, X0, X1, xx)
+
+
+@pytest.mark.parametrize("S,pitch,x0,y0", [(64, 8, 3, 5), (61, 8, 3, 5), (40, 6, 0, 5), (33, 4, 3, 1)])
+def test_grid_closed_form_matches_oracle_edt(S, pitch, x0, y0):
+    """The closed-form distance field that the maximum-size GPU test hands the
+    oracle (edge pixels on a regular grid: the nearest grid column and row)
+    equals the square root of the oracle's exact transform of the same map,
+    borders and sides that end between grid lines included."""
+    from tests.gpu_helpers import GridDTF
+    e = np.zeros((S, S), np.uint8)
+    e[y0::pitch, x0::pitch] = 1
+    yy, xx = np.mgrid[0:S, 0:S]
+    got = GridDTF(S, pitch, x0, y0)[yy, xx]
+    assert np.array_equal(got, np.sqrt(edt.edt_separable(e).astype(np.float64)))
