@@ -253,10 +253,18 @@ __device__ __forceinline__ Residual eval_residual(const uint2 rec, bool active,
 }
 
 // dH/dZ of the source pixel's depth: X' = Z m + t, so dH/dZ = (dH/dX') . m
-// (one expression shared by the kernel that stores it and the one that
-// recomputes it, so both give the same float32 value)
+// with dH/dX' = (A_u, A_v, w) / z.  Since w = -(A_u x_n + A_v y_n), the
+// vector (A_u, A_v, w) is orthogonal to X', and its dot with m = (X' - t) / Z
+// is small next to its terms when the baseline t is small next to Z m: in
+// float32 the roundings of A_u, A_v and w would be amplified by about
+// |Z m| / |t|.  So w and the dot are formed in float64 from the float64
+// coordinates (the cancellation then leaves float64 rounding) and the result
+// is rounded to float32 once.  One expression shared by the kernel that
+// stores it and the one that recomputes it, so both give the same value.
 __device__ __forceinline__ float depth_derivative(const Residual& r) {
-    return r.rz * fmaf(r.Au, (float)r.mx, fmaf(r.Av, (float)r.my, r.w * (float)r.mz));
+    const double Au = (double)r.Au, Av = (double)r.Av;
+    const double w = -fma(Au, r.xd, Av * r.yd);
+    return (float)(r.rd * fma(Au, r.mx, fma(Av, r.my, w * r.mz)));
 }
 
 }  // namespace epo

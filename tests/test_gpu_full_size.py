@@ -242,7 +242,8 @@ def test_max_side_views(gpu):
     columns, projections leaving the image there.  Pair 0 -> 1 in every
     texture format against the oracle, whose distance field of the target is
     the grid's closed form at the taps it reads (the GPU's own transform of
-    the target goes into the textures)."""
+    the target goes into the textures); then the refinement variant's loss,
+    pose, focal and per-record depth gradients against the oracle's."""
     from oracle import cost as ocost
     from paper_2607_00579_amd.api import EdgePlan
     from synth import fixtures
@@ -269,4 +270,24 @@ def test_max_side_views(gpu):
             f"{eL:.2e}, G_d rel err {eG:.2e}")
         assert int(g["pair_valid"][0]) == r["n"]
         assert eL < 1e-5 and eG < 1e-4
+    # the refinement variant (focal sums, per-record depth derivatives) at the
+    # identity refinement, with the autotuner's format for the batch
+    from tests.gpu_helpers import gather_depth, oracle_index
+    plan.set_options(texture_format=2, points_per_thread=16, tile_order=1, persistent=2)
+    got = {k: t.cpu().numpy() for k, t in plan.refine(poses, 10.0).items()}
+    want = op.evaluate(prob.poses_init, 10.0)
+    assert rel_norm_err(got["loss"], want["loss"]) < 1e-4
+    assert rel_norm_err(got["grad"], want["grad"], axis=1) < 1e-4
+    assert rel_norm_err(got["grad_gamma"], want["grad_focal"]) < 1e-4
+    views, idx = oracle_index(prob, plan)
+    want_beta = gather_depth(want["grad_depth"], views, idx, views.size)
+    z0 = np.zeros(views.size)
+    sel = views == 0
+    ys, xs = np.nonzero(prob.edge_map(0))
+    z0[sel] = prob.depth_map(0)[ys, xs].astype(np.float64)[idx[sel]]
+    # the source view's records against the oracle (the target's records are
+    # no pair's source here: exactly zero)
+    check_depth(got["grad_beta"][sel], want_beta[sel], "max side dL/dbeta")
+    check_depth(got["grad_alpha"][sel], z0[sel] * want_beta[sel], "max side dL/dalpha")
+    assert not np.any(got["grad_beta"][~sel]) and not np.any(got["grad_alpha"][~sel])
     assert plan.device_status() == 0
