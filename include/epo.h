@@ -136,7 +136,7 @@ typedef struct epo_plan_s* epo_plan;
  *   dtf_out      float32, same packing: sqrt(d2).  Required: it also serves as
  *                the scratch of the column pass during the call.
  * Errors: EPO_ERR_INVALID_ARG for null pointers, n_views < 0, sides out of
- * range or negative offsets.  No allocation; capture-safe.
+ * range or negative offsets.  No device allocation; capture-safe.
  * ------------------------------------------------------------------------- */
 EPO_API epo_status epo_build_distance_fields(const uint8_t* edge_maps, const int64_t* view_offset,
                                      const int32_t* width, const int32_t* height,

@@ -27,6 +27,10 @@
 
 // Views are processed in batches whose descriptors travel as a kernel
 // argument, so the call needs no device allocation.
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
 #include "epo_internal.h"
 
 namespace epo {
@@ -439,14 +443,23 @@ extern "C" epo_status epo_build_distance_fields(const uint8_t* edge_maps, const 
             EPO_REQUIRE(view_offset[v] >= 0, "view " + std::to_string(v) + ": negative offset");
         }
         hipStream_t s = as_stream(stream);
+        // views batched by size (every view writes at its own offset, so the
+        // order changes nothing else): a launch's grid is sized for its
+        // largest view, and the others' surplus workgroups exit at once
+        std::vector<int32_t> order(n_views);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+            return height[x] != height[y] ? height[x] < height[y] : width[x] < width[y];
+        });
         for (int32_t a = 0; a < n_views; a += kEdtBatch) {
             EdtBatch b{};
             b.n = std::min(kEdtBatch, n_views - a);
             int maxW = 1, maxH = 1;
             for (int k = 0; k < b.n; ++k) {
-                b.w[k] = width[a + k];
-                b.h[k] = height[a + k];
-                b.off[k] = view_offset[a + k];
+                const int32_t v = order[a + k];
+                b.w[k] = width[v];
+                b.h[k] = height[v];
+                b.off[k] = view_offset[v];
                 maxW = std::max(maxW, b.w[k]);
                 maxH = std::max(maxH, b.h[k]);
             }
