@@ -111,6 +111,13 @@ typedef struct epo_plan_options {
     int32_t resort_interval;    /* record_order 2: a captured iteration re-sorts the
                                    chunks c with c mod k == step mod k, k = this many
                                    steps (default 8) */
+    int32_t graph_steps;        /* iterations one captured graph holds, 1 .. 64
+                                   (default 1): the capture entry points record the
+                                   iteration this many times in a row, and each
+                                   epo_iteration_launch then runs that many steps
+                                   (the step counter, schedule and convergence gates
+                                   are read on the device at every one of them), so
+                                   one graph launch serves several steps */
 } epo_plan_options;
 
 typedef struct epo_plan_s* epo_plan;

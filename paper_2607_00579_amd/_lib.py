@@ -44,7 +44,8 @@ class JointState(C.Structure):
 class PlanOptions(C.Structure):
     _fields_ = [("texture_format", C.c_int32), ("points_per_thread", C.c_int32),
                 ("tile_order", C.c_int32), ("persistent", C.c_int32),
-                ("record_order", C.c_int32), ("resort_interval", C.c_int32)]
+                ("record_order", C.c_int32), ("resort_interval", C.c_int32),
+                ("graph_steps", C.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -358,9 +358,11 @@ class EdgePlan:
                           total=2000, beta1=0.9, beta2=0.999, eps=1e-8, convergence=False,
                           early_exit=False):
         """Capture one iteration (schedule -> cost + adjoint -> reductions ->
-        pose step [-> convergence test]); replay with launch_iteration().
-        With the test, early_exit=True leaves a stopped scene's tiles out of
-        the following replays (its loss keeps its last value)."""
+        pose step [-> convergence test]), graph_steps times in a row (plan
+        option, default 1); replay with launch_iteration(), which runs that
+        many steps.  With the test, early_exit=True leaves a stopped scene's
+        tiles out of the following iterations (its loss keeps its last
+        value)."""
         self._graph_refs = (poses, m, v, step, loss, grad, fixed_mask)   # keep buffers alive
         mode = (2 if early_exit else 1) if convergence else 0
         _lib.iteration_capture(self.handle, poses, m, v, step, loss, grad, fixed_mask, lambda0,

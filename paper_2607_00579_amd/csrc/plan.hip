@@ -168,6 +168,8 @@ void upload(DevBuf<T>& b, const std::vector<T>& h, hipStream_t s) {
         EPO_HIP(hipMemcpyAsync(b.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+constexpr int32_t kMaxGraphSteps = 64;   // iterations one captured graph may hold
+
 void validate_options(const epo_plan_options& o) {
     EPO_REQUIRE(o.texture_format >= 1 && o.texture_format <= 3, "texture_format must be 1, 2 or 3");
     EPO_REQUIRE(o.points_per_thread == 1 || o.points_per_thread == 2 || o.points_per_thread == 4 ||
@@ -177,6 +179,8 @@ void validate_options(const epo_plan_options& o) {
     EPO_REQUIRE(o.persistent == 1 || o.persistent == 2, "persistent must be 1 or 2");
     EPO_REQUIRE(o.record_order == 1 || o.record_order == 2, "record_order must be 1 or 2");
     EPO_REQUIRE(o.resort_interval >= 1, "resort_interval must be >= 1");
+    EPO_REQUIRE(o.graph_steps >= 1 && o.graph_steps <= kMaxGraphSteps,
+                "graph_steps must be in [1, 64]");
 }
 
 void fill_default_options(Plan& p, epo_plan_options& o) {
@@ -186,6 +190,7 @@ void fill_default_options(Plan& p, epo_plan_options& o) {
     if (o.persistent == 0) o.persistent = 2;
     if (o.record_order == 0) o.record_order = 1;
     if (o.resort_interval == 0) o.resort_interval = 8;
+    if (o.graph_steps == 0) o.graph_steps = 1;
 }
 
 // the per-pair record copies exist exactly while record_order 2 is in use
@@ -719,7 +724,8 @@ extern "C" epo_status epo_plan_autotune(epo_plan plan, const double* poses, cons
                         for (int pe : pers) {
                             const bool rebuild = pp != p.opt.points_per_thread ||
                                                  o != p.opt.tile_order;
-                            p.opt = epo_plan_options{f, pp, o, pe, ro, interval};
+                            p.opt = epo_plan_options{f, pp, o, pe, ro, interval,
+                                                     p.opt.graph_steps};
                             if (rebuild) build_tiles(p, s);
                             launch_cost(p, poses, lambda, loss.p, nullptr, nullptr, nullptr, grad.p,
                                         nullptr, s);      // warm-up
@@ -761,10 +767,11 @@ extern "C" epo_status epo_plan_autotune(epo_plan plan, const double* poses, cons
 
 namespace {
 
-// Captures the launches `body` makes on a fresh stream as the plan's
-// iteration graph: `step` is the device counter the pair selection reads
-// during capture, with_convergence 2 leaves stopped scenes' tiles out of the
-// fused launch, and no timing events are recorded inside the graph.
+// Captures the launches `body` makes on a fresh stream, graph_steps times in
+// a row, as the plan's iteration graph: `step` is the device counter the pair
+// selection reads during capture, with_convergence 2 leaves stopped scenes'
+// tiles out of the fused launch, and no timing events are recorded inside
+// the graph.
 template <class F>
 void capture_iteration(Plan& p, const int32_t* step, int32_t with_convergence, hipStream_t user,
                        F&& body) {
@@ -784,7 +791,7 @@ void capture_iteration(Plan& p, const int32_t* step, int32_t with_convergence, h
     p.capture_step = step;
     p.gate_phase = with_convergence == 2 ? p.conv_phase.p : nullptr;
     try {
-        body(cs);
+        for (int k = 0; k < p.opt.graph_steps; ++k) body(cs);
     } catch (...) {
         hipGraph_t junk = nullptr;
         (void)hipStreamEndCapture(cs, &junk);

@@ -135,6 +135,8 @@ int main() {
         expect("plan record order 3", a.create(), EPO_ERR_INVALID_ARG, "record_order");
         a.options = epo_plan_options{1, 4, 1, 2, 2, -1};
         expect("plan resort interval", a.create(), EPO_ERR_INVALID_ARG, "resort_interval");
+        a.options = epo_plan_options{1, 4, 1, 2, 1, 8, 65};
+        expect("plan graph steps", a.create(), EPO_ERR_INVALID_ARG, "graph_steps");
     }
     for (const float zmin : {0.0f, -1.0f, 1e-9f, 1e7f, std::nanf("")}) {
         PlanArgs a;

@@ -138,11 +138,15 @@ def test_plan_create_rejects_unsupported_texture(lib):
     with pytest.raises(lib.EpoError) as e:
         lib.plan_create(**_plan_args(options=lib.PlanOptions(1, 4, 1, 2, 2, -1)))
     assert "resort_interval" in str(e.value)
+    for bad in (-1, 65):
+        with pytest.raises(lib.EpoError) as e:
+            lib.plan_create(**_plan_args(options=lib.PlanOptions(1, 4, 1, 2, 1, 8, bad)))
+        assert "graph_steps" in str(e.value)
 
 
 def test_struct_layouts(lib):
     assert C.sizeof(lib.CostParams) == 16
-    assert C.sizeof(lib.PlanOptions) == 24
+    assert C.sizeof(lib.PlanOptions) == 28
 
 
 @pytest.mark.parametrize("z_min", [0.0, -1.0, 1e-9, 1e7, float("nan")])
