@@ -156,26 +156,30 @@ static void launch_pair_setup(Plan& p, const double* poses, const float* lambda,
     EPO_CHECK_LAUNCH();
 }
 
+void launch_tiles(Plan& p, const double* poses, const float* lambda, hipStream_t s,
+                  const RefineOut* ext) {
+    if (p.D == 0) return;
+    launch_pair_setup(p, poses, lambda, s);
+    const bool timed = p.timing;
+    if (timed) EPO_HIP(hipEventRecord(p.ev0, s));
+    // the refinement variant runs for focal gradients, and for depth
+    // gradients when the per-residual derivatives can be stored
+    const bool depth = ext && (ext->grad_alpha || ext->grad_beta);
+    float* dz = depth && p.dz.p ? p.dz.p : nullptr;
+    if (ext && (ext->grad_gamma || dz))
+        launch_cost_variant<true>(p, dz, s);
+    else
+        launch_cost_variant<false>(p, nullptr, s);
+    if (timed) {
+        EPO_HIP(hipEventRecord(p.ev1, s));
+        p.timed_once = true;
+    }
+}
+
 void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss,
                  double* pair_cost, int32_t* pair_valid, double* pair_grad, double* grad,
                  const double* upstream, hipStream_t s, const RefineOut* ext) {
-    if (p.D > 0) {
-        launch_pair_setup(p, poses, lambda, s);
-        const bool timed = p.timing;
-        if (timed) EPO_HIP(hipEventRecord(p.ev0, s));
-        // the refinement variant runs for focal gradients, and for depth
-        // gradients when the per-residual derivatives can be stored
-        const bool depth = ext && (ext->grad_alpha || ext->grad_beta);
-        float* dz = depth && p.dz.p ? p.dz.p : nullptr;
-        if (ext && (ext->grad_gamma || dz))
-            launch_cost_variant<true>(p, dz, s);
-        else
-            launch_cost_variant<false>(p, nullptr, s);
-        if (timed) {
-            EPO_HIP(hipEventRecord(p.ev1, s));
-            p.timed_once = true;
-        }
-    }
+    launch_tiles(p, poses, lambda, s, ext);
     launch_reductions(p, loss, pair_cost, pair_valid, pair_grad, grad, upstream, s,
                       ext ? ext->grad_gamma : nullptr);
     if (ext && (ext->grad_alpha || ext->grad_beta))

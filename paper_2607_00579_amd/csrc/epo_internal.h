@@ -340,6 +340,14 @@ void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss
 void launch_reductions(Plan& p, double* loss, double* pair_cost, int32_t* pair_valid,
                        double* pair_grad, double* grad, const double* upstream,
                        hipStream_t stream, double* grad_gamma = nullptr);
+// pair set-up and the fused kernel alone (launch_cost without the reductions)
+void launch_tiles(Plan& p, const double* poses, const float* lambda, hipStream_t stream,
+                  const RefineOut* ext = nullptr);
+// reductions + pose step + step count in one launch for small plans (false:
+// the plan is too large, nothing launched)
+bool launch_step_epilogue(Plan& p, double* loss, double* grad, double* poses, double* m,
+                          double* v, const uint8_t* fixed, const double* lr, double b1,
+                          double b2, double eps, int32_t* step, hipStream_t stream);
 void launch_depth_grad(Plan& p, const double* upstream, double* grad_alpha, double* grad_beta,
                        bool stored, hipStream_t stream);
 void launch_pose_step(double* poses, double* m, double* v, const double* grad, int32_t n_views,

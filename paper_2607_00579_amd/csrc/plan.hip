@@ -847,9 +847,15 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
                             p.lambda_buf.p, p.lr_buf.p,
                             with_convergence ? p.conv_phase.p : nullptr, cs);
             launch_resort(p, poses, step, p.opt.resort_interval, cs);
-            launch_cost(p, poses, p.lambda_buf.p, loss, nullptr, nullptr, nullptr, g, nullptr, cs);
-            launch_pose_step(poses, adam_m, adam_v, g, p.V, p.scene_of_view_d.p, fixed_mask,
-                             p.lr_buf.p, beta1, beta2, eps, step, cs);
+            // a small plan's reductions, pose step and step count go in one
+            // launch (the same bits as the separate ones)
+            launch_tiles(p, poses, p.lambda_buf.p, cs);
+            if (!launch_step_epilogue(p, loss, g, poses, adam_m, adam_v, fixed_mask, p.lr_buf.p,
+                                      beta1, beta2, eps, step, cs)) {
+                launch_reductions(p, loss, nullptr, nullptr, nullptr, g, nullptr, cs);
+                launch_pose_step(poses, adam_m, adam_v, g, p.V, p.scene_of_view_d.p, fixed_mask,
+                                 p.lr_buf.p, beta1, beta2, eps, step, cs);
+            }
             if (with_convergence) launch_convergence(p, poses, nullptr, cs);
         });
     });

@@ -22,6 +22,7 @@
 #include "epo_internal.h"
 
 namespace epo {
+#include "pose_update.h"
 namespace {
 
 __device__ inline double wave_sum64(double x) {
@@ -30,15 +31,13 @@ __device__ inline double wave_sum64(double x) {
     return x;
 }
 
-__global__ __launch_bounds__(256) void reduce_pairs_kernel(
-    const Partial* __restrict__ partials, const double* __restrict__ ext_partials,
-    const PairStatic* __restrict__ ps, const double* __restrict__ pair_scale, int32_t D,
-    int32_t norm_mode, double* __restrict__ pair_sum, double* __restrict__ pair_w,
-    double* __restrict__ pair_ext, double* __restrict__ pair_cost,
-    int32_t* __restrict__ pair_valid, double* __restrict__ pair_grad,
-    int32_t* __restrict__ status) {
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= D) return;
+// pair d's sums (one thread)
+__device__ inline void reduce_pair(
+    int d, const Partial* __restrict__ partials, const double* __restrict__ ext_partials,
+    const PairStatic* __restrict__ ps, const double* __restrict__ pair_scale, int32_t norm_mode,
+    double* __restrict__ pair_sum, double* __restrict__ pair_w, double* __restrict__ pair_ext,
+    double* __restrict__ pair_cost, int32_t* __restrict__ pair_valid,
+    double* __restrict__ pair_grad, int32_t* __restrict__ status) {
     const PairStatic st = ps[d];
     const double scale = pair_scale[d];
     // a pair skipped by the sub-sampling of this step ran no tiles: all zero
@@ -74,18 +73,29 @@ __global__ __launch_bounds__(256) void reduce_pairs_kernel(
     }
 }
 
-// one wave per pose
-__global__ __launch_bounds__(256) void reduce_views_kernel(
-    const double* __restrict__ pair_sum, const double* __restrict__ pair_w,
+__global__ __launch_bounds__(256) void reduce_pairs_kernel(
+    const Partial* __restrict__ partials, const double* __restrict__ ext_partials,
+    const PairStatic* __restrict__ ps, const double* __restrict__ pair_scale, int32_t D,
+    int32_t norm_mode, double* __restrict__ pair_sum, double* __restrict__ pair_w,
+    double* __restrict__ pair_ext, double* __restrict__ pair_cost,
+    int32_t* __restrict__ pair_valid, double* __restrict__ pair_grad,
+    int32_t* __restrict__ status) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= D) return;
+    reduce_pair(d, partials, ext_partials, ps, pair_scale, norm_mode, pair_sum, pair_w, pair_ext,
+                pair_cost, pair_valid, pair_grad, status);
+}
+
+// pose v's gradient (one wave: lanes stride over the pose's pairs, then a
+// butterfly)
+__device__ inline void reduce_view(
+    int v, int lane, const double* __restrict__ pair_sum, const double* __restrict__ pair_w,
     const double* __restrict__ rel, const int32_t* __restrict__ in_ptr,
     const int32_t* __restrict__ in_idx, const int32_t* __restrict__ out_ptr,
-    const int32_t* __restrict__ out_idx, const int32_t* __restrict__ scene_of_view, int32_t V,
+    const int32_t* __restrict__ out_idx, const int32_t* __restrict__ scene_of_view,
     const double* __restrict__ upstream, double* __restrict__ grad,
     const double* __restrict__ pair_ext, const double* __restrict__ gamma,
     double* __restrict__ grad_gamma) {
-    const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (v >= V) return;                       // whole wave leaves together
     double g[6] = {0, 0, 0, 0, 0, 0};
     double gf = 0.0;
     for (int k = in_ptr[v] + lane; k < in_ptr[v + 1]; k += 64) {
@@ -129,16 +139,30 @@ __global__ __launch_bounds__(256) void reduce_views_kernel(
     }
 }
 
-// one workgroup per scene; a scene the convergence test has stopped (phase
-// 2, when phases are given) evaluated nothing and keeps its last loss
-__global__ __launch_bounds__(256) void reduce_scenes_kernel(
-    const double* __restrict__ pair_sum, const PairStatic* __restrict__ ps,
-    const double* __restrict__ pair_scale, const int32_t* __restrict__ scene_ptr,
-    const int32_t* __restrict__ scene_pairs, int32_t norm_mode, const int32_t* __restrict__ phase,
-    double* __restrict__ loss) {
-    __shared__ double part[4];
-    const int s = blockIdx.x;
-    if (phase && phase[s] == 2) return;
+// one wave per pose
+__global__ __launch_bounds__(256) void reduce_views_kernel(
+    const double* __restrict__ pair_sum, const double* __restrict__ pair_w,
+    const double* __restrict__ rel, const int32_t* __restrict__ in_ptr,
+    const int32_t* __restrict__ in_idx, const int32_t* __restrict__ out_ptr,
+    const int32_t* __restrict__ out_idx, const int32_t* __restrict__ scene_of_view, int32_t V,
+    const double* __restrict__ upstream, double* __restrict__ grad,
+    const double* __restrict__ pair_ext, const double* __restrict__ gamma,
+    double* __restrict__ grad_gamma) {
+    const int v = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (v >= V) return;                       // whole wave leaves together
+    reduce_view(v, lane, pair_sum, pair_w, rel, in_ptr, in_idx, out_ptr, out_idx, scene_of_view,
+                upstream, grad, pair_ext, gamma, grad_gamma);
+}
+
+// scene s's loss (a 256-thread workgroup: threads stride over its pairs, then
+// wave butterflies and an LDS step; `part` holds 4 doubles of LDS)
+__device__ inline void reduce_scene(int s, const double* __restrict__ pair_sum,
+                                    const PairStatic* __restrict__ ps,
+                                    const double* __restrict__ pair_scale,
+                                    const int32_t* __restrict__ scene_ptr,
+                                    const int32_t* __restrict__ scene_pairs, int32_t norm_mode,
+                                    double* __restrict__ loss, double* part) {
     double L = 0.0;
     for (int k = scene_ptr[s] + threadIdx.x; k < scene_ptr[s + 1]; k += blockDim.x) {
         const int d = scene_pairs[k];
@@ -150,6 +174,62 @@ __global__ __launch_bounds__(256) void reduce_scenes_kernel(
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = L;
     __syncthreads();
     if (threadIdx.x == 0) loss[s] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+// one workgroup per scene; a scene the convergence test has stopped (phase
+// 2, when phases are given) evaluated nothing and keeps its last loss
+__global__ __launch_bounds__(256) void reduce_scenes_kernel(
+    const double* __restrict__ pair_sum, const PairStatic* __restrict__ ps,
+    const double* __restrict__ pair_scale, const int32_t* __restrict__ scene_ptr,
+    const int32_t* __restrict__ scene_pairs, int32_t norm_mode, const int32_t* __restrict__ phase,
+    double* __restrict__ loss) {
+    __shared__ double part[4];
+    const int s = blockIdx.x;
+    if (phase && phase[s] == 2) return;
+    reduce_scene(s, pair_sum, ps, pair_scale, scene_ptr, scene_pairs, norm_mode, loss, part);
+}
+
+// The whole step after the fused kernel, for plans whose launches rather than
+// their work set the step time: pair sums, pose gradients, pose update, scene
+// losses and the step count in one 256-thread workgroup, phases separated by
+// barriers (the waves of one workgroup share a CU and its L1, so the sums a
+// phase stores are visible to the next).  Every pair, pose and scene goes
+// through the same device code as in the separate kernels, in the same
+// order: the same bits.
+__global__ __launch_bounds__(256) void step_epilogue_kernel(
+    const Partial* __restrict__ partials, const PairStatic* __restrict__ ps,
+    const double* __restrict__ pair_scale, int32_t D, int32_t norm_mode,
+    double* __restrict__ pair_sum, double* __restrict__ pair_w, const double* __restrict__ rel,
+    const int32_t* __restrict__ in_ptr, const int32_t* __restrict__ in_idx,
+    const int32_t* __restrict__ out_ptr, const int32_t* __restrict__ out_idx,
+    const int32_t* __restrict__ scene_of_view, int32_t V, double* __restrict__ grad,
+    const int32_t* __restrict__ scene_ptr, const int32_t* __restrict__ scene_pairs, int32_t S,
+    const int32_t* __restrict__ phase, double* __restrict__ loss, double* __restrict__ poses,
+    double* __restrict__ m, double* __restrict__ w2, const uint8_t* __restrict__ fixed,
+    const double* __restrict__ lr, double b1, double b2, double eps,
+    int32_t* __restrict__ step, int32_t* __restrict__ status) {
+    __shared__ double part[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int d = tid; d < D; d += blockDim.x)
+        reduce_pair(d, partials, nullptr, ps, pair_scale, norm_mode, pair_sum, pair_w, nullptr,
+                    nullptr, nullptr, nullptr, status);
+    __syncthreads();
+    for (int v = wave; v < V; v += blockDim.x >> 6)
+        reduce_view(v, lane, pair_sum, pair_w, rel, in_ptr, in_idx, out_ptr, out_idx,
+                    scene_of_view, nullptr, grad, nullptr, nullptr, nullptr);
+    __syncthreads();
+    const int st = step[0] + 1;
+    const double bc1 = 1.0 - pow(b1, (double)st);
+    const double bc2 = 1.0 - pow(b2, (double)st);
+    for (int v = tid; v < V; v += blockDim.x)
+        pose_update(v, poses, m, w2, grad, V, scene_of_view, fixed, lr, b1, b2, eps, bc1, bc2);
+    for (int sc = 0; sc < S; ++sc) {
+        if (phase && phase[sc] == 2) continue;        // the same for every thread
+        reduce_scene(sc, pair_sum, ps, pair_scale, scene_ptr, scene_pairs, norm_mode, loss, part);
+        __syncthreads();                              // part is reused by the next scene
+    }
+    __syncthreads();                                  // every thread has read the step
+    if (tid == 0) step[0] = st;
 }
 
 }  // namespace
@@ -178,6 +258,36 @@ void launch_reductions(Plan& p, double* loss, double* pair_cost, int32_t* pair_v
                                                             p.gate_phase, loss);
         EPO_CHECK_LAUNCH();
     }
+}
+
+// bounds of the small-plan epilogue: at most one pair per thread (each thread
+// then sums one pair's tiles, the same dependent chain as in the pair
+// kernel) and 16 poses per wave.  On the 8-view scene (56 pairs) it takes
+// the step from 28 to 24 us; on the 32-view one (992 pairs, four pairs'
+// tile chains per thread in a row) it was 15 us slower than the separate
+// launches
+constexpr int32_t kEpilogueMaxPairs = 256;
+constexpr int32_t kEpilogueMaxViews = 64;
+constexpr int64_t kEpilogueMaxTiles = 16384;
+constexpr int32_t kEpilogueMaxScenes = 64;
+
+// The small-plan epilogue: the reductions, pose step and step count of a
+// captured pose iteration in one launch, when the plan is small enough for
+// one workgroup (the bounds above); returns false (nothing launched)
+// otherwise.
+bool launch_step_epilogue(Plan& p, double* loss, double* grad, double* poses, double* m,
+                          double* v, const uint8_t* fixed, const double* lr, double b1,
+                          double b2, double eps, int32_t* step, hipStream_t s) {
+    if (p.D > kEpilogueMaxPairs || p.V > kEpilogueMaxViews || p.n_tiles > kEpilogueMaxTiles ||
+        p.S > kEpilogueMaxScenes)
+        return false;
+    step_epilogue_kernel<<<1, 256, 0, s>>>(
+        p.partials.p, p.pair_static.p, p.pair_scale.p, p.D, p.params.norm_mode, p.pair_sum.p,
+        p.pair_w.p, p.pair_rel.p, p.view_in_ptr.p, p.view_in_idx.p, p.view_out_ptr.p,
+        p.view_out_idx.p, p.scene_of_view_d.p, p.V, grad, p.scene_ptr.p, p.scene_pairs.p, p.S,
+        p.gate_phase, loss, poses, m, v, fixed, lr, b1, b2, eps, step, p.status.p);
+    EPO_CHECK_LAUNCH();
+    return true;
 }
 
 }  // namespace epo
