@@ -1,8 +1,8 @@
 """GPU: a captured graph holding several iterations (plan option graph_steps)
-runs exactly the iterations of as many one-iteration launches: the poses,
-Adam moments, step counter, last loss and convergence phases come out
-bitwise equal (the pose loop with the convergence test and early exit, on two
-scenes, with and without pair sub-sampling)."""
+runs exactly the iterations of as many one-iteration launches: everything
+the loop carries comes out bitwise equal, for the pose loop (convergence
+test, early exit, with and without pair sub-sampling), the refiner loop and
+the two-phase loop with focal and depth refinement."""
 import numpy as np
 import pytest
 import torch
@@ -62,3 +62,81 @@ def test_graph_steps_out_of_range_rejected(gpu):
     for bad in (-1, 65):
         with pytest.raises(_lib.EpoError):
             plan.set_options(**dict(plan.info()["options"], graph_steps=bad))
+
+
+def _equal(a, b, what):
+    if isinstance(a, dict):
+        assert a.keys() == b.keys(), what
+        for k in a:
+            _equal(a[k], b[k], f"{what}.{k}")
+    else:
+        assert np.array_equal(np.asarray(a), np.asarray(b)), what
+
+
+def run_refiner(prob, graph_steps, launches):
+    from paper_2607_00579_amd.api import EdgePlan, PoseRefiner
+    dev = torch.device("cuda:0")
+    plan = EdgePlan.from_problem(prob)
+    plan.set_options(**dict(plan.info()["options"], graph_steps=graph_steps))
+    ref = PoseRefiner(plan, torch.from_numpy(prob.poses_init.copy()).to(dev), seed=0)
+    step = torch.zeros(1, dtype=torch.int32, device=dev)
+    loss = torch.zeros(prob.n_scenes, dtype=torch.float64, device=dev)
+    grad = torch.zeros(prob.n_views, 6, dtype=torch.float64, device=dev)
+    ref.capture_iteration(step, loss, grad)
+    for _ in range(launches):
+        plan.launch_iteration()
+    torch.cuda.synchronize()
+    state = {k: getattr(ref, k).cpu().numpy().copy()
+             for k in ("params", "m", "v", "grad", "delta", "dm", "dv", "delta_grad", "poses")}
+    return dict(state=state, step=int(step.item()), loss=loss.cpu().numpy(),
+                grad=grad.cpu().numpy())
+
+
+def test_refiner_loop_several_steps_per_graph(gpu):
+    """The refiner loop (MLP forward and backward on matrix cores, AdamW)
+    captured 4 or 12 iterations to a graph equals 12 one-iteration launches
+    bitwise."""
+    from synth.scenes import config_c1, pack
+    prob = pack(list(config_c1().scenes), "c1")
+    ref = run_refiner(prob, 1, 12)
+    assert ref["step"] == 12
+    for g in (4, 12):
+        _equal(ref, run_refiner(prob, g, 12 // g), f"graph_steps {g}")
+
+
+def run_joint(prob, graph_steps, launches, early_exit):
+    from paper_2607_00579_amd.api import EdgePlan
+    dev = torch.device("cuda:0")
+    plan = EdgePlan.from_problem(prob, device=dev)
+    plan.set_options(**dict(plan.info()["options"], graph_steps=graph_steps))
+    poses = torch.from_numpy(prob.poses_init.copy()).to(dev)
+    m = torch.zeros(plan.n_views, 6, dtype=torch.float64, device=dev)
+    v = torch.zeros_like(m)
+    step = torch.zeros(1, dtype=torch.int32, device=dev)
+    loss = torch.zeros(plan.n_scenes, dtype=torch.float64, device=dev)
+    grad = torch.zeros(plan.n_views, 6, dtype=torch.float64, device=dev)
+    state = plan.joint_state()
+    plan.convergence_reset(poses, 2, 1e9, 4, 1e9)
+    plan.capture_joint_iteration(poses, m, v, step, loss, state, grad=grad, convergence=True,
+                                 early_exit=early_exit)
+    for _ in range(launches):
+        plan.launch_iteration()
+    torch.cuda.synchronize()
+    assert plan.device_status() == 0
+    return dict(poses=poses.cpu().numpy(), m=m.cpu().numpy(), v=v.cpu().numpy(),
+                step=int(step.item()), loss=loss.cpu().numpy(), grad=grad.cpu().numpy(),
+                state={k: t.detach().cpu().numpy().copy() for k, t in state.items()},
+                conv={k: np.asarray(x) for k, x in plan.convergence_query().items()})
+
+
+@pytest.mark.parametrize("early_exit", [False, True])
+def test_joint_loop_several_steps_per_graph(gpu, early_exit):
+    """The two-phase loop with focal and depth refinement (the depth step
+    switches on after the third iteration, the scenes stop after the
+    seventh) captured 4 or 8 iterations to a graph equals 8 one-iteration
+    launches bitwise: poses, moments, refinement state, phases."""
+    prob = two_scene_problem()
+    ref = run_joint(prob, 1, 8, early_exit)
+    assert ref["step"] == 8 and ref["conv"]["phase"].tolist() == [2, 2]
+    for g in (4, 8):
+        _equal(ref, run_joint(prob, g, 8 // g, early_exit), f"graph_steps {g}")
