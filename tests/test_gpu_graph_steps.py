@@ -2,7 +2,9 @@
 runs exactly the iterations of as many one-iteration launches: everything
 the loop carries comes out bitwise equal, for the pose loop (convergence
 test, early exit, with and without pair sub-sampling), the refiner loop and
-the two-phase loop with focal and depth refinement."""
+the two-phase loop with focal and depth refinement.  And a small plan's
+captured iteration, whose reductions and pose step run as one workgroup,
+equals eager steps through the separate kernels bitwise."""
 import numpy as np
 import pytest
 import torch
@@ -140,3 +142,62 @@ def test_joint_loop_several_steps_per_graph(gpu, early_exit):
     assert ref["step"] == 8 and ref["conv"]["phase"].tolist() == [2, 2]
     for g in (4, 8):
         _equal(ref, run_joint(prob, g, 8 // g, early_exit), f"graph_steps {g}")
+
+
+def _eager_and_captured(prob, n):
+    """n eager steps (schedule -> cost + adjoint -> separate reductions ->
+    pose step) and n replays of the captured iteration, from the same start."""
+    from paper_2607_00579_amd import _lib
+    from paper_2607_00579_amd.api import EdgePlan
+    dev = torch.device("cuda:0")
+    plan = EdgePlan.from_problem(prob)
+    poses0 = torch.from_numpy(prob.poses_init.copy()).to(dev)
+    out = []
+    for captured in (False, True):
+        P = poses0.clone()
+        m = torch.zeros(prob.n_views, 6, dtype=torch.float64, device=dev)
+        v = torch.zeros_like(m)
+        s = torch.zeros(1, dtype=torch.int32, device=dev)
+        loss = torch.zeros(plan.n_scenes, dtype=torch.float64, device=dev)
+        grad = torch.zeros(prob.n_views, 6, dtype=torch.float64, device=dev)
+        if captured:
+            plan.capture_iteration(P, m, v, s, loss, grad)
+            for _ in range(n):
+                plan.launch_iteration()
+        else:
+            lam = torch.zeros(plan.n_scenes, dtype=torch.float32, device=dev)
+            lr = torch.zeros(plan.n_scenes, dtype=torch.float64, device=dev)
+            st = torch.cuda.current_stream().cuda_stream
+            for _ in range(n):
+                _lib.schedule(s, plan.n_scenes, 10.0, 6.0, 1000, 3e-3, 25, 2000, lam, lr, st)
+                o = plan.cost(P, lam, grad=True)
+                loss.copy_(o["loss"])
+                grad.copy_(o["grad"])
+                plan.pose_step(P, m, v, o["grad"], lr, s)
+        torch.cuda.synchronize()
+        out.append([P.cpu().numpy(), m.cpu().numpy(), v.cpu().numpy(), loss.cpu().numpy(),
+                    grad.cpu().numpy(), int(s.item())])
+    return out
+
+
+@pytest.mark.parametrize("case", ["c2", "c1+one-view"])
+def test_small_plan_epilogue_equals_separate_kernels(gpu, case):
+    """A small plan's captured iteration runs its reductions, pose step and
+    step count as one workgroup; eager calls run the separate kernels: after
+    12 steps the poses, moments, last loss and gradient and the step counter
+    are bitwise equal (the 8-view scene, and a batch with a scene that has no
+    pairs)."""
+    from synth import fixtures
+    from synth.scenes import config_c1, config_c2, pack
+    if case == "c2":
+        prob = pack(list(config_c2().scenes), "c2")
+    else:
+        p = fixtures.odd_size_views()
+        one = fixtures.problem_from_maps([p.width[0]], [p.height[0]], [p.K[0]], [p.edge_map(0)],
+                                         [p.depth_map(0)], [p.poses_init[0]], np.zeros((0, 2)),
+                                         name="one_view")
+        prob = pack(list(config_c1().scenes) + list(one.scenes), "c1+one")
+    eager, captured = _eager_and_captured(prob, 12)
+    assert eager[5] == captured[5] == 12
+    for a, b, what in zip(eager, captured, ("poses", "m", "v", "loss", "grad", "step")):
+        assert np.array_equal(np.asarray(a), np.asarray(b)), what
