@@ -42,17 +42,42 @@ __device__ inline void reduce_pair(
     const double scale = pair_scale[d];
     // a pair skipped by the sub-sampling of this step ran no tiles: all zero
     const int n_tiles = scale != 0.0 ? st.n_tiles : 0;
+    // the tiles' partials four at a time (their loads in flight together),
+    // added one after another in tile order as before
     double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < n_tiles; ++k) {
-        const Partial pt = partials[st.first_tile + k];
+    const Partial* pp = partials + st.first_tile;
+    int k = 0;
+    for (; k + 4 <= n_tiles; k += 4) {
+        Partial pt[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pt[u] = pp[k + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) s[c] += pt[u].v[c];
+    }
+    for (; k < n_tiles; ++k) {
+        const Partial pt = pp[k];
 #pragma unroll
         for (int c = 0; c < 8; ++c) s[c] += pt.v[c];
     }
     if (ext_partials) {
         double ft = 0.0, fs = 0.0;
-        for (int k = 0; k < n_tiles; ++k) {
-            ft += ext_partials[2 * (int64_t)(st.first_tile + k)];
-            fs += ext_partials[2 * (int64_t)(st.first_tile + k) + 1];
+        const double* ep = ext_partials + 2 * (int64_t)st.first_tile;
+        int q = 0;
+        for (; q + 4 <= n_tiles; q += 4) {
+            double e[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) e[u] = ep[2 * q + u];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ft += e[2 * u];
+                fs += e[2 * u + 1];
+            }
+        }
+        for (; q < n_tiles; ++q) {
+            ft += ep[2 * q];
+            fs += ep[2 * q + 1];
         }
         if (!isfinite(ft) || !isfinite(fs)) atomicOr(status, 1);
         pair_ext[2 * d] = ft;
@@ -163,8 +188,27 @@ __device__ inline void reduce_scene(int s, const double* __restrict__ pair_sum,
                                     const int32_t* __restrict__ scene_ptr,
                                     const int32_t* __restrict__ scene_pairs, int32_t norm_mode,
                                     double* __restrict__ loss, double* part) {
+    // the thread's pairs k = first + tid, + blockDim, ... four at a time (the
+    // index and value loads of the four in flight together), added in order
     double L = 0.0;
-    for (int k = scene_ptr[s] + threadIdx.x; k < scene_ptr[s + 1]; k += blockDim.x) {
+    const int k1 = scene_ptr[s + 1], step = blockDim.x;
+    int k = scene_ptr[s] + threadIdx.x;
+    for (; k + 3 * step < k1; k += 4 * step) {
+        int d[4];
+        double den[4], num[4], sc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) d[u] = scene_pairs[k + u * step];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            den[u] = norm_mode == 0 ? pair_sum[8 * d[u] + 1] : (double)ps[d[u]].n_src;
+            num[u] = pair_sum[8 * d[u] + 0];
+            sc[u] = pair_scale[d[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (den[u] > 0) L += sc[u] * (num[u] / den[u]);
+    }
+    for (; k < k1; k += step) {
         const int d = scene_pairs[k];
         const PairStatic st = ps[d];
         const double den = norm_mode == 0 ? pair_sum[8 * d + 1] : (double)st.n_src;
