@@ -247,6 +247,7 @@ struct Plan {
     DevBuf<int32_t> tile_blk;             // per 1024 tiles: selected count, then offset
     DevBuf<int64_t> qbegin_d;             // 9 entries: queue ranges in tile_list
     DevBuf<int32_t> status;               // device status word
+    DevBuf<int32_t> pose_done;            // pose-step workgroups finished (the last advances the step)
     DevBuf<int32_t> scene_view_ptr, scene_view_idx;   // CSR: views of each scene
     // stochastic pair sub-sampling: image pairs (groups of one or two
     // directions) numbered in order of first appearance in the pair list
@@ -350,9 +351,12 @@ bool launch_step_epilogue(Plan& p, double* loss, double* grad, double* poses, do
                           double b2, double eps, int32_t* step, hipStream_t stream);
 void launch_depth_grad(Plan& p, const double* upstream, double* grad_alpha, double* grad_beta,
                        bool stored, hipStream_t stream);
+// with `done` (a device counter at 0), the pose-step kernel's last workgroup
+// advances the step itself and rearms the counter; without, a second launch
 void launch_pose_step(double* poses, double* m, double* v, const double* grad, int32_t n_views,
                       const int32_t* scene_of_view, const uint8_t* fixed, const double* lr,
-                      double b1, double b2, double eps, int32_t* step, hipStream_t stream);
+                      double b1, double b2, double eps, int32_t* step, hipStream_t stream,
+                      int32_t* done = nullptr);
 void launch_schedule(const int32_t* step, int32_t n_scenes, float lambda0, float lambda1,
                      int32_t anneal_steps, double peak_lr, int32_t warmup, int32_t total,
                      float* lambda_out, double* lr_out, const int32_t* phase,

@@ -589,8 +589,10 @@ extern "C" epo_status epo_plan_create(epo_plan* out, int32_t n_views, const int3
         p->pair_ext.alloc(2 * (size_t)std::max(n_pairs, 1));
         p->counters.alloc(16);
         p->status.alloc(1);
+        p->pose_done.alloc(1);
         EPO_HIP(hipMemsetAsync(p->counters.p, 0, 16 * sizeof(int32_t), s));
         EPO_HIP(hipMemsetAsync(p->status.p, 0, sizeof(int32_t), s));
+        EPO_HIP(hipMemsetAsync(p->pose_done.p, 0, sizeof(int32_t), s));
         EPO_HIP(hipMemsetAsync(p->pair_sum.p, 0, p->pair_sum.n * sizeof(double), s));
         EPO_HIP(hipMemsetAsync(p->pair_w.p, 0, p->pair_w.n * sizeof(double), s));
         p->grad_scratch.alloc(6 * (size_t)n_views);
@@ -854,7 +856,7 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
                                       beta1, beta2, eps, step, cs)) {
                 launch_reductions(p, loss, nullptr, nullptr, nullptr, g, nullptr, cs);
                 launch_pose_step(poses, adam_m, adam_v, g, p.V, p.scene_of_view_d.p, fixed_mask,
-                                 p.lr_buf.p, beta1, beta2, eps, step, cs);
+                                 p.lr_buf.p, beta1, beta2, eps, step, cs, p.pose_done.p);
             }
             if (with_convergence) launch_convergence(p, poses, nullptr, cs);
         });
@@ -935,7 +937,7 @@ extern "C" epo_status epo_joint_iteration_capture(epo_plan plan, double* poses, 
                         &out);
             launch_joint_step(p, j, p.lr_buf.p, phase, beta1, beta2, eps, cs);
             launch_pose_step(poses, adam_m, adam_v, g, p.V, p.scene_of_view_d.p, nullptr,
-                             p.lr_buf.p, beta1, beta2, eps, step, cs);
+                             p.lr_buf.p, beta1, beta2, eps, step, cs, p.pose_done.p);
             if (with_convergence) launch_convergence(p, poses, nullptr, cs);
         });
     });

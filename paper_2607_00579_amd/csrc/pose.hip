@@ -16,18 +16,33 @@ namespace epo {
 #include "pose_update.h"
 namespace {
 
-// one thread per view; every thread reads the step counter, which
-// advance_step_kernel increments afterwards
+// one thread per view; every thread reads the step counter, which is
+// advanced after every workgroup has read it: by the last workgroup to
+// finish when `done` is given (a counter at 0, rearmed here), else by
+// advance_step_kernel in a launch of its own
 __global__ __launch_bounds__(64) void pose_step_kernel(
     double* __restrict__ poses, double* __restrict__ m, double* __restrict__ w2,
     const double* __restrict__ grad, int32_t V, const int32_t* __restrict__ scene_of_view,
     const uint8_t* __restrict__ fixed, const double* __restrict__ lr, double b1, double b2,
-    double eps, const int32_t* __restrict__ step) {
+    double eps, int32_t* __restrict__ step, int32_t* __restrict__ done) {
     const int s = step[0] + 1;
     const double bc1 = 1.0 - pow(b1, (double)s);
     const double bc2 = 1.0 - pow(b2, (double)s);
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     pose_update(v, poses, m, w2, grad, V, scene_of_view, fixed, lr, b1, b2, eps, bc1, bc2);
+    if (done) {
+        __shared__ int last;
+        __syncthreads();                      // the workgroup has read the step
+        if (threadIdx.x == 0) {
+            __threadfence();
+            last = atomicAdd(done, 1) == (int)gridDim.x - 1;
+        }
+        __syncthreads();
+        if (last && threadIdx.x == 0) {
+            step[0] = s;
+            done[0] = 0;
+        }
+    }
 }
 
 // the step counter advances after every view has read it (its own launch)
@@ -59,13 +74,15 @@ __global__ __launch_bounds__(256) void schedule_kernel(const int32_t* __restrict
 
 void launch_pose_step(double* poses, double* m, double* v, const double* grad, int32_t n_views,
                       const int32_t* scene_of_view, const uint8_t* fixed, const double* lr,
-                      double b1, double b2, double eps, int32_t* step, hipStream_t s) {
+                      double b1, double b2, double eps, int32_t* step, hipStream_t s,
+                      int32_t* done) {
     // one view per thread over the whole chip (the float64 exponential map is
     // a long dependent chain, so views are spread rather than looped over)
     if (n_views > 0) {
         pose_step_kernel<<<(unsigned)ceil_div(n_views, 64), 64, 0, s>>>(
-            poses, m, v, grad, n_views, scene_of_view, fixed, lr, b1, b2, eps, step);
+            poses, m, v, grad, n_views, scene_of_view, fixed, lr, b1, b2, eps, step, done);
         EPO_CHECK_LAUNCH();
+        if (done) return;
     }
     advance_step_kernel<<<1, 1, 0, s>>>(step);
     EPO_CHECK_LAUNCH();
