@@ -83,6 +83,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def graph_steps_for(steps: int, warmup: int, most: int = 10) -> int:
+    """Iterations per captured graph: the largest number up to `most` that
+    divides both the timed and the warm-up step counts, so that exactly
+    `steps` iterations run between the timing events."""
+    return max(g for g in range(1, most + 1) if steps % g == 0 and warmup % g == 0)
+
+
 def load_counter_records() -> list:
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -737,7 +744,7 @@ def main():
     # graph_steps iterations per graph (the largest divisor of both the timed
     # and the warm-up step counts up to 10), so exactly `steps` iterations run
     # between the timing events
-    graph_steps = max(g for g in range(1, 11) if args.steps % g == 0 and args.warmup % g == 0)
+    graph_steps = graph_steps_for(args.steps, args.warmup)
     plan.set_options(**dict(options, graph_steps=graph_steps))
     options = plan.info()["options"]
     m = torch.zeros(prob.n_views, 6, dtype=torch.float64, device=dev)

@@ -4,6 +4,8 @@ import os
 import subprocess
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
@@ -144,3 +146,13 @@ def test_cpu_baseline_reports_the_host(monkeypatch):
     for k in ("nproc", "affinity", "cpu_model", "numpy"):
         assert r["host"][k], k
     assert "directed pairs" in r["sample"]
+
+
+@pytest.mark.parametrize("steps,warmup,want", [(20, 20, 10), (20, 21, 1), (5, 1, 1), (30, 20, 10),
+                                               (12, 8, 4), (7, 14, 7), (1, 0, 1), (100, 50, 10)])
+def test_graph_steps_divide_timed_and_warmup_steps(steps, warmup, want):
+    """The bench runs steps / g timed and warmup / g warm-up graph launches of
+    g iterations each: g divides both counts, at most 10."""
+    g = bench.graph_steps_for(steps, warmup)
+    assert g == want
+    assert steps % g == 0 and warmup % g == 0 and 1 <= g <= 10
