@@ -46,9 +46,21 @@ __global__ __launch_bounds__(256) void pair_setup_kernel(
     const PairStatic* __restrict__ ps,
     const float* __restrict__ lambda, float lambda_max, PairDesc* __restrict__ desc,
     double* __restrict__ rel, int32_t D, int32_t* __restrict__ counters, int32_t n_counters,
-    int32_t* __restrict__ status) {
+    int32_t* __restrict__ status, ScheduleArgs sched) {
     const int d = blockIdx.x * blockDim.x + threadIdx.x;
     if (d < n_counters) counters[d] = 0;      // work queues of the next cost launch
+    // the schedule of this step, when this launch takes the schedule
+    // kernel's place: lambda for every pair, each scene's lambda and rate
+    // written for the kernels after it
+    float lv = 0.0f;
+    if (sched.step) {
+        double r;
+        schedule_at(sched, sched.step[0], lv, r);
+        if (d < sched.S) {
+            if (sched.lam) sched.lam[d] = lv;
+            if (sched.lr) sched.lr[d] = (sched.phase && sched.phase[d] == 2) ? 0.0 : r;
+        }
+    }
     if (d >= D) return;
     const PairStatic st = ps[d];
     const int i = st.src, j = st.tgt;
@@ -66,7 +78,7 @@ __global__ __launch_bounds__(256) void pair_setup_kernel(
     o.fy = (float)fyj;
     o.wcells = wh[2 * j + 0] - 1;
     o.hcells = wh[2 * j + 1] - 1;
-    const float lam = lambda[st.scene];
+    const float lam = sched.step ? lv : lambda[st.scene];
     if (!(lam >= 0.0f && lam <= lambda_max)) atomicOr(status, 2);
     o.lambda = lam;
     // texture addressing of the format in use: blocked u8 quads (blk_off
@@ -147,19 +159,22 @@ void launch_cost_variant(Plan& p, float* dz, hipStream_t s) {
 
 // this step's pair subset (stochastic sub-sampling, stopped scenes skipped),
 // if enabled, the compacted list of its tiles, and the pair descriptors
-static void launch_pair_setup(Plan& p, const double* poses, const float* lambda, hipStream_t s) {
+static void launch_pair_setup(Plan& p, const double* poses, const float* lambda, hipStream_t s,
+                              const ScheduleArgs* sched) {
     launch_pair_selection(p, p.capture_step ? p.capture_step : p.sample_step, s);
-    pair_setup_kernel<<<(unsigned)ceil_div(std::max(p.D, 16), 256), 256, 0, s>>>(
+    const int threads = std::max({p.D, 16, sched ? sched->S : 0});
+    pair_setup_kernel<<<(unsigned)ceil_div(threads, 256), 256, 0, s>>>(
         poses, p.K_d.p, p.wh_d.p, p.view_offset_d.p,
         p.opt.texture_format == 2 ? p.blk_off_d.p : nullptr, p.pair_static.p, lambda,
-        p.params.lambda_max, p.pair_desc.p, p.pair_rel.p, p.D, p.counters.p, 8, p.status.p);
+        p.params.lambda_max, p.pair_desc.p, p.pair_rel.p, p.D, p.counters.p, 8, p.status.p,
+        sched ? *sched : ScheduleArgs{});
     EPO_CHECK_LAUNCH();
 }
 
 void launch_tiles(Plan& p, const double* poses, const float* lambda, hipStream_t s,
-                  const RefineOut* ext) {
+                  const RefineOut* ext, const ScheduleArgs* sched) {
     if (p.D == 0) return;
-    launch_pair_setup(p, poses, lambda, s);
+    launch_pair_setup(p, poses, lambda, s, sched);
     const bool timed = p.timing;
     if (timed) EPO_HIP(hipEventRecord(p.ev0, s));
     // the refinement variant runs for focal gradients, and for depth
@@ -214,7 +229,7 @@ extern "C" epo_status epo_plan_time_kernel(epo_plan plan, const double* poses,
         hipStream_t s = as_stream(stream);
         *ms = 0.0f;
         if (p.D == 0) return;
-        launch_pair_setup(p, poses, lambda, s);
+        launch_pair_setup(p, poses, lambda, s, nullptr);
         EPO_HIP(hipStreamSynchronize(s));
         // `reps` launches of the kernel captured as one graph (the way a
         // captured iteration launches it), replayed once to warm up and once

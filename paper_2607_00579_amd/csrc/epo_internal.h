@@ -334,6 +334,32 @@ struct RefineOut {
 // sub-sampling, or stopped scenes skipped) instead of every tile
 inline bool compacted_launch(const Plan& p) { return p.sample_budget > 0 || p.gate_phase; }
 
+// The paper's schedules at step s (Sec. 4 "Implementation Details"): the
+// clamp lambda falls linearly from l0 to l1 over `anneal` steps (the same for
+// every scene); the learning rate rises linearly over `warmup` steps, then
+// follows a cosine to 0 at `total`; a stopped scene (phase 2) gets rate 0.
+// One function for the schedule kernel and the pair set-up kernel that takes
+// its place in the captured pose iteration.
+struct ScheduleArgs {
+    const int32_t* step;        // null: no schedule in this launch
+    float l0, l1;
+    int32_t anneal;
+    double peak;
+    int32_t warmup, total;
+    float* lam;                 // per scene (may be null)
+    double* lr;                 // per scene (may be null)
+    const int32_t* phase;       // per scene (may be null)
+    int32_t S;
+};
+__device__ inline void schedule_at(const ScheduleArgs& a, int s, float& lv, double& r) {
+    const double frac = a.anneal > 0 ? (double)min(s, a.anneal) / (double)a.anneal : 1.0;
+    lv = (float)((double)a.l0 - ((double)a.l0 - (double)a.l1) * frac);
+    if (s < a.warmup)
+        r = a.peak * (double)(s + 1) / (double)a.warmup;
+    else
+        r = a.peak * 0.5 * (1.0 + cos(M_PI * (double)(s - a.warmup) / (double)(a.total - a.warmup)));
+}
+
 // launches of the per-iteration pipeline (no allocation, no sync)
 void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss,
                  double* pair_cost, int32_t* pair_valid, double* pair_grad, double* grad,
@@ -341,9 +367,11 @@ void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss
 void launch_reductions(Plan& p, double* loss, double* pair_cost, int32_t* pair_valid,
                        double* pair_grad, double* grad, const double* upstream,
                        hipStream_t stream, double* grad_gamma = nullptr);
-// pair set-up and the fused kernel alone (launch_cost without the reductions)
+// pair set-up and the fused kernel alone (launch_cost without the reductions);
+// with `sched`, the pair set-up also evaluates the schedule (lambda from the
+// step instead of `lambda`, and the per-scene lambda and rate written out)
 void launch_tiles(Plan& p, const double* poses, const float* lambda, hipStream_t stream,
-                  const RefineOut* ext = nullptr);
+                  const RefineOut* ext = nullptr, const ScheduleArgs* sched = nullptr);
 // reductions + pose step + step count in one launch for small plans (false:
 // the plan is too large, nothing launched)
 bool launch_step_epilogue(Plan& p, double* loss, double* grad, double* poses, double* m,

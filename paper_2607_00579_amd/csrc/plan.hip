@@ -845,13 +845,18 @@ extern "C" epo_status epo_iteration_capture(epo_plan plan, double* poses, double
         // starts from; each replay then re-sorts 1 / resort_interval of them
         launch_resort(p, poses, nullptr, 1, as_stream(stream));
         capture_iteration(p, step, with_convergence, as_stream(stream), [&](hipStream_t cs) {
-            launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
-                            p.lambda_buf.p, p.lr_buf.p,
-                            with_convergence ? p.conv_phase.p : nullptr, cs);
+            // the schedule is evaluated by the pair set-up (one launch fewer);
+            // a plan without pairs runs the schedule kernel
+            const ScheduleArgs sched{step, lambda0, lambda1, anneal_steps, peak_lr, warmup,
+                                     total, p.lambda_buf.p, p.lr_buf.p,
+                                     with_convergence ? p.conv_phase.p : nullptr, p.S};
+            if (p.D == 0)
+                launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
+                                p.lambda_buf.p, p.lr_buf.p, sched.phase, cs);
             launch_resort(p, poses, step, p.opt.resort_interval, cs);
             // a small plan's reductions, pose step and step count go in one
             // launch (the same bits as the separate ones)
-            launch_tiles(p, poses, p.lambda_buf.p, cs);
+            launch_tiles(p, poses, p.lambda_buf.p, cs, nullptr, &sched);
             if (!launch_step_epilogue(p, loss, g, poses, adam_m, adam_v, fixed_mask, p.lr_buf.p,
                                       beta1, beta2, eps, step, cs)) {
                 launch_reductions(p, loss, nullptr, nullptr, nullptr, g, nullptr, cs);

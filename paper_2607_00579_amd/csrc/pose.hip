@@ -55,14 +55,10 @@ __global__ __launch_bounds__(256) void schedule_kernel(const int32_t* __restrict
                                                        float* __restrict__ lam,
                                                        double* __restrict__ lr,
                                                        const int32_t* __restrict__ phase) {
-    const int s = step[0];
-    const double frac = anneal > 0 ? (double)min(s, anneal) / (double)anneal : 1.0;
-    const float lv = (float)((double)l0 - ((double)l0 - (double)l1) * frac);
+    const ScheduleArgs a{step, l0, l1, anneal, peak, warmup, total, lam, lr, phase, S};
+    float lv;
     double r;
-    if (s < warmup)
-        r = peak * (double)(s + 1) / (double)warmup;
-    else
-        r = peak * 0.5 * (1.0 + cos(M_PI * (double)(s - warmup) / (double)(total - warmup)));
+    schedule_at(a, step[0], lv, r);
     for (int k = threadIdx.x; k < S; k += blockDim.x) {
         if (lam) lam[k] = lv;
         // a scene whose run has stopped (phase 2) keeps its poses
