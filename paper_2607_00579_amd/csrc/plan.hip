@@ -890,11 +890,16 @@ extern "C" epo_status epo_mlp_iteration_capture(
             // backward (activations of the forward that made them) -> AdamW
             // (advances the step) -> poses of the new parameters ->
             // (pose-change test)
-            launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
-                            p.lambda_buf.p, p.lr_buf.p,
-                            with_convergence ? p.conv_phase.p : nullptr, cs);
+            // the schedule evaluated by the pair set-up, as in the pose loop
+            const ScheduleArgs sched{step, lambda0, lambda1, anneal_steps, peak_lr, warmup,
+                                     total, p.lambda_buf.p, p.lr_buf.p,
+                                     with_convergence ? p.conv_phase.p : nullptr, p.S};
+            if (p.D == 0)
+                launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
+                                p.lambda_buf.p, p.lr_buf.p, sched.phase, cs);
             launch_resort(p, poses, step, p.opt.resort_interval, cs);
-            launch_cost(p, poses, p.lambda_buf.p, loss, nullptr, nullptr, nullptr, g, nullptr, cs);
+            launch_tiles(p, poses, p.lambda_buf.p, cs, nullptr, &sched);
+            launch_reductions(p, loss, nullptr, nullptr, nullptr, g, nullptr, cs);
             launch_mlp_backward(p, params, poses0, poses, g, param_grad, delta_grad, cs);
             launch_adamw(p, params, adam_m, adam_v, param_grad, delta, delta_m, delta_v,
                          delta_grad, p.lr_buf.p, beta1, beta2, eps, wd_mlp, wd_delta, step, cs);
