@@ -193,8 +193,9 @@ void launch_tiles(Plan& p, const double* poses, const float* lambda, hipStream_t
 
 void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss,
                  double* pair_cost, int32_t* pair_valid, double* pair_grad, double* grad,
-                 const double* upstream, hipStream_t s, const RefineOut* ext) {
-    launch_tiles(p, poses, lambda, s, ext);
+                 const double* upstream, hipStream_t s, const RefineOut* ext,
+                 const ScheduleArgs* sched) {
+    launch_tiles(p, poses, lambda, s, ext, sched);
     launch_reductions(p, loss, pair_cost, pair_valid, pair_grad, grad, upstream, s,
                       ext ? ext->grad_gamma : nullptr);
     if (ext && (ext->grad_alpha || ext->grad_beta))

@@ -363,7 +363,8 @@ __device__ inline void schedule_at(const ScheduleArgs& a, int s, float& lv, doub
 // launches of the per-iteration pipeline (no allocation, no sync)
 void launch_cost(Plan& p, const double* poses, const float* lambda, double* loss,
                  double* pair_cost, int32_t* pair_valid, double* pair_grad, double* grad,
-                 const double* upstream, hipStream_t stream, const RefineOut* ext = nullptr);
+                 const double* upstream, hipStream_t stream, const RefineOut* ext = nullptr,
+                 const ScheduleArgs* sched = nullptr);
 void launch_reductions(Plan& p, double* loss, double* pair_cost, int32_t* pair_valid,
                        double* pair_grad, double* grad, const double* upstream,
                        hipStream_t stream, double* grad_gamma = nullptr);

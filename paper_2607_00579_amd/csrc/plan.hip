@@ -941,10 +941,14 @@ extern "C" epo_status epo_joint_iteration_capture(epo_plan plan, double* poses, 
             // refinement -> joint AdamW gated by the phase (installs the new
             // refinement) -> pose step (advances the step) -> (pose-change
             // test, phase switches)
-            launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
-                            p.lambda_buf.p, p.lr_buf.p, phase, cs);
+            // the schedule evaluated by the pair set-up, as in the pose loop
+            const ScheduleArgs sched{step, lambda0, lambda1, anneal_steps, peak_lr, warmup,
+                                     total, p.lambda_buf.p, p.lr_buf.p, phase, p.S};
+            if (p.D == 0)
+                launch_schedule(step, p.S, lambda0, lambda1, anneal_steps, peak_lr, warmup, total,
+                                p.lambda_buf.p, p.lr_buf.p, phase, cs);
             launch_cost(p, poses, p.lambda_buf.p, loss, nullptr, nullptr, nullptr, g, nullptr, cs,
-                        &out);
+                        &out, &sched);
             launch_joint_step(p, j, p.lr_buf.p, phase, beta1, beta2, eps, cs);
             launch_pose_step(poses, adam_m, adam_v, g, p.V, p.scene_of_view_d.p, nullptr,
                              p.lr_buf.p, beta1, beta2, eps, step, cs, p.pose_done.p);
