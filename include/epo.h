@@ -607,7 +607,12 @@ EPO_API epo_status epo_convergence_query(epo_plan plan, int32_t* phase, double* 
  * One whole iteration captured as a HIP graph owned by the plan:
  *   schedule -> fused cost + adjoint -> float64 reductions -> pose_step
  *   [-> convergence update, when with_convergence != 0; call
- *   epo_convergence_reset before the first replay].
+ *   epo_convergence_reset before the first replay],
+ * recorded graph_steps times in a row (plan option, default 1).  The same
+ * arithmetic as the separate calls, with fewer launches: the pair set-up
+ * evaluates the schedule, the pose step advances the step counter, and on
+ * plans of at most 256 pairs and 64 views the reductions, pose step and step
+ * count run as one workgroup (bitwise the same results).
  * The pointers given here are baked into the graph; replays read the current
  * contents of every buffer.  Capturing synchronises `stream` once.
  *   poses, adam_m, adam_v, step   as in epo_pose_step
@@ -627,7 +632,8 @@ EPO_API epo_status epo_convergence_query(epo_plan plan, int32_t* phase, double* 
  *                                 Poses, phases and the other scenes' results
  *                                 are bitwise those of mode 1.  Other values:
  *                                 EPO_ERR_INVALID_ARG.
- * epo_iteration_launch replays it on `stream` (any stream of the device).
+ * epo_iteration_launch replays it on `stream` (any stream of the device):
+ * graph_steps iterations per call.
  * ------------------------------------------------------------------------- */
 EPO_API epo_status epo_iteration_capture(epo_plan plan, double* poses, double* adam_m, double* adam_v,
                                  int32_t* step, double* loss, double* grad,
