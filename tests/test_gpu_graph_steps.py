@@ -180,13 +180,14 @@ def _eager_and_captured(prob, n):
     return out
 
 
-@pytest.mark.parametrize("case", ["c2", "c1+one-view"])
+@pytest.mark.parametrize("case", ["c2", "c1+one-view", "one-view"])
 def test_small_plan_epilogue_equals_separate_kernels(gpu, case):
     """A small plan's captured iteration runs its reductions, pose step and
     step count as one workgroup; eager calls run the separate kernels: after
     12 steps the poses, moments, last loss and gradient and the step counter
-    are bitwise equal (the 8-view scene, and a batch with a scene that has no
-    pairs)."""
+    are bitwise equal (the 8-view scene, a batch with a scene that has no
+    pairs, and a plan with no pair at all: zero loss and gradient, poses
+    unchanged)."""
     from synth import fixtures
     from synth.scenes import config_c1, config_c2, pack
     if case == "c2":
@@ -196,8 +197,14 @@ def test_small_plan_epilogue_equals_separate_kernels(gpu, case):
         one = fixtures.problem_from_maps([p.width[0]], [p.height[0]], [p.K[0]], [p.edge_map(0)],
                                          [p.depth_map(0)], [p.poses_init[0]], np.zeros((0, 2)),
                                          name="one_view")
-        prob = pack(list(config_c1().scenes) + list(one.scenes), "c1+one")
+        if case == "one-view":
+            prob = one          # no pair at all: the schedule runs as its own kernel
+        else:
+            prob = pack(list(config_c1().scenes) + list(one.scenes), "c1+one")
     eager, captured = _eager_and_captured(prob, 12)
     assert eager[5] == captured[5] == 12
+    if case == "one-view":
+        assert not np.any(captured[3]) and not np.any(captured[4])
+        assert np.array_equal(captured[0], prob.poses_init)
     for a, b, what in zip(eager, captured, ("poses", "m", "v", "loss", "grad", "step")):
         assert np.array_equal(np.asarray(a), np.asarray(b)), what
